@@ -1,0 +1,210 @@
+"""Seeded synthetic inputs: node sets, order maps, test fields.
+
+This module holds none of the method's arithmetic; it only produces inputs
+that both the HIP path and the oracle consume.
+
+Node sets follow the paper's noisy Cartesian distribution (Sec. 4.1): a
+lattice of spacing s, every node perturbed by at most eps*s.  Here the
+lattice is cell-centred ((i + 1/2) s) and each coordinate is perturbed by
+U(-eps s, +eps s); nodes are stored in Morton order of their lattice cell
+so that neighbours are close in memory.
+"""
+import math
+
+import numpy as np
+
+# ---------------------------------------------------------------------------
+# node sets
+
+
+def _morton_key(i, j):
+    """Interleave the bits of two non-negative int arrays (i in even bits)."""
+    key = np.zeros(np.broadcast(i, j).shape, dtype=np.uint64)
+    i = i.astype(np.uint64)
+    j = j.astype(np.uint64)
+    for b in range(21):
+        key |= ((i >> np.uint64(b)) & np.uint64(1)) << np.uint64(2 * b)
+        key |= ((j >> np.uint64(b)) & np.uint64(1)) << np.uint64(2 * b + 1)
+    return key
+
+
+def jittered_lattice(nx, ny=None, eps=0.3, seed=0, periodic=False, morton=True):
+    """Cell-centred nx*ny lattice on [0,1]^2 with per-coordinate jitter U(-eps s, eps s).
+
+    Returns (x, y, s) with x, y float64 of length nx*ny.  On a periodic domain
+    coordinates are wrapped into [0, 1)."""
+    ny = nx if ny is None else ny
+    sx, sy = 1.0 / nx, 1.0 / ny
+    rng = np.random.default_rng(seed)
+    jj, ii = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    ii = ii.ravel()
+    jj = jj.ravel()
+    jx = rng.uniform(-eps, eps, ii.size)
+    jy = rng.uniform(-eps, eps, ii.size)
+    x = (ii + 0.5 + jx) * sx
+    y = (jj + 0.5 + jy) * sy
+    if periodic:
+        x = np.mod(x, 1.0)
+        y = np.mod(y, 1.0)
+    if morton:
+        perm = np.argsort(_morton_key(ii, jj), kind="stable")
+        x, y = x[perm], y[perm]
+    return np.ascontiguousarray(x), np.ascontiguousarray(y), min(sx, sy)
+
+
+def wall_conforming_lattice(n, eps=0.3, seed=0, morton=True):
+    """n*n nodes at (i/(n-1), j/(n-1)); interior nodes jittered in both
+    coordinates, wall nodes only along the wall, corners fixed.  Used for the
+    one-sided boundary stencil tests (nodes lie on the boundary as in the
+    paper's bounded cases)."""
+    s = 1.0 / (n - 1)
+    rng = np.random.default_rng(seed)
+    jj, ii = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    ii = ii.ravel()
+    jj = jj.ravel()
+    jx = rng.uniform(-eps, eps, ii.size)
+    jy = rng.uniform(-eps, eps, ii.size)
+    on_x = (ii == 0) | (ii == n - 1)
+    on_y = (jj == 0) | (jj == n - 1)
+    jx[on_x] = 0.0
+    jy[on_y] = 0.0
+    x = (ii + jx) * s
+    y = (jj + jy) * s
+    if morton:
+        perm = np.argsort(_morton_key(ii, jj), kind="stable")
+        x, y = x[perm], y[perm]
+    return np.ascontiguousarray(x), np.ascontiguousarray(y), s
+
+
+def unit_domain(periodic=False):
+    return {"lo": (0.0, 0.0), "hi": (1.0, 1.0), "periodic": (bool(periodic), bool(periodic))}
+
+
+def order_map(x, y, k, band=0.0, k_boundary=None, periodic=False):
+    """Per-node order: k everywhere; min(k, k_boundary) where the distance to
+    the nearest wall of [0,1]^2 is below `band` (non-periodic domains)."""
+    order = np.full(x.size, k, dtype=np.int8)
+    if not periodic and band > 0.0 and k_boundary is not None:
+        wall = np.minimum(np.minimum(x, 1.0 - x), np.minimum(y, 1.0 - y))
+        order[wall < band] = min(k, k_boundary)
+    return order
+
+
+def interior_mask(x, y, band):
+    wall = np.minimum(np.minimum(x, 1.0 - x), np.minimum(y, 1.0 - y))
+    return wall >= band
+
+
+# ---------------------------------------------------------------------------
+# workload configurations (sizes and conventions of the measured workloads)
+
+def config(name):
+    """Workload parameters.  Radii are in units of the lattice spacing s."""
+    cfgs = {
+        # 32x32, order 4 everywhere, R0 = 2.85 s (mean N ~ 24), FP64 weights
+        "c1": dict(n_side=32, eps=0.3, seed=1, k=4, k_boundary=4, R_s=2.85, periodic=False),
+        # 512x512, order 8 interior / order 4 in a boundary band of width R0, R0 = 4.4 s (mean N ~ 60)
+        "c2": dict(n_side=512, eps=0.3, seed=2, k=8, k_boundary=4, R_s=4.4, periodic=False),
+        # 1024x1024 periodic, order 6, R = 4.0 s (mean N ~ 50), RK4 advection-diffusion
+        "c5": dict(n_side=1024, eps=0.3, seed=5, k=6, k_boundary=6, R_s=4.0, periodic=True,
+                   a=(1.0, 0.5), nu=1e-3, beta=1e-7, dt_s=0.2, nsteps=1000,
+                   x0=(0.5, 0.5), width2=0.01),
+    }
+    return dict(cfgs[name])
+
+
+def make_nodes(cfg, n_side=None, seed=None):
+    """Node set + per-node order + initial radius for a config dict."""
+    n_side = cfg["n_side"] if n_side is None else n_side
+    seed = cfg["seed"] if seed is None else seed
+    x, y, s = jittered_lattice(n_side, eps=cfg["eps"], seed=seed, periodic=cfg["periodic"])
+    R0 = cfg["R_s"] * s
+    order = order_map(x, y, cfg["k"], band=R0, k_boundary=cfg["k_boundary"], periodic=cfg["periodic"])
+    R = np.full(x.size, R0)
+    return dict(x=x, y=y, s=s, R0=R0, R=R, order=order, domain=unit_domain(cfg["periodic"]))
+
+
+# ---------------------------------------------------------------------------
+# test fields with analytic derivatives (dx, dy, laplacian)
+
+def sincos_field(x, y):
+    """f = sin(2 pi x) cos(2 pi y)."""
+    tp = 2.0 * math.pi
+    f = np.sin(tp * x) * np.cos(tp * y)
+    fx = tp * np.cos(tp * x) * np.cos(tp * y)
+    fy = -tp * np.sin(tp * x) * np.sin(tp * y)
+    lap = -2.0 * tp * tp * f
+    return f, fx, fy, lap
+
+
+def p6_field(x, y):
+    """The paper's polynomial test function (Sec. 4.1 eq. p6), H = 1:
+    1 + (xh yh)^4 + sum_{n=1..6} (xh^n + yh^n), xh = x - 0.1453, yh = y - 0.16401."""
+    xh = x - 0.1453
+    yh = y - 0.16401
+    f = 1.0 + (xh * yh) ** 4
+    fx = 4.0 * xh ** 3 * yh ** 4
+    fy = 4.0 * xh ** 4 * yh ** 3
+    lap = 12.0 * xh ** 2 * yh ** 4 + 12.0 * xh ** 4 * yh ** 2
+    for n in range(1, 7):
+        f = f + xh ** n + yh ** n
+        fx = fx + n * xh ** (n - 1)
+        fy = fy + n * yh ** (n - 1)
+        if n >= 2:
+            lap = lap + n * (n - 1) * (xh ** (n - 2) + yh ** (n - 2))
+    return f, fx, fy, lap
+
+
+def trig_poly(seed, deg=8):
+    """Random trigonometric polynomial of degree <= deg on the unit torus:
+    coefficients a, b ~ N(0,1)/(1 + m^2 + n^2) for |m|, |n| <= deg, (m,n) != 0."""
+    rng = np.random.default_rng(seed)
+    modes = [(m, n) for m in range(-deg, deg + 1) for n in range(-deg, deg + 1) if (m, n) != (0, 0)]
+    modes = np.array(modes, dtype=np.float64)
+    scale = 1.0 / (1.0 + modes[:, 0] ** 2 + modes[:, 1] ** 2)
+    a = rng.standard_normal(len(modes)) * scale
+    b = rng.standard_normal(len(modes)) * scale
+    return modes, a, b
+
+
+def trig_field(x, y, poly):
+    modes, a, b = poly
+    f = np.zeros_like(x)
+    fx = np.zeros_like(x)
+    fy = np.zeros_like(x)
+    lap = np.zeros_like(x)
+    tp = 2.0 * math.pi
+    for (m, n), am, bm in zip(modes, a, b):
+        ph = tp * (m * x + n * y)
+        c, s_ = np.cos(ph), np.sin(ph)
+        f += am * c + bm * s_
+        fx += tp * m * (-am * s_ + bm * c)
+        fy += tp * n * (-am * s_ + bm * c)
+        lap += -(tp ** 2) * (m * m + n * n) * (am * c + bm * s_)
+    return f, fx, fy, lap
+
+
+def gaussian_pulse(x, y, x0=(0.5, 0.5), width2=0.01, periodic=True):
+    """u0 = exp(-|x - x0|^2 / width2), minimum-image distance when periodic."""
+    dx = x - x0[0]
+    dy = y - x0[1]
+    if periodic:
+        dx = dx - np.round(dx)
+        dy = dy - np.round(dy)
+    return np.exp(-(dx * dx + dy * dy) / width2)
+
+
+def advected_gaussian(x, y, t, a, nu, x0=(0.5, 0.5), width2=0.01, images=2):
+    """Free-space solution of u_t + a.grad u = nu lap u from gaussian_pulse,
+    summed over periodic images of the unit torus."""
+    s2 = width2 + 4.0 * nu * t
+    amp = width2 / s2
+    cx = x0[0] + a[0] * t
+    cy = x0[1] + a[1] * t
+    u = np.zeros_like(x)
+    for ix in range(-images, images + 1):
+        for iy in range(-images, images + 1):
+            dx = x - cx - ix
+            dy = y - cy - iy
+            u += amp * np.exp(-(dx * dx + dy * dy) / s2)
+    return u
