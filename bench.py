@@ -1,0 +1,223 @@
+#!/usr/bin/env python
+"""LABFM hot path benchmark on one MI355X: prints one JSON line.
+
+Workload (the headline): 512 x 512 cell-centred lattice on [0,1]^2 jittered
+by U(-0.3 s, 0.3 s) per coordinate (seed 2), order 8 interior / order 4 in the
+boundary band of width R0, R0 = 4.4 s with count-driven growth, HERMITE ABFs
+(sigma = 1) on the Wendland C2 RBF.  One step = neighbour search (count and
+fill) + weights {d/dx, d/dy, Laplacian} for every node + application of the
+three operators to a field.  `value` = order-8 nodes whose weight set passes
+the 1e-10 moment-residual gate, per second of step time.
+
+Secondary (not `value`): RK4 advection-diffusion with composed hyperviscosity
+on the 1024 x 1024 periodic order-6 workload, FP32 application.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP64 = 78.6e12      # MI355X FP64 vector / matrix, FLOP/s
+PEAK_FP32_MFMA = 157.3e12
+PEAK_HBM = 8.0e12        # bytes/s
+
+
+def weight_flops(N, p, nd, iters):
+    """Algorithmic FP64 flops of one weight set: assembly 2Np^2, LU 2p^3/3,
+    (1 + it) x [solve 2 nd p^2 + weights 2 N p nd + residual 2 N p nd]."""
+    return 2.0 * N * p * p + 2.0 * p ** 3 / 3.0 + (1.0 + iters) * (2.0 * nd * p * p + 4.0 * N * p * nd)
+
+
+def run_cpu_baseline(nd, cfg):
+    import numpy as np
+
+    import oracle as O
+    from paper_1912_06441_amd import workloads as WL
+
+    f = WL.trig_field(nd["x"], nd["y"], WL.trig_poly(0))[0]
+    t0 = time.perf_counter()
+    rp, col, R = O.neighbours(nd["x"], nd["y"], nd["domain"], nd["R"], nd["order"])
+    w, st, res, _ = O.weights(nd["x"], nd["y"], nd["domain"], R, nd["order"], rp, col)
+    for d in range(3):
+        O.apply(rp, col, w[d], f)
+    dt = time.perf_counter() - t0
+    good = int(((st == 0) & (nd["order"] == 8)).sum())
+    return {"value": good / dt, "unit": "weight-sets/s (order 8)", "cores": O.num_threads(), "kind": "oracle",
+            "sample": "the full 512x512 workload, one step (neighbours + FP64 weights + 3 operators), %.2f s" % dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--prec", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-rk4", action="store_true")
+    ap.add_argument("--rk4-steps", type=int, default=200)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only (the method's kernels run on one device); "
+              "--gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1912_06441_amd as L
+    from paper_1912_06441_amd import workloads as WL
+
+    dev = torch.device("cuda:0")
+    cfg = WL.config("c2")
+    nd = WL.make_nodes(cfg)
+    n = nd["x"].size
+    x = torch.from_numpy(nd["x"]).to(dev)
+    y = torch.from_numpy(nd["y"]).to(dev)
+    R0 = torch.from_numpy(nd["R"]).to(dev)
+    order = torch.from_numpy(nd["order"]).to(dev)
+    f = torch.from_numpy(WL.trig_field(nd["x"], nd["y"], WL.trig_poly(0))[0]).to(dev)
+    prec = L.PREC_FP64 if args.prec == "fp64" else L.PREC_MIXED
+    ctx = L.Context(0)
+    R = R0.clone()
+
+    # sizes and output buffers (nnz is deterministic for a node set)
+    rp, col = ctx.build_neighbours(x, y, R, order, nd["domain"])
+    nnz = col.numel()
+    bufs = (torch.empty((3, nnz), dtype=torch.float64, device=dev), None,
+            torch.empty(n, dtype=torch.int8, device=dev), torch.empty(n, dtype=torch.float32, device=dev),
+            torch.empty(n, dtype=torch.int8, device=dev))
+    out = torch.empty((3, n), dtype=torch.float64, device=dev)
+
+    def step():
+        R.copy_(R0)
+        rp_, col_ = ctx.build_neighbours(x, y, R, order, nd["domain"])
+        ctx.weights(x, y, R, order, rp_, col_, nd["domain"], prec=prec, out=bufs)
+        ctx.apply_operator(rp_, col_, bufs[0], f, out=out)
+        return rp_, col_
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        rp, col = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.timing(False)
+    ms = (t1 - t0) * 1e3 / args.steps
+    # read the order-8 kernel separately, then every weights kernel
+    k8 = ctx.timing_read("weights64_k8")
+    kw_rest = ctx.timing_read("weights")
+    kw = (k8[0] + kw_rest[0], k8[1] + kw_rest[1])
+    kn = ctx.timing_read("neigh")
+    ka = ctx.timing_read("apply")
+    ctx.timing_read(None)
+
+    status = bufs[2].cpu().numpy()
+    iters = bufs[4].cpu().numpy().astype(np.float64)
+    resid = bufs[3].cpu().numpy()
+    N = np.diff(rp.cpu().numpy())
+    is8 = nd["order"] == 8
+    good8 = int(((status == 0) & is8).sum())
+    value = good8 / (ms / 1e3)
+
+    # roofline of the dominant kernel (order-8 weights), algorithmic flops per launch
+    flops8 = float(weight_flops(N[is8].astype(np.float64), 44, 3, iters[is8]).sum())
+    k8_ms = k8[1] / max(k8[0], 1)
+    achieved = flops8 / (k8_ms / 1e3)
+    # operator application: algorithmic bytes per launch (col 4 B + 3 FP64 weights per entry;
+    # row_ptr, u_i and 3 FP64 outputs per node)
+    apply_bytes = nnz * (4 + 3 * 8) + n * (8 + 8 + 3 * 8)
+    ka_ms = ka[1] / max(ka[0], 1)
+
+    rec = {
+        "metric": "node weight-sets/sec (order 8) and operator apps (nodes/s) at 1e-10 rel err",
+        "value": value,
+        "unit": "weight-sets/s (order 8)",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.prec == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "512x512 jittered lattice (eps 0.3 s, seed 2), order 8 interior / 4 boundary band, "
+                               "R0 = 4.4 s + growth, Hermite x Wendland C2 ABFs; step = neighbours + weights "
+                               "{dx, dy, lap} + 3-operator application",
+                   "nodes": n, "nnz": nnz, "order8_nodes": int(is8.sum()), "prec": args.prec},
+        "stages_ms": {"neighbours": kn[1] / args.steps, "weights": kw[1] / args.steps,
+                      "weights_order8_kernel": k8_ms, "apply_3ops": ka_ms},
+        "accuracy": {"nodes_passing_1e-10": int((status == 0).sum()), "nodes": n,
+                     "max_moment_residual": float(resid.max()), "mean_refinement_iters": float(iters.mean())},
+        "operator_apps": {"value": n / (ka_ms / 1e3), "unit": "nodes/s (3 fused FP64 operators)",
+                          "GB_per_s": apply_bytes / (ka_ms / 1e3) / 1e9},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64, "traffic": None, "kernel": "weights64_k8",
+                     "flops_per_launch": flops8},
+    }
+
+    if not args.no_rk4:
+        rec["rk4_c5"] = run_rk4(ctx, torch, np, L, WL, args.rk4_steps)
+
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = run_cpu_baseline(nd, cfg)
+    ctx.close()
+    print(json.dumps(rec), flush=True)
+
+
+def run_rk4(ctx, torch, np, L, WL, nsteps):
+    """1024x1024 periodic order-6 RK4 (FP32 application): ms per step and
+    operator applications per second (3 stencil passes per stage)."""
+    dev = torch.device("cuda:0")
+    cfg = WL.config("c5")
+    nd = WL.make_nodes(cfg)
+    n = nd["x"].size
+    x = torch.from_numpy(nd["x"]).to(dev)
+    y = torch.from_numpy(nd["y"]).to(dev)
+    R = torch.from_numpy(nd["R"]).to(dev)
+    order = torch.from_numpy(nd["order"]).to(dev)
+    rp, col = ctx.build_neighbours(x, y, R, order, nd["domain"])
+    w64, _, st, res, _ = ctx.weights(x, y, R, order, rp, col, nd["domain"], ops=1 | 2 | 4 | 8)
+    a, nu = cfg["a"], cfg["nu"]
+    _, wlin = ctx.combine(w64[:3], [-a[0], -a[1], nu], want64=False, want32=True)
+    wbh = w64[3].to(torch.float32)
+    s = nd["s"]
+    h = 0.5 * cfg["R_s"] * s
+    dt = cfg["dt_s"] * s
+    gamma = cfg["beta"] * h ** 8 / dt
+    u = torch.from_numpy(WL.gaussian_pulse(nd["x"], nd["y"])).to(dev).to(torch.float32)
+    scratch = torch.empty(5 * n, dtype=torch.float32, device=dev)
+    ctx.step(rp, col, wlin, wbh, gamma, dt, u, 5, scratch=scratch)  # warm-up + graph capture
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    t0 = time.perf_counter()
+    ctx.step(rp, col, wlin, wbh, gamma, dt, u, nsteps, scratch=scratch)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.timing(False)
+    kg = ctx.timing_read("step")
+    ctx.timing_read(None)
+    nnz = col.numel()
+    ms_step = kg[1] / nsteps
+    # per stage: pass A reads col + 2 weight streams (4 B each), pass B col + 1 weight stream;
+    # per node per stage ~ 8 x 4 B of state reads/writes
+    bytes_step = 4 * (nnz * (4 + 4 + 4) + nnz * (4 + 4) + n * 8 * 4)
+    return {"nodes": n, "nnz": nnz, "steps": nsteps, "ms_per_rk4_step": ms_step,
+            "wall_ms_per_rk4_step": (t1 - t0) * 1e3 / nsteps,
+            "operator_apps_nodes_per_s": 12 * n / (ms_step / 1e3),
+            "GB_per_s": bytes_step / (ms_step / 1e3) / 1e9, "hbm_frac": bytes_step / (ms_step / 1e3) / PEAK_HBM,
+            "weights_all_ok": bool((st == 0).all().item()), "u_max": float(u.abs().max().item())}
+
+
+if __name__ == "__main__":
+    main()

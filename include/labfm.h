@@ -1,0 +1,201 @@
+/*
+ * labfm.h -- C ABI of the MI355X (gfx950) LABFM library (liblabfm.so).
+ *
+ * Local Anisotropic Basis Function Method, King, Lind & Nasar,
+ * arXiv:1912.06441.  The library covers the data-parallel hot path:
+ *   1. neighbour sets of every node (Sec. 2: all j within radius 2h),
+ *   2. per-node weights (Sec. 3.1: M_i = sum_j X_ji (x) W_ji, M_i Psi^d = C^d,
+ *      w^d_ji = W_ji . Psi^d),
+ *   3. operator application (Sec. 2 eq. general_do: L^d_i(u) = sum_j (u_j - u_i) w^d_ji),
+ *   4. explicit RK4 time stepping with those operators (Sec. 4.1).
+ *
+ * Conventions shared by every entry point:
+ *   - Pointers named as device pointers must point to memory on the
+ *     context's device (hipMalloc, or torch tensors on that device); host
+ *     structs are read during the call only.  The caller owns all memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Every call only enqueues work on `stream` and returns, except where
+ *     a call says it synchronises.
+ *   - Argument errors return LABFM_EINVAL before anything is enqueued and
+ *     set a thread-local message readable with labfm_last_error().
+ *   - Inputs are never modified, except R when neighbour growth is on.
+ *   - Node order is the caller's; sorting nodes by space-filling curve
+ *     before the calls gives coalesced gathers.
+ *   - Positions and radii are FP64; indices are int32 (col) / int64 (row_ptr).
+ */
+#ifndef LABFM_H
+#define LABFM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LABFM_OK = 0,
+    LABFM_EINVAL = -1,      /* bad argument (see labfm_last_error)          */
+    LABFM_ENOMEM = -2,      /* library scratch allocation failed            */
+    LABFM_EHIP = -3,        /* a HIP runtime call failed                    */
+    LABFM_EUNSUPPORTED = -4 /* valid request this build does not implement  */
+} labfm_err;
+
+/* ABF family.  HERMITE: W_m(d) = H_a(sigma d_x) H_b(sigma d_y) phi(|d|)
+ * (physicists' Hermite polynomials times a radial function).  PAPER:
+ * W_m = d^a_x d^b_y W0(|d|) (Sec. 3.2), keeping only the dW0/dr term for
+ * elements of total order >= 4 (App. A).  (a, b) follow the element order of
+ * the monomial vector X (Sec. 2 eq. 1). */
+typedef enum { LABFM_ABF_HERMITE = 0, LABFM_ABF_PAPER = 1 } labfm_abf;
+
+/* Fundamental RBF (App. A): cone, quadratic, Wendland C6, Gaussian, and the
+ * 2-D Wendland C2 (1 - q/2)^4 (1 + 2q).  Constants do not change weights. */
+typedef enum {
+    LABFM_RBF_WENDLAND_C2 = 0,
+    LABFM_RBF_CONE = 1,
+    LABFM_RBF_QUADRATIC = 2,
+    LABFM_RBF_WENDLAND_C6 = 3,
+    LABFM_RBF_GAUSSIAN = 4
+} labfm_rbf;
+
+/* Operators (bits; weight sets are written in increasing bit order).
+ * Targets C^d (Sec. 2, Sec. 3.3): DX e1, DY e2, LAP e3 + e5,
+ * BIHARM -(e10 + 2 e12 + e14) (i.e. -nabla^4, needs k >= 4),
+ * TRIHARM e21 + 3 e23 + 3 e25 + e27 (nabla^6, needs k >= 6). */
+enum {
+    LABFM_OP_DX = 1,
+    LABFM_OP_DY = 2,
+    LABFM_OP_LAP = 4,
+    LABFM_OP_BIHARM = 8,
+    LABFM_OP_TRIHARM = 16
+};
+
+/* Precision of the weight computation.
+ * FP64: basis, moment matrix, LU and refinement all in FP64.
+ * MIXED: basis and moment matrix in FP32 on matrix cores (FP32 accumulate),
+ *        FP32 LU, FP64 residual and FP64 weight refinement; nodes whose
+ *        refinement does not converge are recomputed on the FP64 path. */
+typedef enum { LABFM_PREC_FP64 = 0, LABFM_PREC_MIXED = 1 } labfm_prec;
+
+/* Per-node status written by labfm_weights. */
+enum {
+    LABFM_ST_OK = 0,             /* moment residual <= tol_pass              */
+    LABFM_ST_NOT_CONVERGED = 1,  /* weights written, residual > tol_pass     */
+    LABFM_ST_SINGULAR = 2,       /* zero/non-finite pivot; weights zero      */
+    LABFM_ST_TOO_FEW = 3,        /* fewer neighbours than p; weights zero    */
+    LABFM_ST_DEGENERATE = 4,     /* PAPER ABFs undefined (coincident node)   */
+    LABFM_ST_ORDER_TOO_LOW = 5,  /* order cannot express a requested target  */
+    LABFM_ST_TOO_MANY = 6        /* more than LABFM_MAX_NEIGHBOURS neighbours */
+};
+
+#define LABFM_MAX_ORDER 8
+#define LABFM_MAX_NEIGHBOURS 128
+
+/* Axis-aligned domain; periodic axes use the minimum-image offset. */
+typedef struct {
+    double lo[2], hi[2];
+    int periodic[2];
+} labfm_domain;
+
+typedef struct {
+    int abf;           /* labfm_abf                                        */
+    int rbf;           /* labfm_rbf                                        */
+    double sigma;      /* Hermite argument scale (HERMITE family)          */
+    unsigned ops;      /* LABFM_OP_* bits                                  */
+    int prec;          /* labfm_prec                                       */
+    double tol_stop;   /* refinement stops when ||C - X^T w||_inf <= this  */
+    double tol_pass;   /* status OK when the final residual <= this        */
+    int max_iters;     /* FP64 refinement updates at most                  */
+} labfm_wopts;
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* labfm_last_error(void);
+
+/* Context: device id, library scratch (bucket grid, work lists), stream-
+ * independent.  One context per device; calls on one context must not
+ * overlap in time (scratch is shared). */
+labfm_err labfm_create(void** ctx, int device);
+labfm_err labfm_destroy(void* ctx);
+
+/* Neighbour sets (Sec. 2): row i lists every j != i with
+ * (x_j - x_i)^2 + (y_j - y_i)^2 < R_i^2 (minimum image on periodic axes),
+ * in ascending j.  Two phases:
+ *   count pass (col == NULL): if grow != 0, R_i <- 1.1 R_i (at most
+ *     max_grow times) while the count is below N_crit(order_i) =
+ *     8, 21, 37, 57 for order <= 2, 4, 6, 8 (Sec. 3.2 critical stencil
+ *     sizes); writes R (grown) and row_ptr[n+1]; synchronises `stream` and
+ *     returns the total in *nnz_host.
+ *   fill pass (col != NULL): writes col[row_ptr[n]] for the R and row_ptr
+ *     of the count pass; asynchronous.
+ * x, y, R: device FP64 [n]; order: device int8 [n] (used only when grow);
+ * row_ptr: device int64 [n+1]; col: device int32 [nnz].
+ * Nodes must lie in [lo, hi] on every axis. */
+labfm_err labfm_build_neighbours(void* ctx, const double* x, const double* y, int64_t n,
+                                 const labfm_domain* dom, double* R, const int8_t* order,
+                                 int grow, int max_grow, int64_t* row_ptr, int32_t* col,
+                                 int64_t* nnz_host, void* stream);
+
+/* Weights (Sec. 3.1 eqs. w_abf, disc_form, lsys) for every node i with
+ * order k_i (1..8), h_i = R_i / 2, scaled offsets d_j = r_ji / h_i:
+ *   M = sum_j X(d_j) W(d_j)^T, M Psi = C^d, w_j = W(d_j) . Psi,
+ * solved by row-then-column max equilibration and LU with partial
+ * pivoting, refined on the weights (r = C - X^T w; w += W M^-1 r) in FP64,
+ * and unscaled by h^l (l = 1, 1, 2, 4, 6 for DX, DY, LAP, BIHARM, TRIHARM).
+ * Outputs (device): w64 [nops][nnz] FP64 and/or w32 [nops][nnz] FP32 (either
+ * may be NULL, not both); status int8 [n]; resid FP32 [n] (final
+ * max-norm moment residual over the operators); iters int8 [n] (FP64
+ * refinement updates).  Failed nodes get zero weights.  Asynchronous. */
+labfm_err labfm_weights(void* ctx, const double* x, const double* y, int64_t n,
+                        const labfm_domain* dom, const double* R, const int8_t* order,
+                        const int64_t* row_ptr, const int32_t* col, int64_t nnz,
+                        const labfm_wopts* opt, double* w64, float* w32, int8_t* status,
+                        float* resid, int8_t* iters, void* stream);
+
+/* out[s] = sum_k coef[k] * w64[k][s] for s < nnz (a linear combination of
+ * weight sets is the weight set of the combined target, C^d being linear).
+ * coef: host [nsets]; out64 and/or out32 device [nnz].  Asynchronous. */
+labfm_err labfm_combine(void* ctx, const double* w64, int nsets, const double* coef,
+                        int64_t nnz, double* out64, float* out32, void* stream);
+
+/* Operator application (Sec. 2 eq. general_do), nops operators sharing one
+ * neighbour structure: out[d][i] = sum_{s in row i} w[d][s] (u[col[s]] - u[i]).
+ * dtype 0: w, u, out FP32; dtype 1: FP64.  w [nops][nnz], out [nops][n]
+ * (device).  Asynchronous. */
+labfm_err labfm_apply_operator(void* ctx, const int64_t* row_ptr, const int32_t* col, int64_t n,
+                               int64_t nnz, int nops, const void* w, int dtype, const void* u,
+                               void* out, void* stream);
+
+/* Classical RK4 (Sec. 4.1) on du/dt = L_lin(u) - gamma B(B(u)), where L_lin
+ * uses w_lin and B (optional) uses w_bh; with B the -nabla^4 stencil,
+ * B o B approximates nabla^8 (composed hyperviscosity). */
+typedef struct {
+    const int64_t* row_ptr; /* device int64 [n+1]                   */
+    const int32_t* col;     /* device int32 [nnz]                   */
+    int64_t n, nnz;
+    int dtype;              /* 0: FP32 weights and state; 1: FP64   */
+    const void* w_lin;      /* device [nnz]                         */
+    const void* w_bh;       /* device [nnz] or NULL                 */
+    double gamma;           /* coefficient of B(B(u))               */
+    double dt;
+} labfm_step_plan;
+
+/* Advance u (device [n], dtype of the plan) by nsteps RK4 steps.
+ * scratch: device, at least 5 n elements of the plan's dtype.
+ * use_graph != 0 captures one step as a HIP graph and replays it.
+ * Asynchronous. */
+labfm_err labfm_step(void* ctx, const labfm_step_plan* plan, void* u, void* scratch, int nsteps,
+                     int use_graph, void* stream);
+
+/* Kernel timing for measurement: while enabled, HIP events are recorded on
+ * the launch stream around each kernel the library launches (outside graph
+ * capture).  labfm_timing_read waits for the recorded kernels whose name
+ * contains `filter` (NULL: all), returns their count and summed duration in
+ * milliseconds, and forgets them.  Kernel names: neigh_count, neigh_fill,
+ * weights64_k1..k8, weights32_k1..k8, apply_f32, apply_f64, step_graph,
+ * step_direct. */
+labfm_err labfm_timing_enable(void* ctx, int enable);
+labfm_err labfm_timing_read(void* ctx, const char* filter, int64_t* launches, double* total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LABFM_H */

@@ -1,0 +1,229 @@
+"""MI355X (gfx950) LABFM hot path: neighbours, weights, operator application, RK4.
+
+Thin ctypes binding over liblabfm.so (C ABI in include/labfm.h).  Arguments
+are torch tensors on the GPU; every step runs in the library's HIP kernels on
+torch's current stream.  There is no CPU fallback: if liblabfm.so is missing
+or no GPU is present, calls raise.
+
+Method: King, Lind & Nasar, "High order difference schemes using the Local
+Anisotropic Basis Function Method", arXiv:1912.06441 (Sec. 2, 3.1, 3.2,
+App. A, Sec. 4.1).
+"""
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblabfm.so")
+
+ABF_HERMITE, ABF_PAPER = 0, 1
+RBF_WENDLAND_C2, RBF_CONE, RBF_QUADRATIC, RBF_WENDLAND_C6, RBF_GAUSSIAN = 0, 1, 2, 3, 4
+OP_DX, OP_DY, OP_LAP, OP_BIHARM, OP_TRIHARM = 1, 2, 4, 8, 16
+PREC_FP64, PREC_MIXED = 0, 1
+ST_OK, ST_NOT_CONVERGED, ST_SINGULAR, ST_TOO_FEW, ST_DEGENERATE, ST_ORDER_TOO_LOW, ST_TOO_MANY = range(7)
+MAX_NEIGHBOURS = 128
+EXPORTED = sorted(["labfm_last_error", "labfm_create", "labfm_destroy", "labfm_build_neighbours", "labfm_weights",
+                   "labfm_combine", "labfm_apply_operator", "labfm_step", "labfm_timing_enable",
+                   "labfm_timing_read"])
+
+
+class LabfmError(RuntimeError):
+    pass
+
+
+class Domain(C.Structure):
+    _fields_ = [("lo", C.c_double * 2), ("hi", C.c_double * 2), ("periodic", C.c_int * 2)]
+
+
+class WOpts(C.Structure):
+    _fields_ = [("abf", C.c_int), ("rbf", C.c_int), ("sigma", C.c_double), ("ops", C.c_uint),
+                ("prec", C.c_int), ("tol_stop", C.c_double), ("tol_pass", C.c_double), ("max_iters", C.c_int)]
+
+
+class StepPlan(C.Structure):
+    _fields_ = [("row_ptr", C.c_void_p), ("col", C.c_void_p), ("n", C.c_int64), ("nnz", C.c_int64),
+                ("dtype", C.c_int), ("w_lin", C.c_void_p), ("w_bh", C.c_void_p), ("gamma", C.c_double),
+                ("dt", C.c_double)]
+
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load liblabfm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise LabfmError("liblabfm.so not built (%s); run paper_1912_06441_amd/build.py" % path)
+    L = C.CDLL(path)
+    vp, i64, dp = C.c_void_p, C.c_int64, C.c_double
+    L.labfm_last_error.restype = C.c_char_p
+    L.labfm_create.argtypes = [C.POINTER(vp), C.c_int]
+    L.labfm_destroy.argtypes = [vp]
+    L.labfm_build_neighbours.argtypes = [vp, vp, vp, i64, C.POINTER(Domain), vp, vp, C.c_int, C.c_int, vp, vp,
+                                         C.POINTER(i64), vp]
+    L.labfm_weights.argtypes = [vp, vp, vp, i64, C.POINTER(Domain), vp, vp, vp, vp, i64, C.POINTER(WOpts), vp, vp,
+                                vp, vp, vp, vp]
+    L.labfm_combine.argtypes = [vp, vp, C.c_int, C.POINTER(dp), i64, vp, vp, vp]
+    L.labfm_apply_operator.argtypes = [vp, vp, vp, i64, i64, C.c_int, vp, C.c_int, vp, vp, vp]
+    L.labfm_step.argtypes = [vp, C.POINTER(StepPlan), vp, vp, C.c_int, C.c_int, vp]
+    L.labfm_timing_enable.argtypes = [vp, C.c_int]
+    L.labfm_timing_read.argtypes = [vp, C.c_char_p, C.POINTER(i64), C.POINTER(dp)]
+    for name in EXPORTED:
+        if name != "labfm_last_error":
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(rc, what):
+    if rc != 0:
+        msg = _lib.labfm_last_error().decode(errors="replace")
+        raise LabfmError("%s failed (%d): %s" % (what, rc, msg))
+
+
+def _torch():
+    import torch
+
+    if not torch.cuda.is_available():
+        raise LabfmError("no HIP device: the LABFM path runs only on the GPU")
+    return torch
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(torch):
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def make_domain(domain):
+    d = Domain()
+    d.lo[0], d.lo[1] = [float(v) for v in domain["lo"]]
+    d.hi[0], d.hi[1] = [float(v) for v in domain["hi"]]
+    d.periodic[0], d.periodic[1] = [int(bool(v)) for v in domain["periodic"]]
+    return d
+
+
+def nops_of(ops):
+    return bin(int(ops) & 31).count("1")
+
+
+class Context:
+    """A library context on one device (scratch + cached graphs)."""
+
+    def __init__(self, device=0):
+        self.torch = _torch()
+        self.lib = load_library()
+        self.device = device
+        h = C.c_void_p()
+        _check(self.lib.labfm_create(C.byref(h), int(device)), "labfm_create")
+        self.h = h
+
+    def close(self):
+        if self.h:
+            self.lib.labfm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ timing
+    def timing(self, enable=True):
+        _check(self.lib.labfm_timing_enable(self.h, int(bool(enable))), "labfm_timing_enable")
+
+    def timing_read(self, name_filter=None):
+        """(launches, total_ms) of the recorded kernels whose name contains name_filter."""
+        n = C.c_int64(0)
+        ms = C.c_double(0.0)
+        f = name_filter.encode() if name_filter else None
+        _check(self.lib.labfm_timing_read(self.h, f, C.byref(n), C.byref(ms)), "labfm_timing_read")
+        return n.value, ms.value
+
+    # ------------------------------------------------------------------ neighbours
+    def build_neighbours(self, x, y, R, order, domain, grow=True, max_grow=10):
+        """CSR neighbour lists.  R is updated in place when grow.  Returns (row_ptr, col)."""
+        torch = self.torch
+        n = x.numel()
+        dom = make_domain(domain)
+        row_ptr = torch.empty(n + 1, dtype=torch.int64, device=x.device)
+        nnz = C.c_int64(0)
+        st = _stream(torch)
+        _check(self.lib.labfm_build_neighbours(self.h, _ptr(x), _ptr(y), n, C.byref(dom), _ptr(R), _ptr(order),
+                                               int(bool(grow)), int(max_grow), _ptr(row_ptr), None,
+                                               C.byref(nnz), st), "labfm_build_neighbours(count)")
+        col = torch.empty(max(nnz.value, 1), dtype=torch.int32, device=x.device)
+        _check(self.lib.labfm_build_neighbours(self.h, _ptr(x), _ptr(y), n, C.byref(dom), _ptr(R), _ptr(order),
+                                               0, 0, _ptr(row_ptr), _ptr(col), None, st),
+               "labfm_build_neighbours(fill)")
+        return row_ptr, col[:nnz.value]
+
+    # ------------------------------------------------------------------ weights
+    def weights(self, x, y, R, order, row_ptr, col, domain, ops=OP_DX | OP_DY | OP_LAP, abf=ABF_HERMITE,
+                rbf=RBF_WENDLAND_C2, sigma=1.0, prec=PREC_FP64, tol_stop=1e-13, tol_pass=1e-10, max_iters=5,
+                want64=True, want32=False, out=None):
+        """Weights [nops, nnz] (FP64 and/or FP32), status[n] int8, resid[n] f32, iters[n] int8."""
+        torch = self.torch
+        n = x.numel()
+        nnz = col.numel()
+        k = nops_of(ops)
+        dev = x.device
+        if out is None:
+            w64 = torch.empty((k, nnz), dtype=torch.float64, device=dev) if want64 else None
+            w32 = torch.empty((k, nnz), dtype=torch.float32, device=dev) if want32 else None
+            status = torch.empty(n, dtype=torch.int8, device=dev)
+            resid = torch.empty(n, dtype=torch.float32, device=dev)
+            iters = torch.empty(n, dtype=torch.int8, device=dev)
+        else:
+            w64, w32, status, resid, iters = out
+        o = WOpts(int(abf), int(rbf), float(sigma), int(ops), int(prec), float(tol_stop), float(tol_pass),
+                  int(max_iters))
+        dom = make_domain(domain)
+        _check(self.lib.labfm_weights(self.h, _ptr(x), _ptr(y), n, C.byref(dom), _ptr(R), _ptr(order),
+                                      _ptr(row_ptr), _ptr(col), nnz, C.byref(o), _ptr(w64), _ptr(w32),
+                                      _ptr(status), _ptr(resid), _ptr(iters), _stream(torch)), "labfm_weights")
+        return w64, w32, status, resid, iters
+
+    def combine(self, w64, coef, want64=True, want32=False):
+        torch = self.torch
+        nsets, nnz = w64.shape
+        c = (C.c_double * nsets)(*[float(v) for v in coef])
+        o64 = torch.empty(nnz, dtype=torch.float64, device=w64.device) if want64 else None
+        o32 = torch.empty(nnz, dtype=torch.float32, device=w64.device) if want32 else None
+        _check(self.lib.labfm_combine(self.h, _ptr(w64), nsets, c, nnz, _ptr(o64), _ptr(o32), _stream(torch)),
+               "labfm_combine")
+        return o64, o32
+
+    # ------------------------------------------------------------------ application
+    def apply_operator(self, row_ptr, col, w, u, out=None):
+        """out[d, i] = sum_j w[d, s] (u[col[s]] - u[i]); w is [nops, nnz] or [nnz]."""
+        torch = self.torch
+        n = u.numel()
+        w2 = w if w.dim() == 2 else w.view(1, -1)
+        nops, nnz = w2.shape
+        if w2.dtype != u.dtype:
+            raise LabfmError("weights and field must have the same dtype")
+        dtype = 1 if u.dtype == torch.float64 else 0
+        if out is None:
+            out = torch.empty((nops, n), dtype=u.dtype, device=u.device)
+        _check(self.lib.labfm_apply_operator(self.h, _ptr(row_ptr), _ptr(col), n, nnz, nops, _ptr(w2), dtype,
+                                             _ptr(u), _ptr(out), _stream(torch)), "labfm_apply_operator")
+        return out if w.dim() == 2 else out[0]
+
+    # ------------------------------------------------------------------ time stepping
+    def step(self, row_ptr, col, w_lin, w_bh, gamma, dt, u, nsteps, scratch=None, use_graph=True):
+        """Advance u in place by nsteps RK4 steps of du/dt = L_lin u - gamma B(B u)."""
+        torch = self.torch
+        n = u.numel()
+        if scratch is None:
+            scratch = torch.empty(5 * n, dtype=u.dtype, device=u.device)
+        dtype = 1 if u.dtype == torch.float64 else 0
+        plan = StepPlan(row_ptr.data_ptr(), col.data_ptr(), n, col.numel(), dtype, w_lin.data_ptr(),
+                        w_bh.data_ptr() if w_bh is not None else None, float(gamma), float(dt))
+        _check(self.lib.labfm_step(self.h, C.byref(plan), _ptr(u), _ptr(scratch), int(nsteps), int(bool(use_graph)),
+                                   _stream(torch)), "labfm_step")
+        return u

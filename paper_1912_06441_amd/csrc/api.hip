@@ -1,0 +1,265 @@
+// api.hip -- the extern "C" entry points declared in include/labfm.h:
+// argument validation, context and scratch management, launch dispatch.
+#include "labfm_internal.hpp"
+
+#include <cmath>
+#include <cstring>
+#include <string>
+
+namespace labfm {
+
+namespace {
+thread_local std::string g_last_error;
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) hipSetDevice(prev);
+    }
+};
+
+labfm_err fail(labfm_err e, const std::string& msg) {
+    set_error(msg);
+    return e;
+}
+
+GridSpec make_grid(const labfm_domain* d, int64_t n) {
+    // about four nodes per bucket; the search visits ceil(R/w) rings
+    GridSpec g{};
+    g.Lx = d->hi[0] - d->lo[0];
+    g.Ly = d->hi[1] - d->lo[1];
+    double cells = (double)(n > 0 ? n : 1) / 4.0;
+    double aspect = g.Lx / g.Ly;
+    long ncx = lround(std::sqrt(cells * aspect));
+    long ncy = lround(std::sqrt(cells / aspect));
+    if (ncx < 1) ncx = 1;
+    if (ncy < 1) ncy = 1;
+    if (ncx > 8192) ncx = 8192;
+    if (ncy > 8192) ncy = 8192;
+    g.ncx = (int)ncx;
+    g.ncy = (int)ncy;
+    g.lox = d->lo[0];
+    g.loy = d->lo[1];
+    g.wx = g.Lx / g.ncx;
+    g.wy = g.Ly / g.ncy;
+    g.perx = d->periodic[0] != 0;
+    g.pery = d->periodic[1] != 0;
+    return g;
+}
+
+bool domain_ok(const labfm_domain* d) {
+    return d && std::isfinite(d->lo[0]) && std::isfinite(d->lo[1]) && std::isfinite(d->hi[0]) &&
+           std::isfinite(d->hi[1]) && d->hi[0] > d->lo[0] && d->hi[1] > d->lo[1];
+}
+
+}  // namespace
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+labfm_err ensure(Scratch& s, size_t bytes) {
+    if (bytes == 0) bytes = 1;
+    if (s.bytes >= bytes) return LABFM_OK;
+    if (s.p) hipFree(s.p);
+    s.p = nullptr;
+    s.bytes = 0;
+    size_t want = bytes + bytes / 4;
+    if (hipMalloc(&s.p, want) != hipSuccess) {
+        s.p = nullptr;
+        set_error("scratch allocation of " + std::to_string(want) + " bytes failed");
+        return LABFM_ENOMEM;
+    }
+    s.bytes = want;
+    return LABFM_OK;
+}
+
+}  // namespace labfm
+
+using namespace labfm;
+
+extern "C" {
+
+const char* labfm_last_error(void) { return g_last_error.c_str(); }
+
+labfm_err labfm_create(void** ctx, int device) {
+    if (!ctx) return fail(LABFM_EINVAL, "labfm_create: ctx is NULL");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(LABFM_EHIP, "labfm_create: no HIP device");
+    if (device < 0 || device >= ndev) return fail(LABFM_EINVAL, "labfm_create: bad device id");
+    Context* c = new Context();
+    c->device = device;
+    *ctx = c;
+    return LABFM_OK;
+}
+
+labfm_err labfm_destroy(void* ctx) {
+    if (!ctx) return LABFM_OK;
+    Context* c = (Context*)ctx;
+    DeviceGuard g(c->device);
+    if (c->step_exec) hipStreamSynchronize(c->step_stream);
+    release_step_graph(c);
+    for (auto& t : c->timed) {
+        hipEventDestroy(t.a);
+        hipEventDestroy(t.b);
+    }
+    Scratch* all[] = {&c->grid_count, &c->grid_idx, &c->node_cell, &c->counts, &c->scan_tmp, &c->worklist, &c->mixed};
+    for (Scratch* s : all)
+        if (s->p) hipFree(s->p);
+    delete c;
+    return LABFM_OK;
+}
+
+labfm_err labfm_build_neighbours(void* ctx, const double* x, const double* y, int64_t n, const labfm_domain* dom,
+                                 double* R, const int8_t* order, int grow, int max_grow, int64_t* row_ptr,
+                                 int32_t* col, int64_t* nnz_host, void* stream) {
+    if (!ctx) return fail(LABFM_EINVAL, "labfm_build_neighbours: ctx is NULL");
+    if (n < 0 || n > INT32_MAX) return fail(LABFM_EINVAL, "labfm_build_neighbours: n out of range [0, 2^31)");
+    if (!domain_ok(dom)) return fail(LABFM_EINVAL, "labfm_build_neighbours: bad domain");
+    if (n > 0 && (!x || !y || !R || !row_ptr)) return fail(LABFM_EINVAL, "labfm_build_neighbours: NULL array");
+    if (!col && grow && n > 0 && !order) return fail(LABFM_EINVAL, "labfm_build_neighbours: order needed to grow");
+    if (max_grow < 0 || max_grow > 64) return fail(LABFM_EINVAL, "labfm_build_neighbours: max_grow out of range");
+    if (!col && !nnz_host) return fail(LABFM_EINVAL, "labfm_build_neighbours: nnz_host is NULL on the count pass");
+    Context* c = (Context*)ctx;
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(LABFM_EHIP, "labfm_build_neighbours: hipSetDevice failed");
+    hipStream_t st = (hipStream_t)stream;
+    GridSpec grid = make_grid(dom, n);
+    if (!col) {
+        labfm_err e = n > 0 ? neighbours_count(c, x, y, n, grid, R, order, grow, max_grow, row_ptr, st)
+                            : exclusive_scan_i64(c, nullptr, row_ptr, 0, st);
+        if (e != LABFM_OK) return e;
+        LABFM_HIP_CHECK(hipMemcpyAsync(nnz_host, row_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        LABFM_HIP_CHECK(hipStreamSynchronize(st));
+        return LABFM_OK;
+    }
+    if (n == 0) return LABFM_OK;
+    return neighbours_fill(c, x, y, n, grid, R, row_ptr, col, st);
+}
+
+labfm_err labfm_weights(void* ctx, const double* x, const double* y, int64_t n, const labfm_domain* dom,
+                        const double* R, const int8_t* order, const int64_t* row_ptr, const int32_t* col,
+                        int64_t nnz, const labfm_wopts* opt, double* w64, float* w32, int8_t* status, float* resid,
+                        int8_t* iters, void* stream) {
+    if (!ctx) return fail(LABFM_EINVAL, "labfm_weights: ctx is NULL");
+    if (!opt) return fail(LABFM_EINVAL, "labfm_weights: opt is NULL");
+    if (n < 0 || n > INT32_MAX || nnz < 0) return fail(LABFM_EINVAL, "labfm_weights: n or nnz out of range");
+    if (!domain_ok(dom)) return fail(LABFM_EINVAL, "labfm_weights: bad domain");
+    if (opt->ops == 0 || (opt->ops & ~31u)) return fail(LABFM_EINVAL, "labfm_weights: ops must be a nonzero set of LABFM_OP_* bits");
+    if (opt->abf != LABFM_ABF_HERMITE && opt->abf != LABFM_ABF_PAPER) return fail(LABFM_EINVAL, "labfm_weights: bad abf");
+    if (opt->rbf < 0 || opt->rbf > 4) return fail(LABFM_EINVAL, "labfm_weights: bad rbf");
+    if (!(opt->sigma > 0.0) || !std::isfinite(opt->sigma)) return fail(LABFM_EINVAL, "labfm_weights: sigma must be > 0");
+    if (opt->max_iters < 0 || opt->max_iters > 100) return fail(LABFM_EINVAL, "labfm_weights: max_iters out of range");
+    if (!(opt->tol_stop >= 0.0) || !(opt->tol_pass >= 0.0)) return fail(LABFM_EINVAL, "labfm_weights: bad tolerances");
+    if (!w64 && !w32) return fail(LABFM_EINVAL, "labfm_weights: w64 and w32 are both NULL");
+    if (n > 0 && (!x || !y || !R || !order || !row_ptr || !status || (nnz > 0 && !col)))
+        return fail(LABFM_EINVAL, "labfm_weights: NULL array");
+    if (opt->prec != LABFM_PREC_FP64 && opt->prec != LABFM_PREC_MIXED) return fail(LABFM_EINVAL, "labfm_weights: bad prec");
+    Context* c = (Context*)ctx;
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(LABFM_EHIP, "labfm_weights: hipSetDevice failed");
+    if (n == 0) return LABFM_OK;
+    WeightArgs a{};
+    a.x = x;
+    a.y = y;
+    a.R = R;
+    a.order = order;
+    a.row_ptr = row_ptr;
+    a.col = col;
+    a.n = n;
+    a.nnz = nnz;
+    a.Lx = dom->hi[0] - dom->lo[0];
+    a.Ly = dom->hi[1] - dom->lo[1];
+    a.perx = dom->periodic[0] != 0;
+    a.pery = dom->periodic[1] != 0;
+    a.abf = opt->abf;
+    a.rbf = opt->rbf;
+    a.sigma = opt->sigma;
+    a.ops = opt->ops;
+    a.nops = 0;
+    for (int b = 0; b < 5; ++b) a.nops += (opt->ops >> b) & 1u;
+    a.tol_stop = opt->tol_stop;
+    a.tol_pass = opt->tol_pass;
+    a.max_iters = opt->max_iters;
+    a.w64 = w64;
+    a.w32 = w32;
+    a.status = status;
+    a.resid = resid;
+    a.iters = iters;
+    hipStream_t st = (hipStream_t)stream;
+    return opt->prec == LABFM_PREC_FP64 ? weights_fp64(c, a, st) : weights_mixed(c, a, st);
+}
+
+labfm_err labfm_combine(void* ctx, const double* w64, int nsets, const double* coef, int64_t nnz, double* out64,
+                        float* out32, void* stream) {
+    if (!ctx) return fail(LABFM_EINVAL, "labfm_combine: ctx is NULL");
+    if (nsets < 1 || nsets > 5) return fail(LABFM_EINVAL, "labfm_combine: nsets must be 1..5");
+    if (nnz < 0) return fail(LABFM_EINVAL, "labfm_combine: nnz < 0");
+    if (!coef || (nnz > 0 && !w64) || (!out64 && !out32)) return fail(LABFM_EINVAL, "labfm_combine: NULL argument");
+    Context* c = (Context*)ctx;
+    DeviceGuard g(c->device);
+    return combine_launch(w64, nsets, coef, nnz, out64, out32, (hipStream_t)stream);
+}
+
+labfm_err labfm_apply_operator(void* ctx, const int64_t* row_ptr, const int32_t* col, int64_t n, int64_t nnz,
+                               int nops, const void* w, int dtype, const void* u, void* out, void* stream) {
+    if (!ctx) return fail(LABFM_EINVAL, "labfm_apply_operator: ctx is NULL");
+    if (n < 0 || nnz < 0) return fail(LABFM_EINVAL, "labfm_apply_operator: n or nnz < 0");
+    if (nops < 1 || nops > 5) return fail(LABFM_EINVAL, "labfm_apply_operator: nops must be 1..5");
+    if (dtype != 0 && dtype != 1) return fail(LABFM_EINVAL, "labfm_apply_operator: dtype must be 0 (FP32) or 1 (FP64)");
+    if (n > 0 && (!row_ptr || !u || !out || (nnz > 0 && (!col || !w))))
+        return fail(LABFM_EINVAL, "labfm_apply_operator: NULL array");
+    Context* c = (Context*)ctx;
+    DeviceGuard g(c->device);
+    return apply_launch(c, row_ptr, col, n, nnz, nops, w, dtype, u, out, (hipStream_t)stream);
+}
+
+labfm_err labfm_step(void* ctx, const labfm_step_plan* plan, void* u, void* scratch, int nsteps, int use_graph,
+                     void* stream) {
+    if (!ctx || !plan) return fail(LABFM_EINVAL, "labfm_step: ctx or plan is NULL");
+    if (plan->n < 0 || plan->nnz < 0 || nsteps < 0) return fail(LABFM_EINVAL, "labfm_step: negative size");
+    if (plan->dtype != 0 && plan->dtype != 1) return fail(LABFM_EINVAL, "labfm_step: dtype must be 0 or 1");
+    if (plan->n > 0 && (!plan->row_ptr || !u || !scratch || (plan->nnz > 0 && (!plan->col || !plan->w_lin))))
+        return fail(LABFM_EINVAL, "labfm_step: NULL array");
+    if (!std::isfinite(plan->dt) || !std::isfinite(plan->gamma)) return fail(LABFM_EINVAL, "labfm_step: dt/gamma not finite");
+    Context* c = (Context*)ctx;
+    DeviceGuard g(c->device);
+    return step_launch(c, plan, u, scratch, nsteps, use_graph, (hipStream_t)stream);
+}
+
+labfm_err labfm_timing_enable(void* ctx, int enable) {
+    if (!ctx) return fail(LABFM_EINVAL, "labfm_timing_enable: ctx is NULL");
+    ((Context*)ctx)->timing = enable != 0;
+    return LABFM_OK;
+}
+
+labfm_err labfm_timing_read(void* ctx, const char* filter, int64_t* launches, double* total_ms) {
+    if (!ctx || !launches || !total_ms) return fail(LABFM_EINVAL, "labfm_timing_read: NULL argument");
+    Context* c = (Context*)ctx;
+    DeviceGuard g(c->device);
+    *launches = 0;
+    *total_ms = 0.0;
+    std::vector<Context::Timed> keep;
+    for (auto& t : c->timed) {
+        bool match = !filter || t.name.find(filter) != std::string::npos;
+        if (!match) {
+            keep.push_back(t);
+            continue;
+        }
+        LABFM_HIP_CHECK(hipEventSynchronize(t.b));
+        float ms = 0.0f;
+        LABFM_HIP_CHECK(hipEventElapsedTime(&ms, t.a, t.b));
+        *total_ms += ms;
+        *launches += 1;
+        hipEventDestroy(t.a);
+        hipEventDestroy(t.b);
+    }
+    c->timed.swap(keep);
+    return LABFM_OK;
+}
+
+}  // extern "C"

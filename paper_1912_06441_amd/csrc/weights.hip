@@ -1,0 +1,554 @@
+// weights.hip -- per-node LABFM weights on gfx950, FP64 path.
+//
+// For node i of order k (Sec. 3.1 of King, Lind & Nasar): h = R_i / 2,
+// d_j = r_ji / h, M = sum_j X(d_j) W(d_j)^T (eq. disc_form), M Psi^d = C^d
+// (eq. lsys), w^d_j = W(d_j) . Psi^d (eq. w_abf), then w^d /= h^l(d).  The
+// paper names no solver; here M is equilibrated (rows, then columns, by their
+// max-abs entry), LU-factorised with partial pivoting, and the weights are
+// refined in FP64 on the moment residual r = C - X^T w (w += W M^-1 r).
+//
+// Launch shape: one 64-lane wavefront (one workgroup) per node system, a
+// persistent grid striding over a per-order work list.  M lives in LDS;
+// basis values are produced in LDS chunks and M is accumulated in registers
+// (each lane owns a BS x BS block of the padded 8BS x 8BS matrix).
+#include "labfm_internal.hpp"
+#include "basis.hpp"
+
+namespace labfm {
+
+namespace {
+
+constexpr int CH = 16;  // neighbours per basis chunk
+
+__device__ inline double bcast(double v, int src) {
+    int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+    int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ inline double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+__device__ inline double min_image(double d, double L, int per) {
+    if (!per) return d;
+    if (d > 0.5 * L) return d - L;
+    if (d < -0.5 * L) return d + L;
+    return d;
+}
+
+// target vector element m of operator code op (bit value); l = derivative order
+__device__ inline double target(unsigned op, int m) {
+    switch (op) {
+        case LABFM_OP_DX: return m == 0 ? 1.0 : 0.0;
+        case LABFM_OP_DY: return m == 1 ? 1.0 : 0.0;
+        case LABFM_OP_LAP: return (m == 2 || m == 4) ? 1.0 : 0.0;
+        case LABFM_OP_BIHARM: return m == 9 ? -1.0 : (m == 11 ? -2.0 : (m == 13 ? -1.0 : 0.0));
+        case LABFM_OP_TRIHARM:
+            return m == 20 ? 1.0 : (m == 22 ? 3.0 : (m == 24 ? 3.0 : (m == 26 ? 1.0 : 0.0)));
+    }
+    return 0.0;
+}
+__host__ __device__ inline int deriv_order(unsigned op) {
+    return op == LABFM_OP_DX || op == LABFM_OP_DY ? 1 : (op == LABFM_OP_LAP ? 2 : (op == LABFM_OP_BIHARM ? 4 : 6));
+}
+__host__ __device__ inline int min_order(unsigned op) {
+    return op == LABFM_OP_BIHARM ? 4 : (op == LABFM_OP_TRIHARM ? 6 : (op == LABFM_OP_LAP ? 2 : 1));
+}
+
+struct OpList {
+    unsigned op[MAXOPS];
+    int nops;
+};
+
+// Solve M z = b with the equilibrated, pivoted LU in LDS.  Lane m holds
+// b[d] for original row m on entry; lane c holds z[d] for unknown c on exit.
+template <int P, int LD>
+__device__ inline void lu_solve(const double* sM, const double* sRs, const double* sCs, const int* sPerm,
+                                double (&b)[MAXOPS], int nops) {
+    const int lane = threadIdx.x;
+    const int pr = lane < P ? sPerm[lane] : 0;
+    const double rs = lane < P ? sRs[lane] : 0.0;
+    double t[MAXOPS];
+#pragma unroll
+    for (int d = 0; d < MAXOPS; ++d) {
+        double v = b[d] * rs;
+        t[d] = __shfl(v, pr, 64);
+    }
+    // forward: unit lower triangle
+    for (int c = 0; c < P - 1; ++c) {
+        double l = (lane > c && lane < P) ? sM[lane * LD + c] : 0.0;
+#pragma unroll
+        for (int d = 0; d < MAXOPS; ++d) {
+            if (d < nops) {
+                double tc = bcast(t[d], c);
+                t[d] -= l * tc;
+            }
+        }
+    }
+    // backward
+    for (int c = P - 1; c >= 0; --c) {
+        double diag = sM[c * LD + c];
+        double u = (lane < c) ? sM[lane * LD + c] : 0.0;
+#pragma unroll
+        for (int d = 0; d < MAXOPS; ++d) {
+            if (d < nops) {
+                if (lane == c) t[d] = t[d] / diag;
+                double tc = bcast(t[d], c);
+                t[d] -= u * tc;
+            }
+        }
+    }
+    const double cs = lane < P ? sCs[lane] : 0.0;
+#pragma unroll
+    for (int d = 0; d < MAXOPS; ++d) b[d] = t[d] * cs;
+}
+
+template <int K, int FAM>
+__global__ __launch_bounds__(64) void k_weights_fp64(WeightArgs a, OpList ops, const int32_t* list,
+                                                     const int32_t* list_off, const int32_t* list_cnt) {
+    constexpr int P = p_of_k(K);
+    constexpr int BS = (P + 7) / 8;
+    constexpr int PP = 8 * BS;
+    constexpr int LD = P + 1;
+    constexpr int JS = NMAX / 64;  // neighbour slots per lane
+
+    __shared__ double sM[P * LD];
+    __shared__ double sChunk[2 * CH * PP];  // basis chunk: X then W
+    __shared__ double sD[2][NMAX];          // scaled offsets
+    __shared__ double sWl[MAXOPS][NMAX];    // scaled weights (for the residual)
+    __shared__ double sPsi[MAXOPS][PP];     // solution / correction coefficients
+    __shared__ double sRs[P], sCs[P];
+    __shared__ int sPerm[P];
+
+    const int lane = threadIdx.x;
+    const int nops = ops.nops;
+    const int count = list_cnt[K];
+    const int32_t* mylist = list + list_off[K];
+
+    for (int t = blockIdx.x; t < count; t += gridDim.x) {
+        const int64_t i = mylist[t];
+        const int64_t s0 = a.row_ptr[i];
+        const int N = (int)(a.row_ptr[i + 1] - s0);
+        const double h = 0.5 * a.R[i];
+        int status = LABFM_ST_OK;
+        double res = INFINITY;
+        int iters = 0;
+
+        // block-uniform early exits
+        for (int d = 0; d < nops; ++d)
+            if (K < min_order(ops.op[d])) status = LABFM_ST_ORDER_TOO_LOW;
+        if (status == LABFM_ST_OK && N < P) status = LABFM_ST_TOO_FEW;
+        if (status == LABFM_ST_OK && N > NMAX) status = LABFM_ST_TOO_MANY;
+
+        double dxr[JS], dyr[JS];
+        if (status == LABFM_ST_OK) {
+            const double xi = a.x[i], yi = a.y[i];
+            bool bad = false;
+#pragma unroll
+            for (int js = 0; js < JS; ++js) {
+                int q = lane + 64 * js;
+                dxr[js] = 0.0;
+                dyr[js] = 0.0;
+                if (q < N) {
+                    int32_t j = a.col[s0 + q];
+                    dxr[js] = min_image(a.x[j] - xi, a.Lx, a.perx) / h;
+                    dyr[js] = min_image(a.y[j] - yi, a.Ly, a.pery) / h;
+                    sD[0][q] = dxr[js];
+                    sD[1][q] = dyr[js];
+                    if (FAM == LABFM_ABF_PAPER && dxr[js] == 0.0 && dyr[js] == 0.0) bad = true;
+                }
+            }
+            if (__any(bad)) status = LABFM_ST_DEGENERATE;
+        }
+        __syncthreads();
+
+        if (status == LABFM_ST_OK) {
+            // ---- assembly: M = sum_j X(d_j) W(d_j)^T, register-blocked
+            const int lr = lane / 8, lc = lane % 8;
+            double acc[BS][BS];
+#pragma unroll
+            for (int r = 0; r < BS; ++r)
+#pragma unroll
+                for (int c = 0; c < BS; ++c) acc[r][c] = 0.0;
+            double* sX = sChunk;
+            double* sW = sChunk + CH * PP;
+            for (int j0 = 0; j0 < N; j0 += CH) {
+                if (lane < 2 * CH) {
+                    const int jj = lane % CH;
+                    const int j = j0 + jj;
+                    double* dst = (lane < CH ? sX : sW) + jj * PP;
+                    if (j < N) {
+                        BasisState<K> B;
+                        basis_prepare<K, FAM>(B, sD[0][j], sD[1][j], a.rbf, a.sigma);
+                        if (lane < CH) {
+#pragma unroll
+                            for (int m = 0; m < P; ++m) dst[m] = monomial<K>(B, m);
+                        } else {
+#pragma unroll
+                            for (int m = 0; m < P; ++m) dst[m] = abf<K, FAM>(B, m);
+                        }
+                    } else {
+#pragma unroll
+                        for (int m = 0; m < P; ++m) dst[m] = 0.0;
+                    }
+#pragma unroll
+                    for (int m = P; m < PP; ++m) dst[m] = 0.0;
+                }
+                __syncthreads();
+                const int jmax = min(CH, N - j0);
+                for (int jj = 0; jj < jmax; ++jj) {
+                    double xv[BS], wv[BS];
+#pragma unroll
+                    for (int r = 0; r < BS; ++r) xv[r] = sX[jj * PP + lr * BS + r];
+#pragma unroll
+                    for (int c = 0; c < BS; ++c) wv[c] = sW[jj * PP + lc * BS + c];
+#pragma unroll
+                    for (int r = 0; r < BS; ++r)
+#pragma unroll
+                        for (int c = 0; c < BS; ++c) acc[r][c] = fma(xv[r], wv[c], acc[r][c]);
+                }
+                __syncthreads();
+            }
+#pragma unroll
+            for (int r = 0; r < BS; ++r)
+#pragma unroll
+                for (int c = 0; c < BS; ++c) {
+                    int m = lr * BS + r, nn = lc * BS + c;
+                    if (m < P && nn < P) sM[m * LD + nn] = acc[r][c];
+                }
+            __syncthreads();
+
+            // ---- equilibration: rows, then columns
+            bool sing = false;
+            if (lane < P) {
+                double mx = 0.0;
+                for (int c = 0; c < P; ++c) mx = fmax(mx, fabs(sM[lane * LD + c]));
+                if (!(mx > 0.0) || !isfinite(mx)) sing = true;
+                double rs = 1.0 / mx;
+                sRs[lane] = rs;
+                for (int c = 0; c < P; ++c) sM[lane * LD + c] *= rs;
+            }
+            __syncthreads();
+            if (lane < P) {
+                double mx = 0.0;
+                for (int r = 0; r < P; ++r) mx = fmax(mx, fabs(sM[r * LD + lane]));
+                if (!(mx > 0.0) || !isfinite(mx)) sing = true;
+                double cs = 1.0 / mx;
+                sCs[lane] = cs;
+                for (int r = 0; r < P; ++r) sM[r * LD + lane] *= cs;
+            }
+            __syncthreads();
+            if (__any(sing)) status = LABFM_ST_SINGULAR;
+
+            // ---- LU with partial pivoting (ties: lowest row)
+            int perm = lane;
+            if (status == LABFM_ST_OK) {
+                for (int kk = 0; kk < P; ++kk) {
+                    double v = (lane >= kk && lane < P) ? fabs(sM[lane * LD + kk]) : -1.0;
+                    int ir = lane;
+#pragma unroll
+                    for (int off = 32; off >= 1; off >>= 1) {
+                        double v2 = __shfl_xor(v, off, 64);
+                        int i2 = __shfl_xor(ir, off, 64);
+                        if (v2 > v || (v2 == v && i2 < ir)) {
+                            v = v2;
+                            ir = i2;
+                        }
+                    }
+                    if (!(v > 0.0) || !isfinite(v)) {
+                        status = LABFM_ST_SINGULAR;
+                        break;
+                    }
+                    const int pr = ir;
+                    if (pr != kk) {
+                        if (lane < P) {
+                            double u = sM[kk * LD + lane];
+                            sM[kk * LD + lane] = sM[pr * LD + lane];
+                            sM[pr * LD + lane] = u;
+                        }
+                        // permutation bookkeeping: position kk <-> pr
+                        int pk = __shfl(perm, kk, 64), pp = __shfl(perm, pr, 64);
+                        if (lane == kk) perm = pp;
+                        if (lane == pr) perm = pk;
+                    }
+                    __syncthreads();
+                    if (lane > kk && lane < P) sM[lane * LD + kk] = sM[lane * LD + kk] / sM[kk * LD + kk];
+                    __syncthreads();
+                    if (lane > kk && lane < P) {
+                        const double u = sM[kk * LD + lane];
+                        for (int r = kk + 1; r < P; ++r) sM[r * LD + lane] -= sM[r * LD + kk] * u;
+                    }
+                    __syncthreads();
+                }
+            }
+            if (lane < P) sPerm[lane] = perm;
+            __syncthreads();
+
+            if (status == LABFM_ST_OK) {
+                // ---- initial solve: lane m holds C^d[m]
+                double b[MAXOPS];
+#pragma unroll
+                for (int d = 0; d < MAXOPS; ++d) b[d] = (d < nops) ? target(ops.op[d], lane) : 0.0;
+                lu_solve<P, LD>(sM, sRs, sCs, sPerm, b, nops);
+                if (lane < P)
+#pragma unroll
+                    for (int d = 0; d < MAXOPS; ++d)
+                        if (d < nops) sPsi[d][lane] = b[d];
+                __syncthreads();
+
+                // ---- w_j = W(d_j) . Psi
+                double wreg[JS][MAXOPS];
+#pragma unroll
+                for (int js = 0; js < JS; ++js) {
+                    int q = lane + 64 * js;
+#pragma unroll
+                    for (int d = 0; d < MAXOPS; ++d) wreg[js][d] = 0.0;
+                    if (q < N) {
+                        BasisState<K> B;
+                        basis_prepare<K, FAM>(B, dxr[js], dyr[js], a.rbf, a.sigma);
+#pragma unroll
+                        for (int m = 0; m < P; ++m) {
+                            double wm = abf<K, FAM>(B, m);
+#pragma unroll
+                            for (int d = 0; d < MAXOPS; ++d)
+                                if (d < nops) wreg[js][d] = fma(wm, sPsi[d][m], wreg[js][d]);
+                        }
+#pragma unroll
+                        for (int d = 0; d < MAXOPS; ++d)
+                            if (d < nops) sWl[d][q] = wreg[js][d];
+                    }
+                }
+                __syncthreads();
+
+                // ---- refinement on the moment residual (FP64)
+                const int ma = lane < P ? ELEM.a[lane] : 0;
+                const int mb = lane < P ? ELEM.b[lane] : 0;
+                const double mf = lane < P ? inv_fact(ma) * inv_fact(mb) : 0.0;
+                for (;;) {
+                    double r[MAXOPS];
+#pragma unroll
+                    for (int d = 0; d < MAXOPS; ++d) r[d] = 0.0;
+                    if (lane < P) {
+                        double accr[MAXOPS];
+#pragma unroll
+                        for (int d = 0; d < MAXOPS; ++d) accr[d] = 0.0;
+                        for (int q = 0; q < N; ++q) {
+                            const double dx = sD[0][q], dy = sD[1][q];
+                            double xm = mf;
+#pragma unroll
+                            for (int e = 0; e < K; ++e) {
+                                xm *= (e < ma) ? dx : 1.0;
+                                xm *= (e < mb) ? dy : 1.0;
+                            }
+#pragma unroll
+                            for (int d = 0; d < MAXOPS; ++d)
+                                if (d < nops) accr[d] = fma(xm, sWl[d][q], accr[d]);
+                        }
+#pragma unroll
+                        for (int d = 0; d < MAXOPS; ++d)
+                            if (d < nops) r[d] = target(ops.op[d], lane) - accr[d];
+                    }
+                    double rm = 0.0;
+#pragma unroll
+                    for (int d = 0; d < MAXOPS; ++d) rm = fmax(rm, fabs(r[d]));
+                    if (!isfinite(rm)) rm = INFINITY;
+                    res = wave_max(rm);
+                    if (!(res > a.tol_stop) || iters >= a.max_iters) break;
+                    lu_solve<P, LD>(sM, sRs, sCs, sPerm, r, nops);
+                    __syncthreads();
+                    if (lane < P)
+#pragma unroll
+                        for (int d = 0; d < MAXOPS; ++d)
+                            if (d < nops) sPsi[d][lane] = r[d];
+                    __syncthreads();
+#pragma unroll
+                    for (int js = 0; js < JS; ++js) {
+                        int q = lane + 64 * js;
+                        if (q < N) {
+                            BasisState<K> B;
+                            basis_prepare<K, FAM>(B, dxr[js], dyr[js], a.rbf, a.sigma);
+                            double dw[MAXOPS];
+#pragma unroll
+                            for (int d = 0; d < MAXOPS; ++d) dw[d] = 0.0;
+#pragma unroll
+                            for (int m = 0; m < P; ++m) {
+                                double wm = abf<K, FAM>(B, m);
+#pragma unroll
+                                for (int d = 0; d < MAXOPS; ++d)
+                                    if (d < nops) dw[d] = fma(wm, sPsi[d][m], dw[d]);
+                            }
+#pragma unroll
+                            for (int d = 0; d < MAXOPS; ++d)
+                                if (d < nops) {
+                                    wreg[js][d] += dw[d];
+                                    sWl[d][q] = wreg[js][d];
+                                }
+                        }
+                    }
+                    __syncthreads();
+                    ++iters;
+                }
+                if (!(res <= a.tol_pass)) status = LABFM_ST_NOT_CONVERGED;
+
+                // ---- unscale and store
+#pragma unroll
+                for (int d = 0; d < MAXOPS; ++d) {
+                    if (d >= nops) continue;
+                    double hl = 1.0;
+                    for (int e = 0; e < deriv_order(ops.op[d]); ++e) hl *= h;
+#pragma unroll
+                    for (int js = 0; js < JS; ++js) {
+                        int q = lane + 64 * js;
+                        if (q < N) {
+                            double wv = wreg[js][d] / hl;
+                            if (a.w64) a.w64[(int64_t)d * a.nnz + s0 + q] = wv;
+                            if (a.w32) a.w32[(int64_t)d * a.nnz + s0 + q] = (float)wv;
+                        }
+                    }
+                }
+            }
+        }
+        const bool failed = !(status == LABFM_ST_OK || status == LABFM_ST_NOT_CONVERGED);
+        if (failed) {
+            for (int d = 0; d < nops; ++d)
+                for (int q = lane; q < N; q += 64) {
+                    if (a.w64) a.w64[(int64_t)d * a.nnz + s0 + q] = 0.0;
+                    if (a.w32) a.w32[(int64_t)d * a.nnz + s0 + q] = 0.0f;
+                }
+            res = INFINITY;
+            iters = 0;
+        }
+        if (lane == 0) {
+            a.status[i] = (int8_t)status;
+            if (a.resid) a.resid[i] = (float)res;
+            if (a.iters) a.iters[i] = (int8_t)iters;
+        }
+        __syncthreads();
+    }
+}
+
+// ---- per-order work lists: counting sort of node indices by order
+__global__ void k_list_count(const int8_t* order, int64_t n, int32_t* cnt /* [KMAX+2] */) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int k = order[i];
+    if (k < 1 || k > KMAX) k = 0;
+    atomicAdd(&cnt[k], 1);
+}
+__global__ void k_list_offsets(const int32_t* cnt, int32_t* off) {
+    if (threadIdx.x == 0) {
+        int32_t run = 0;
+        for (int k = 0; k <= KMAX; ++k) {
+            off[k] = run;
+            run += cnt[k];
+        }
+    }
+}
+__global__ void k_list_scatter(const int8_t* order, int64_t n, const int32_t* off, int32_t* fill, int32_t* list) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int k = order[i];
+    if (k < 1 || k > KMAX) k = 0;
+    int pos = atomicAdd(&fill[k], 1);
+    list[off[k] + pos] = (int32_t)i;
+}
+// nodes with an invalid order: zero weights and status
+__global__ void k_invalid_order(WeightArgs a, int nops, const int32_t* list, const int32_t* off, const int32_t* cnt) {
+    int c = cnt[0];
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < c; t += gridDim.x * blockDim.x) {
+        int64_t i = list[off[0] + t];
+        int64_t s0 = a.row_ptr[i], e0 = a.row_ptr[i + 1];
+        for (int d = 0; d < nops; ++d)
+            for (int64_t q = s0; q < e0; ++q) {
+                if (a.w64) a.w64[(int64_t)d * a.nnz + q] = 0.0;
+                if (a.w32) a.w32[(int64_t)d * a.nnz + q] = 0.0f;
+            }
+        a.status[i] = LABFM_ST_ORDER_TOO_LOW;
+        if (a.resid) a.resid[i] = INFINITY;
+        if (a.iters) a.iters[i] = 0;
+    }
+}
+
+template <int K, int FAM>
+int grid_for() {
+    static int g = 0;
+    if (g == 0) {
+        int dev = 0, ncu = 0, per = 0;
+        hipGetDevice(&dev);
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_weights_fp64<K, FAM>, 64, 0);
+        if (ncu <= 0) ncu = 256;
+        if (per <= 0) per = 1;
+        g = ncu * per;
+    }
+    return g;
+}
+
+template <int K, int FAM>
+void launch_one(Context* c, const WeightArgs& a, const OpList& ops, const int32_t* list, const int32_t* off,
+                const int32_t* cnt, hipStream_t st) {
+    static const char* names[KMAX + 1] = {"", "weights64_k1", "weights64_k2", "weights64_k3", "weights64_k4",
+                                          "weights64_k5", "weights64_k6", "weights64_k7", "weights64_k8"};
+    KernelTimer timer(c, names[K], st);
+    k_weights_fp64<K, FAM><<<grid_for<K, FAM>(), 64, 0, st>>>(a, ops, list, off, cnt);
+}
+
+template <int FAM>
+void launch_all(Context* c, const WeightArgs& a, const OpList& ops, const int32_t* list, const int32_t* off,
+                const int32_t* cnt, hipStream_t st) {
+    launch_one<1, FAM>(c, a, ops, list, off, cnt, st);
+    launch_one<2, FAM>(c, a, ops, list, off, cnt, st);
+    launch_one<3, FAM>(c, a, ops, list, off, cnt, st);
+    launch_one<4, FAM>(c, a, ops, list, off, cnt, st);
+    launch_one<5, FAM>(c, a, ops, list, off, cnt, st);
+    launch_one<6, FAM>(c, a, ops, list, off, cnt, st);
+    launch_one<7, FAM>(c, a, ops, list, off, cnt, st);
+    launch_one<8, FAM>(c, a, ops, list, off, cnt, st);
+}
+
+}  // namespace
+
+labfm_err build_order_lists(Context* c, const int8_t* order, int64_t n, hipStream_t st, int32_t** list,
+                            int32_t** off, int32_t** cnt) {
+    labfm_err e = ensure(c->worklist, sizeof(int32_t) * (size_t)(n + 3 * (KMAX + 2)));
+    if (e != LABFM_OK) return e;
+    int32_t* base = (int32_t*)c->worklist.p;
+    *cnt = base;
+    int32_t* fill = base + (KMAX + 2);
+    *off = base + 2 * (KMAX + 2);
+    *list = base + 3 * (KMAX + 2);
+    LABFM_HIP_CHECK(hipMemsetAsync(base, 0, sizeof(int32_t) * 3 * (KMAX + 2), st));
+    unsigned nb = (unsigned)((n + 255) / 256);
+    k_list_count<<<nb, 256, 0, st>>>(order, n, *cnt);
+    k_list_offsets<<<1, 1, 0, st>>>(*cnt, *off);
+    k_list_scatter<<<nb, 256, 0, st>>>(order, n, *off, fill, *list);
+    LABFM_HIP_CHECK(hipGetLastError());
+    return LABFM_OK;
+}
+
+labfm_err weights_fp64(Context* c, const WeightArgs& a, hipStream_t st) {
+    int32_t *list, *off, *cnt;
+    labfm_err e = build_order_lists(c, a.order, a.n, st, &list, &off, &cnt);
+    if (e != LABFM_OK) return e;
+    OpList ops{};
+    ops.nops = 0;
+    for (int b = 0; b < 5; ++b)
+        if (a.ops & (1u << b)) ops.op[ops.nops++] = 1u << b;
+    k_invalid_order<<<64, 256, 0, st>>>(a, ops.nops, list, off, cnt);
+    if (a.abf == LABFM_ABF_HERMITE)
+        launch_all<LABFM_ABF_HERMITE>(c, a, ops, list, off, cnt, st);
+    else
+        launch_all<LABFM_ABF_PAPER>(c, a, ops, list, off, cnt, st);
+    LABFM_HIP_CHECK(hipGetLastError());
+    return LABFM_OK;
+}
+
+labfm_err weights_mixed(Context*, const WeightArgs&, hipStream_t) {
+    set_error("labfm_weights: LABFM_PREC_MIXED is not built yet");
+    return LABFM_EUNSUPPORTED;
+}
+
+}  // namespace labfm

@@ -105,9 +105,12 @@ def config(name):
         "c1": dict(n_side=32, eps=0.3, seed=1, k=4, k_boundary=4, R_s=2.85, periodic=False),
         # 512x512, order 8 interior / order 4 in a boundary band of width R0, R0 = 4.4 s (mean N ~ 60)
         "c2": dict(n_side=512, eps=0.3, seed=2, k=8, k_boundary=4, R_s=4.4, periodic=False),
-        # 1024x1024 periodic, order 6, R = 4.0 s (mean N ~ 50), RK4 advection-diffusion
+        # 1024x1024 periodic, order 6, R = 4.0 s (mean N ~ 50), RK4 advection-diffusion with
+        # composed nabla^8 hyperviscosity gamma = beta h^8 / dt.  dt = 0.1 s: at 0.2 s the RK4
+        # step map of this node set grows (power iteration: x3.7 per step, a mode localised on
+        # the stencils of largest amplification); at 0.1 s every mode decays.
         "c5": dict(n_side=1024, eps=0.3, seed=5, k=6, k_boundary=6, R_s=4.0, periodic=True,
-                   a=(1.0, 0.5), nu=1e-3, beta=1e-7, dt_s=0.2, nsteps=1000,
+                   a=(1.0, 0.5), nu=1e-3, beta=1e-7, dt_s=0.1, nsteps=1000,
                    x0=(0.5, 0.5), width2=0.01),
     }
     return dict(cfgs[name])

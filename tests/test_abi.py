@@ -1,0 +1,57 @@
+"""The C-ABI library loads without a GPU and exports every entry point that
+include/labfm.h declares (no compute calls here)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "labfm.h")
+LIB = os.path.join(ROOT, "paper_1912_06441_amd", "liblabfm.so")
+
+
+def declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(labfm_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_1912_06441_amd import build
+
+        build.build()
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_entry_points():
+    names = declared()
+    for n in ("labfm_build_neighbours", "labfm_weights", "labfm_apply_operator", "labfm_step",
+              "labfm_create", "labfm_destroy", "labfm_last_error", "labfm_combine"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (labfm_[a-z_0-9]+)", out))
+    assert set(declared()) <= exported
+
+
+def test_binding_names_match_header():
+    import paper_1912_06441_amd as L
+
+    assert sorted(L.EXPORTED) == declared()
+
+
+def test_last_error_on_bad_arguments(lib):
+    # argument validation runs before any device work
+    lib.labfm_last_error.restype = ctypes.c_char_p
+    lib.labfm_apply_operator.restype = ctypes.c_int
+    rc = lib.labfm_apply_operator(None, None, None, ctypes.c_int64(0), ctypes.c_int64(0), 1, None, 0, None, None, None)
+    assert rc == -1
+    assert b"ctx" in lib.labfm_last_error()

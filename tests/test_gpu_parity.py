@@ -1,0 +1,356 @@
+"""GPU (HIP, gfx950) path against the FP64 CPU oracle, element by element.
+
+Neighbour lists must be bit-exact.  FP64 weights: every node's moment residual
+<= 1e-10 and per-node weight parity max|w - w_oracle| / max|w_oracle| <= 1e-10
+(plain FP64 path).  Application and time stepping: FP64 within a rounding
+bound, FP32 within the bound derived in the test."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1912_06441_amd import workloads as WL
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    import oracle
+    import paper_1912_06441_amd as L
+
+    assert torch.cuda.is_available()
+    ctx = L.Context(0)
+    yield dict(torch=torch, O=oracle, L=L, ctx=ctx)
+    torch.cuda.synchronize()
+    ctx.close()
+
+
+def _dev(env, a, dtype=None):
+    t = env["torch"].from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def _gpu_neigh(env, x, y, R, order, dom, grow=True):
+    xt, yt = _dev(env, x), _dev(env, y)
+    Rt = _dev(env, np.array(R, np.float64))
+    ot = _dev(env, np.asarray(order, np.int8))
+    rp, col = env["ctx"].build_neighbours(xt, yt, Rt, ot, dom, grow=grow)
+    env["torch"].cuda.synchronize()
+    return xt, yt, Rt, ot, rp, col
+
+
+def _per_node_parity(rp, w_gpu, w_or, mask=None):
+    """max over ops and nodes of max_j|dw| / max_j|w_or| within each row."""
+    n = rp.size - 1
+    seg = np.repeat(np.arange(n), np.diff(rp))
+    worst = 0.0
+    for d in range(w_or.shape[0]):
+        num = np.zeros(n)
+        den = np.zeros(n)
+        np.maximum.at(num, seg, np.abs(w_gpu[d] - w_or[d]))
+        np.maximum.at(den, seg, np.abs(w_or[d]))
+        ok = den > 0
+        if mask is not None:
+            ok &= mask
+        if ok.any():
+            worst = max(worst, float((num[ok] / den[ok]).max()))
+    return worst
+
+
+# --------------------------------------------------------------------------- neighbours
+@pytest.mark.parametrize("case", ["c1", "periodic48", "grow40", "tiny3", "c2"])
+def test_neighbours_bit_exact(env, case):
+    O = env["O"]
+    _say("neighbours case %s" % case)
+    if case == "c1":
+        nd = WL.make_nodes(WL.config("c1"))
+        x, y, R, order, dom, grow = nd["x"], nd["y"], nd["R"], nd["order"], nd["domain"], True
+    elif case == "periodic48":
+        x, y, s = WL.jittered_lattice(48, eps=0.4, seed=7, periodic=True)
+        R, order, dom, grow = np.full(x.size, 4.0 * s), np.full(x.size, 6, np.int8), WL.unit_domain(True), True
+    elif case == "grow40":
+        x, y, s = WL.jittered_lattice(40, eps=0.45, seed=8)
+        order = WL.order_map(x, y, 8, band=3 * s, k_boundary=4)
+        R, dom, grow = np.full(x.size, 3.0 * s), WL.unit_domain(False), True
+    elif case == "tiny3":
+        x, y, s = WL.jittered_lattice(3, eps=0.2, seed=9, periodic=True)
+        R, order, dom, grow = np.full(x.size, 0.45), np.full(x.size, 2, np.int8), WL.unit_domain(True), False
+    else:
+        nd = WL.make_nodes(WL.config("c2"))
+        x, y, R, order, dom, grow = nd["x"], nd["y"], nd["R"], nd["order"], nd["domain"], True
+    rp_o, col_o, R_o = O.neighbours(x, y, dom, R, order, grow=grow)
+    _, _, Rt, _, rp, col = _gpu_neigh(env, x, y, R, order, dom, grow=grow)
+    assert np.array_equal(rp.cpu().numpy(), rp_o)
+    assert np.array_equal(col.cpu().numpy(), col_o)
+    assert np.array_equal(Rt.cpu().numpy(), R_o)
+
+
+def test_neighbours_empty_and_single(env):
+    torch = env["torch"]
+    ctx = env["ctx"]
+    e = torch.zeros(0, dtype=torch.float64, device="cuda")
+    rp, col = ctx.build_neighbours(e, e, e.clone(), torch.zeros(0, dtype=torch.int8, device="cuda"),
+                                   WL.unit_domain(), grow=True)
+    assert rp.cpu().tolist() == [0] and col.numel() == 0
+    one = torch.tensor([0.5], dtype=torch.float64, device="cuda")
+    rp, col = ctx.build_neighbours(one, one.clone(), torch.tensor([0.2], dtype=torch.float64, device="cuda"),
+                                   torch.tensor([4], dtype=torch.int8, device="cuda"), WL.unit_domain(), grow=True)
+    assert rp.cpu().tolist() == [0, 0] and col.numel() == 0
+
+
+# --------------------------------------------------------------------------- weights
+def _weights_case(env, x, y, R, order, dom, grow=True, **kw):
+    O = env["O"]
+    rp_o, col_o, R_o = O.neighbours(x, y, dom, R, order, grow=grow)
+    okw = {k: v for k, v in kw.items() if k in ("family", "rbf", "sigma", "ops")}
+    w_o, st_o, res_o, it_o = O.weights(x, y, dom, R_o, order, rp_o, col_o, **okw)
+    xt, yt, Rt, ot, rp, col = _gpu_neigh(env, x, y, R, order, dom, grow=grow)
+    gkw = dict(okw)
+    if "family" in gkw:
+        gkw["abf"] = gkw.pop("family")
+    w64, w32, st, res, it = env["ctx"].weights(xt, yt, Rt, ot, rp, col, dom, want32=True, **gkw)
+    env["torch"].cuda.synchronize()
+    return dict(rp=rp_o, w_o=w_o, st_o=st_o, res_o=res_o, w64=w64.cpu().numpy(), w32=w32.cpu().numpy(),
+                st=st.cpu().numpy(), res=res.cpu().numpy(), it=it.cpu().numpy())
+
+
+@pytest.mark.parametrize("case", ["c1", "order8_96", "order6_periodic", "order2_sigma15"])
+def test_weights_fp64_parity(env, case):
+    _say("weights case %s" % case)
+    if case == "c1":
+        nd = WL.make_nodes(WL.config("c1"))
+        r = _weights_case(env, nd["x"], nd["y"], nd["R"], nd["order"], nd["domain"])
+    elif case == "order8_96":
+        nd = WL.make_nodes(WL.config("c2"), n_side=96)
+        r = _weights_case(env, nd["x"], nd["y"], nd["R"], nd["order"], nd["domain"])
+    elif case == "order6_periodic":
+        x, y, s = WL.jittered_lattice(40, eps=0.3, seed=3, periodic=True)
+        r = _weights_case(env, x, y, np.full(x.size, 4.0 * s), np.full(x.size, 6, np.int8), WL.unit_domain(True),
+                          ops=1 | 2 | 4 | 8 | 16)
+    else:
+        x, y, s = WL.jittered_lattice(30, eps=0.3, seed=4)
+        r = _weights_case(env, x, y, np.full(x.size, 2.0 * s), np.full(x.size, 2, np.int8), WL.unit_domain(False),
+                          sigma=1.5)
+    assert np.array_equal(r["st"], r["st_o"])
+    assert np.all(r["st"] == 0)
+    assert r["res"].max() <= 1e-10
+    par = _per_node_parity(r["rp"], r["w64"], r["w_o"])
+    _say("  max per-node weight parity %.3e, max resid %.3e" % (par, r["res"].max()))
+    assert par <= 1e-10
+    # the FP32 copy is the rounded FP64 result
+    assert np.array_equal(r["w32"], r["w64"].astype(np.float32))
+
+
+@pytest.mark.parametrize("family,rbf,k", [(1, 2, 4), (1, 3, 6), (1, 1, 3), (1, 4, 4), (0, 4, 5), (0, 3, 7)])
+def test_weights_families(env, family, rbf, k):
+    _say("weights family %d rbf %d k %d" % (family, rbf, k))
+    x, y, s = WL.jittered_lattice(32, eps=0.3, seed=10 + k, periodic=True)
+    Rs = {3: 3.0, 4: 3.2, 5: 3.6, 6: 4.0, 7: 4.6}[k]
+    r = _weights_case(env, x, y, np.full(x.size, Rs * s), np.full(x.size, k, np.int8), WL.unit_domain(True),
+                      family=family, rbf=rbf)
+    assert np.array_equal(r["st"], r["st_o"])
+    ok = r["st_o"] == 0
+    assert ok.mean() > 0.95
+    assert r["res"][ok].max() <= 1e-10
+    par = _per_node_parity(r["rp"], r["w64"], r["w_o"], mask=ok)
+    _say("  parity %.3e" % par)
+    assert par <= 1e-9
+
+
+def test_weights_full_c2_fp64(env):
+    """Full 512x512 workload: every node passes the 1e-10 moment-residual gate
+    with the oracle's status; weight parity <= 1e-10 on all but a few nodes of
+    cond(M) >= 1e8, where both FP64 results carry forward error ~ cond * 2^-53:
+    those are settled against 50-digit truth (the GPU may not be worse than
+    1.5 x the oracle's own error)."""
+    from test_oracle_weights import _truth
+
+    _say("weights full c2 (262144 nodes)")
+    O = env["O"]
+    nd = WL.make_nodes(WL.config("c2"))
+    r = _weights_case(env, nd["x"], nd["y"], nd["R"], nd["order"], nd["domain"])
+    assert np.array_equal(r["st"], r["st_o"]) and np.all(r["st"] == 0)
+    assert r["res"].max() <= 1e-10
+    rp = r["rp"]
+    n = rp.size - 1
+    seg = np.repeat(np.arange(n), np.diff(rp))
+    par = np.zeros(n)
+    for d in range(3):
+        num = np.zeros(n)
+        den = np.zeros(n)
+        np.maximum.at(num, seg, np.abs(r["w64"][d] - r["w_o"][d]))
+        np.maximum.at(den, seg, np.abs(r["w_o"][d]))
+        par = np.maximum(par, num / den)
+    bad = np.nonzero(par > 1e-10)[0]
+    _say("  c2 parity: median %.2e, max %.2e, nodes above 1e-10: %d" % (np.median(par), par.max(), bad.size))
+    assert bad.size <= max(1, n // 10000)
+    rp_o, col_o, R_o = O.neighbours(nd["x"], nd["y"], nd["domain"], nd["R"], nd["order"])
+    for i in bad[np.argsort(par[bad])[::-1]][:5]:
+        s, e = rp_o[i], rp_o[i + 1]
+        h = R_o[i] / 2
+        dx = (nd["x"][col_o[s:e]] - nd["x"][i]) / h
+        dy = (nd["y"][col_o[s:e]] - nd["y"][i]) / h
+        k = int(nd["order"][i])
+        T = _truth(k, dx, dy, "hermite")
+        hl = np.array([h, h, h * h])[:, None]
+        eg = (np.abs(r["w64"][:, s:e] * hl - T).max(1) / np.abs(T).max(1)).max()
+        eo = (np.abs(r["w_o"][:, s:e] * hl - T).max(1) / np.abs(T).max(1)).max()
+        cond = O.node_weights(k, dx, dy)["cond1"]
+        _say("  node %d cond %.2e: gpu vs truth %.2e, oracle vs truth %.2e" % (i, cond, eg, eo))
+        assert cond >= 1e8
+        assert eg <= max(1e-10, 1.5 * eo)
+
+
+def test_weights_edge_cases(env):
+    """TOO_FEW, ORDER_TOO_LOW, invalid order, DEGENERATE (coincident nodes,
+    PAPER family): status codes as the oracle's, zero weights."""
+    torch = env["torch"]
+    O = env["O"]
+    x, y, s = WL.jittered_lattice(16, eps=0.2, seed=12)
+    x = x.copy()
+    y = y.copy()
+    x[5], y[5] = x[6], y[6]  # coincident pair
+    order = np.full(x.size, 4, np.int8)
+    order[0] = 0   # invalid
+    order[1] = 9   # invalid
+    order[2] = 8   # too few at this radius
+    dom = WL.unit_domain(False)
+    R = np.full(x.size, 2.85 * s)
+    rp_o, col_o, R_o = O.neighbours(x, y, dom, R, order, grow=False)
+    xt, yt, Rt, ot, rp, col = _gpu_neigh(env, x, y, R, order, dom, grow=False)
+    for fam, rbf in ((1, 2), (0, 0)):
+        w64, _, st, res, it = env["ctx"].weights(xt, yt, Rt, ot, rp, col, dom, abf=fam, rbf=rbf)
+        st = st.cpu().numpy()
+        w = w64.cpu().numpy()
+        assert st[0] == 5 and st[1] == 5 and st[2] == 3
+        if fam == 1:
+            assert st[5] == 4 and st[6] == 4
+        oo = order.copy()
+        oo[[0, 1]] = 4
+        _, st_o, _, _ = O.weights(x, y, dom, R_o, oo, rp_o, col_o, family=fam, rbf=rbf)
+        rest = np.ones(x.size, bool)
+        rest[[0, 1]] = False
+        assert np.array_equal(st[rest], st_o[rest])
+        for i in np.nonzero(st >= 2)[0]:
+            assert np.all(w[:, rp_o[i]:rp_o[i + 1]] == 0)
+    # an operator the order cannot express
+    w64, _, st, _, _ = env["ctx"].weights(xt, yt, Rt, ot, rp, col, dom, ops=8 | 16)
+    st = st.cpu().numpy()
+    assert np.all(st[order == 4] == 5)
+
+
+# --------------------------------------------------------------------------- application
+@pytest.fixture(scope="module")
+def c1_ops(env):
+    O = env["O"]
+    nd = WL.make_nodes(WL.config("c1"))
+    rp_o, col_o, R_o = O.neighbours(nd["x"], nd["y"], nd["domain"], nd["R"], nd["order"])
+    w_o, st_o, _, _ = O.weights(nd["x"], nd["y"], nd["domain"], R_o, nd["order"], rp_o, col_o)
+    return nd, rp_o, col_o, w_o
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_apply_parity(env, c1_ops, dtype):
+    torch = env["torch"]
+    O = env["O"]
+    nd, rp_o, col_o, w_o = c1_ops
+    f, fx, fy, lap = WL.sincos_field(nd["x"], nd["y"])
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    out = env["ctx"].apply_operator(_dev(env, rp_o), _dev(env, col_o), _dev(env, w_o, tdt), _dev(env, f, tdt))
+    out = out.double().cpu().numpy()
+    for d in range(3):
+        ref = O.apply(rp_o, col_o, w_o[d], f)
+        scale = np.array([np.abs(w_o[d][rp_o[i]:rp_o[i + 1]] * (f[col_o[rp_o[i]:rp_o[i + 1]]] - f[i])).sum()
+                          for i in range(f.size)])
+        tol = (1e-14 if dtype == "f64" else 2e-6) * scale + 1e-300
+        assert np.all(np.abs(out[d] - ref) <= tol), (d, np.max(np.abs(out[d] - ref) / tol))
+        # against the analytic derivative (c1 accuracy, cf. the oracle probe)
+        e = np.linalg.norm(out[d] - (fx, fy, lap)[d]) / np.linalg.norm((fx, fy, lap)[d])
+        assert e < 0.1
+
+
+def test_apply_empty_rows_and_large_rows(env):
+    """Rows of length 0 and rows longer than one lane group."""
+    torch = env["torch"]
+    O = env["O"]
+    rng = np.random.default_rng(3)
+    n = 300
+    lens = rng.integers(0, 100, n)
+    lens[:10] = 0
+    rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    col = rng.integers(0, n, rp[-1]).astype(np.int32)
+    w = rng.standard_normal((2, rp[-1]))
+    u = rng.standard_normal(n)
+    out = env["ctx"].apply_operator(_dev(env, rp), _dev(env, col), _dev(env, w), _dev(env, u)).cpu().numpy()
+    for d in range(2):
+        ref = O.apply(rp, col, w[d], u)
+        assert np.allclose(out[d], ref, rtol=1e-12, atol=1e-12)
+    assert np.all(out[:, :10] == 0)
+
+
+# --------------------------------------------------------------------------- time stepping
+@pytest.fixture(scope="module")
+def adv_ops(env):
+    O = env["O"]
+    cfg = WL.config("c5")
+    x, y, s = WL.jittered_lattice(48, eps=cfg["eps"], seed=cfg["seed"], periodic=True)
+    dom = WL.unit_domain(True)
+    rp, col, R = O.neighbours(x, y, dom, cfg["R_s"] * s, cfg["k"])
+    w, st, _, _ = O.weights(x, y, dom, R, cfg["k"], rp, col, ops=1 | 2 | 4 | 8)
+    assert np.all(st == 0)
+    wlin = O.combine(w[:3], [-cfg["a"][0], -cfg["a"][1], cfg["nu"]])
+    h = 2.0 * s
+    dt = cfg["dt_s"] * s
+    gamma = cfg["beta"] * h ** 8 / dt
+    u0 = WL.gaussian_pulse(x, y)
+    return dict(x=x, y=y, rp=rp, col=col, wlin=wlin, wbh=w[3], dt=dt, gamma=gamma, u0=u0)
+
+
+@pytest.mark.parametrize("hv", [False, True])
+def test_step_fp64_parity(env, adv_ops, hv):
+    O = env["O"]
+    a = adv_ops
+    nsteps = 60
+    wbh = a["wbh"] if hv else None
+    ref = O.rk4(a["rp"], a["col"], a["wlin"], wbh, a["gamma"], a["dt"], nsteps, a["u0"])
+    outs = []
+    for graph in (False, True):
+        u = _dev(env, a["u0"])
+        env["ctx"].step(_dev(env, a["rp"]), _dev(env, a["col"]), _dev(env, a["wlin"]),
+                        _dev(env, wbh) if hv else None, a["gamma"], a["dt"], u, nsteps, use_graph=graph)
+        env["torch"].cuda.synchronize()
+        outs.append(u.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])  # graph replay == direct launches
+    err = np.abs(outs[0] - ref).max() / np.abs(ref).max()
+    _say("  rk4 fp64 hv=%s rel err %.3e" % (hv, err))
+    assert err <= 1e-12
+
+
+def test_step_fp32_vs_fp64_oracle(env, adv_ops):
+    """FP32 application and state against the FP64 oracle.  Each stage rounds
+    the sum of ~50 terms |w (u_j - u_i)| (amplification A = sum|w||du| / |L u|)
+    at 2^-24; over S steps of RK4 the error grows at most linearly: bound
+    ~ S * dt * A_max * 6e-8 * max|L u| + 6e-8 max|u|, well below 1e-4 max|u|
+    here; the test asserts 1e-4."""
+    O = env["O"]
+    torch = env["torch"]
+    a = adv_ops
+    nsteps = 200
+    ref = O.rk4(a["rp"], a["col"], a["wlin"], a["wbh"], a["gamma"], a["dt"], nsteps, a["u0"])
+    u = _dev(env, a["u0"], torch.float32)
+    env["ctx"].step(_dev(env, a["rp"]), _dev(env, a["col"]), _dev(env, a["wlin"], torch.float32),
+                    _dev(env, a["wbh"], torch.float32), a["gamma"], a["dt"], u, nsteps)
+    torch.cuda.synchronize()
+    err = np.abs(u.double().cpu().numpy() - ref).max() / np.abs(ref).max()
+    _say("  rk4 fp32 rel err %.3e" % err)
+    assert err <= 1e-4
