@@ -28,6 +28,27 @@ PEAK_FP32_MFMA = 157.3e12
 PEAK_HBM = 8.0e12        # bytes/s
 
 
+def measured_traffic(kernel, sources):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None if the kernel's sources changed since it was taken."""
+    import glob
+    import hashlib
+
+    h = hashlib.sha256()
+    for src in sources:
+        with open(os.path.join(ROOT, "paper_1912_06441_amd", "csrc", src), "rb") as fh:
+            h.update(fh.read())
+    digest = h.hexdigest()[:16]
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        with open(path) as fh:
+            for line in fh:
+                parts = line.split()
+                if len(parts) == 4 and parts[0] == "TRAFFIC" and parts[1] == kernel:
+                    if parts[2] == "src=" + digest:
+                        return float(parts[3].split("=")[1])
+    return None
+
+
 def weight_flops(N, p, nd, iters):
     """Algorithmic FP64 flops of one weight set: assembly 2Np^2, LU 2p^3/3,
     (1 + it) x [solve 2 nd p^2 + weights 2 N p nd + residual 2 N p nd]."""
@@ -61,7 +82,19 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-rk4", action="store_true")
     ap.add_argument("--rk4-steps", type=int, default=200)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 1 GiB device to device 4 times (counter calibration) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": src.numel() * 8, "launches": 4}))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only (the method's kernels run on one device); "
               "--gpus %d is not supported" % args.gpus, file=sys.stderr)
@@ -162,8 +195,13 @@ def main():
         "operator_apps": {"value": n / (ka_ms / 1e3), "unit": "nodes/s (3 fused FP64 operators)",
                           "GB_per_s": apply_bytes / (ka_ms / 1e3) / 1e9},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64, "traffic": None, "kernel": "weights64_k8",
-                     "flops_per_launch": flops8},
+                     "frac": achieved / PEAK_FP64,
+                     "traffic": measured_traffic("weights64_k8", ["weights.hip", "basis.hpp"]),
+                     "kernel": "weights64_k8", "flops_per_launch": flops8},
+        "roofline_apply": {"bound": "hbm", "achieved": apply_bytes / (ka_ms / 1e3) / 1e9, "peak": PEAK_HBM / 1e9,
+                           "unit": "GB/s", "frac": apply_bytes / (ka_ms / 1e3) / PEAK_HBM,
+                           "traffic": measured_traffic("apply_f64", ["apply.hip"]), "kernel": "apply_f64",
+                           "bytes_per_launch": apply_bytes},
     }
 
     if not args.no_rk4:

@@ -430,13 +430,21 @@ __global__ __launch_bounds__(64) void k_weights_fp64(WeightArgs a, OpList ops, c
     }
 }
 
-// ---- per-order work lists: counting sort of node indices by order
-__global__ void k_list_count(const int8_t* order, int64_t n, int32_t* cnt /* [KMAX+2] */) {
+// ---- per-order work lists: counting sort of node indices by order, with a
+// workgroup-level histogram in LDS so that each workgroup issues one global
+// atomic per order class.
+__global__ __launch_bounds__(256) void k_list_count(const int8_t* order, int64_t n, int32_t* cnt /* [KMAX+2] */) {
+    __shared__ int32_t h[KMAX + 1];
+    if (threadIdx.x <= KMAX) h[threadIdx.x] = 0;
+    __syncthreads();
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int k = order[i];
-    if (k < 1 || k > KMAX) k = 0;
-    atomicAdd(&cnt[k], 1);
+    if (i < n) {
+        int k = order[i];
+        if (k < 1 || k > KMAX) k = 0;
+        atomicAdd(&h[k], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x <= KMAX && h[threadIdx.x]) atomicAdd(&cnt[threadIdx.x], h[threadIdx.x]);
 }
 __global__ void k_list_offsets(const int32_t* cnt, int32_t* off) {
     if (threadIdx.x == 0) {
@@ -447,13 +455,22 @@ __global__ void k_list_offsets(const int32_t* cnt, int32_t* off) {
         }
     }
 }
-__global__ void k_list_scatter(const int8_t* order, int64_t n, const int32_t* off, int32_t* fill, int32_t* list) {
+__global__ __launch_bounds__(256) void k_list_scatter(const int8_t* order, int64_t n, const int32_t* off,
+                                                      int32_t* fill, int32_t* list) {
+    __shared__ int32_t h[KMAX + 1], base[KMAX + 1];
+    if (threadIdx.x <= KMAX) h[threadIdx.x] = 0;
+    __syncthreads();
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int k = order[i];
-    if (k < 1 || k > KMAX) k = 0;
-    int pos = atomicAdd(&fill[k], 1);
-    list[off[k] + pos] = (int32_t)i;
+    int k = 0, pos = 0;
+    if (i < n) {
+        k = order[i];
+        if (k < 1 || k > KMAX) k = 0;
+        pos = atomicAdd(&h[k], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x <= KMAX) base[threadIdx.x] = h[threadIdx.x] ? atomicAdd(&fill[threadIdx.x], h[threadIdx.x]) : 0;
+    __syncthreads();
+    if (i < n) list[off[k] + base[k] + pos] = (int32_t)i;
 }
 // nodes with an invalid order: zero weights and status
 __global__ void k_invalid_order(WeightArgs a, int nops, const int32_t* list, const int32_t* off, const int32_t* cnt) {
