@@ -204,6 +204,10 @@ def main():
                            "bytes_per_launch": apply_bytes},
     }
 
+    # the other precision on the same workload, for comparison at the same accuracy gate
+    other = L.PREC_MIXED if prec == L.PREC_FP64 else L.PREC_FP64
+    rec["compare"] = compare_precision(ctx, torch, np, L, x, y, R0, order, nd, other, bufs, args.steps)
+
     if not args.no_rk4:
         rec["rk4_c5"] = run_rk4(ctx, torch, np, L, WL, args.rk4_steps)
 
@@ -211,6 +215,30 @@ def main():
         rec["cpu_baseline"] = run_cpu_baseline(nd, cfg)
     ctx.close()
     print(json.dumps(rec), flush=True)
+
+
+def compare_precision(ctx, torch, np, L, x, y, R0, order, nd, prec, bufs, reps):
+    """Weights-only timing of the other precision mode on the same workload."""
+    R = R0.clone()
+    rp, col = ctx.build_neighbours(x, y, R, order, nd["domain"])
+    ctx.weights(x, y, R, order, rp, col, nd["domain"], prec=prec, out=bufs)
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    for _ in range(reps):
+        ctx.weights(x, y, R, order, rp, col, nd["domain"], prec=prec, out=bufs)
+    torch.cuda.synchronize()
+    ctx.timing(False)
+    kw = ctx.timing_read("weights")
+    ctx.timing_read(None)
+    st = bufs[2].cpu().numpy()
+    it = bufs[4].cpu().numpy()
+    res = bufs[3].cpu().numpy()
+    good8 = int(((st == 0) & (nd["order"] == 8)).sum())
+    ms = kw[1] / reps
+    return {"prec": "fp64" if prec == L.PREC_FP64 else "mixed", "weights_ms": ms,
+            "weight_sets_per_s_order8": good8 / (ms / 1e3), "nodes_passing_1e-10": int((st == 0).sum()),
+            "max_moment_residual": float(res.max()), "fp64_fallback_nodes": int((it >= 64).sum()),
+            "mean_refinement_iters": float(it[it < 64].mean())}
 
 
 def run_rk4(ctx, torch, np, L, WL, nsteps):

@@ -143,7 +143,9 @@ labfm_err labfm_build_neighbours(void* ctx, const double* x, const double* y, in
  * Outputs (device): w64 [nops][nnz] FP64 and/or w32 [nops][nnz] FP32 (either
  * may be NULL, not both); status int8 [n]; resid FP32 [n] (final
  * max-norm moment residual over the operators); iters int8 [n] (FP64
- * refinement updates).  Failed nodes get zero weights.  Asynchronous. */
+ * refinement updates; on the MIXED path at most 30, and 64 + the FP64
+ * path's count for nodes the mixed path handed to the FP64 path).  Failed
+ * nodes get zero weights.  Asynchronous. */
 labfm_err labfm_weights(void* ctx, const double* x, const double* y, int64_t n,
                         const labfm_domain* dom, const double* R, const int8_t* order,
                         const int64_t* row_ptr, const int32_t* col, int64_t nnz,

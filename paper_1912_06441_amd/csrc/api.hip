@@ -185,6 +185,8 @@ labfm_err labfm_weights(void* ctx, const double* x, const double* y, int64_t n, 
     a.tol_stop = opt->tol_stop;
     a.tol_pass = opt->tol_pass;
     a.max_iters = opt->max_iters;
+    a.iters_offset = 0;
+    a.max_iters32 = 30;
     a.w64 = w64;
     a.w32 = w32;
     a.status = status;

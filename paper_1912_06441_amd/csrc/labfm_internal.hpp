@@ -67,11 +67,11 @@ struct KernelTimer {
             a = b = nullptr;
             return;
         }
-        hipEventRecord(a, st);
+        (void)hipEventRecord(a, st);
     }
     ~KernelTimer() {
         if (!a) return;
-        hipEventRecord(b, st);
+        (void)hipEventRecord(b, st);
         c->timed.push_back({name, a, b});
     }
 };
@@ -118,8 +118,17 @@ struct WeightArgs {
     int8_t* status;
     float* resid;
     int8_t* iters;
+    int iters_offset;  // added to iters (marks nodes recomputed on the FP64 path)
+    int max_iters32;   // refinement updates allowed on the mixed path
 };
 labfm_err weights_fp64(Context* c, const WeightArgs& a, hipStream_t st);
+labfm_err build_order_lists(Context* c, const int8_t* order, int64_t n, hipStream_t st, int32_t** list,
+                            int32_t** off, int32_t** cnt);
+labfm_err weights_invalid_orders(const WeightArgs& a, const int32_t* list, const int32_t* off, const int32_t* cnt,
+                                 hipStream_t st);
+// FP64 kernels over given per-order lists (segment K at list + off[K], cnt[K] entries)
+labfm_err weights_fp64_lists(Context* c, const WeightArgs& a, const int32_t* list, const int32_t* off,
+                             const int32_t* cnt, hipStream_t st);
 labfm_err weights_mixed(Context* c, const WeightArgs& a, hipStream_t st);
 
 // ---- application and time stepping

@@ -11,100 +11,12 @@
 // persistent grid striding over a per-order work list.  M lives in LDS;
 // basis values are produced in LDS chunks and M is accumulated in registers
 // (each lane owns a BS x BS block of the padded 8BS x 8BS matrix).
-#include "labfm_internal.hpp"
-#include "basis.hpp"
+#include "weights_common.hpp"
 
 namespace labfm {
 
 namespace {
-
-constexpr int CH = 16;  // neighbours per basis chunk
-
-__device__ inline double bcast(double v, int src) {
-    int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
-    int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
-    return __hiloint2double(hi, lo);
-}
-
-__device__ inline double wave_max(double v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-    return v;
-}
-
-__device__ inline double min_image(double d, double L, int per) {
-    if (!per) return d;
-    if (d > 0.5 * L) return d - L;
-    if (d < -0.5 * L) return d + L;
-    return d;
-}
-
-// target vector element m of operator code op (bit value); l = derivative order
-__device__ inline double target(unsigned op, int m) {
-    switch (op) {
-        case LABFM_OP_DX: return m == 0 ? 1.0 : 0.0;
-        case LABFM_OP_DY: return m == 1 ? 1.0 : 0.0;
-        case LABFM_OP_LAP: return (m == 2 || m == 4) ? 1.0 : 0.0;
-        case LABFM_OP_BIHARM: return m == 9 ? -1.0 : (m == 11 ? -2.0 : (m == 13 ? -1.0 : 0.0));
-        case LABFM_OP_TRIHARM:
-            return m == 20 ? 1.0 : (m == 22 ? 3.0 : (m == 24 ? 3.0 : (m == 26 ? 1.0 : 0.0)));
-    }
-    return 0.0;
-}
-__host__ __device__ inline int deriv_order(unsigned op) {
-    return op == LABFM_OP_DX || op == LABFM_OP_DY ? 1 : (op == LABFM_OP_LAP ? 2 : (op == LABFM_OP_BIHARM ? 4 : 6));
-}
-__host__ __device__ inline int min_order(unsigned op) {
-    return op == LABFM_OP_BIHARM ? 4 : (op == LABFM_OP_TRIHARM ? 6 : (op == LABFM_OP_LAP ? 2 : 1));
-}
-
-struct OpList {
-    unsigned op[MAXOPS];
-    int nops;
-};
-
-// Solve M z = b with the equilibrated, pivoted LU in LDS.  Lane m holds
-// b[d] for original row m on entry; lane c holds z[d] for unknown c on exit.
-template <int P, int LD>
-__device__ inline void lu_solve(const double* sM, const double* sRs, const double* sCs, const int* sPerm,
-                                double (&b)[MAXOPS], int nops) {
-    const int lane = threadIdx.x;
-    const int pr = lane < P ? sPerm[lane] : 0;
-    const double rs = lane < P ? sRs[lane] : 0.0;
-    double t[MAXOPS];
-#pragma unroll
-    for (int d = 0; d < MAXOPS; ++d) {
-        double v = b[d] * rs;
-        t[d] = __shfl(v, pr, 64);
-    }
-    // forward: unit lower triangle
-    for (int c = 0; c < P - 1; ++c) {
-        double l = (lane > c && lane < P) ? sM[lane * LD + c] : 0.0;
-#pragma unroll
-        for (int d = 0; d < MAXOPS; ++d) {
-            if (d < nops) {
-                double tc = bcast(t[d], c);
-                t[d] -= l * tc;
-            }
-        }
-    }
-    // backward
-    for (int c = P - 1; c >= 0; --c) {
-        double diag = sM[c * LD + c];
-        double u = (lane < c) ? sM[lane * LD + c] : 0.0;
-#pragma unroll
-        for (int d = 0; d < MAXOPS; ++d) {
-            if (d < nops) {
-                if (lane == c) t[d] = t[d] / diag;
-                double tc = bcast(t[d], c);
-                t[d] -= u * tc;
-            }
-        }
-    }
-    const double cs = lane < P ? sCs[lane] : 0.0;
-#pragma unroll
-    for (int d = 0; d < MAXOPS; ++d) b[d] = t[d] * cs;
-}
+using namespace wk;
 
 template <int K, int FAM>
 __global__ __launch_bounds__(64) void k_weights_fp64(WeightArgs a, OpList ops, const int32_t* list,
@@ -278,8 +190,20 @@ __global__ __launch_bounds__(64) void k_weights_fp64(WeightArgs a, OpList ops, c
                     if (lane > kk && lane < P) sM[lane * LD + kk] = sM[lane * LD + kk] / sM[kk * LD + kk];
                     __syncthreads();
                     if (lane > kk && lane < P) {
+                        // rows in groups of four: all loads issued before the stores
                         const double u = sM[kk * LD + lane];
-                        for (int r = kk + 1; r < P; ++r) sM[r * LD + lane] -= sM[r * LD + kk] * u;
+                        int r = kk + 1;
+                        for (; r + 4 <= P; r += 4) {
+                            const double l0 = sM[r * LD + kk], l1 = sM[(r + 1) * LD + kk];
+                            const double l2 = sM[(r + 2) * LD + kk], l3 = sM[(r + 3) * LD + kk];
+                            const double a0 = sM[r * LD + lane], a1 = sM[(r + 1) * LD + lane];
+                            const double a2 = sM[(r + 2) * LD + lane], a3 = sM[(r + 3) * LD + lane];
+                            sM[r * LD + lane] = fma(-l0, u, a0);
+                            sM[(r + 1) * LD + lane] = fma(-l1, u, a1);
+                            sM[(r + 2) * LD + lane] = fma(-l2, u, a2);
+                            sM[(r + 3) * LD + lane] = fma(-l3, u, a3);
+                        }
+                        for (; r < P; ++r) sM[r * LD + lane] = fma(-sM[r * LD + kk], u, sM[r * LD + lane]);
                     }
                     __syncthreads();
                 }
@@ -424,7 +348,7 @@ __global__ __launch_bounds__(64) void k_weights_fp64(WeightArgs a, OpList ops, c
         if (lane == 0) {
             a.status[i] = (int8_t)status;
             if (a.resid) a.resid[i] = (float)res;
-            if (a.iters) a.iters[i] = (int8_t)iters;
+            if (a.iters) a.iters[i] = (int8_t)(iters + a.iters_offset);
         }
         __syncthreads();
     }
@@ -494,9 +418,9 @@ int grid_for() {
     static int g = 0;
     if (g == 0) {
         int dev = 0, ncu = 0, per = 0;
-        hipGetDevice(&dev);
-        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_weights_fp64<K, FAM>, 64, 0);
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_weights_fp64<K, FAM>, 64, 0);
         if (ncu <= 0) ncu = 256;
         if (per <= 0) per = 1;
         g = ncu * per;
@@ -546,15 +470,12 @@ labfm_err build_order_lists(Context* c, const int8_t* order, int64_t n, hipStrea
     return LABFM_OK;
 }
 
-labfm_err weights_fp64(Context* c, const WeightArgs& a, hipStream_t st) {
-    int32_t *list, *off, *cnt;
-    labfm_err e = build_order_lists(c, a.order, a.n, st, &list, &off, &cnt);
-    if (e != LABFM_OK) return e;
-    OpList ops{};
+labfm_err weights_fp64_lists(Context* c, const WeightArgs& a, const int32_t* list, const int32_t* off,
+                             const int32_t* cnt, hipStream_t st) {
+    OpList ops{};  // unused slots stay 0: a zero target
     ops.nops = 0;
     for (int b = 0; b < 5; ++b)
         if (a.ops & (1u << b)) ops.op[ops.nops++] = 1u << b;
-    k_invalid_order<<<64, 256, 0, st>>>(a, ops.nops, list, off, cnt);
     if (a.abf == LABFM_ABF_HERMITE)
         launch_all<LABFM_ABF_HERMITE>(c, a, ops, list, off, cnt, st);
     else
@@ -563,9 +484,25 @@ labfm_err weights_fp64(Context* c, const WeightArgs& a, hipStream_t st) {
     return LABFM_OK;
 }
 
-labfm_err weights_mixed(Context*, const WeightArgs&, hipStream_t) {
-    set_error("labfm_weights: LABFM_PREC_MIXED is not built yet");
-    return LABFM_EUNSUPPORTED;
+labfm_err weights_invalid_orders(const WeightArgs& a, const int32_t* list, const int32_t* off, const int32_t* cnt,
+                                 hipStream_t st) {
+    int nops = 0;
+    for (int b = 0; b < 5; ++b) nops += (a.ops >> b) & 1u;
+    k_invalid_order<<<64, 256, 0, st>>>(a, nops, list, off, cnt);
+    LABFM_HIP_CHECK(hipGetLastError());
+    return LABFM_OK;
 }
+
+labfm_err weights_fp64(Context* c, const WeightArgs& a, hipStream_t st) {
+    int32_t *list, *off, *cnt;
+    labfm_err e = build_order_lists(c, a.order, a.n, st, &list, &off, &cnt);
+    if (e != LABFM_OK) return e;
+    int nops = 0;
+    for (int b = 0; b < 5; ++b) nops += (a.ops >> b) & 1u;
+    k_invalid_order<<<64, 256, 0, st>>>(a, nops, list, off, cnt);
+    return weights_fp64_lists(c, a, list, off, cnt, st);
+}
+
+
 
 }  // namespace labfm

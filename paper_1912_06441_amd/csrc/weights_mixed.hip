@@ -1,0 +1,436 @@
+// weights_mixed.hip -- per-node LABFM weights, mixed precision.
+//
+// Same system as the FP64 path (Sec. 3.1 of King, Lind & Nasar: M = sum_j
+// X(d_j) W(d_j)^T, M Psi = C, w = W Psi), with the work split by precision:
+//   * basis values rounded to FP32 and M assembled on the matrix cores
+//     (v_mfma_f32_16x16x4f32, FP32 accumulation),
+//   * FP32 equilibration and LU with partial pivoting in LDS,
+//   * FP64 weights w = W Psi, FP64 moment residual r = C - X^T w and FP64
+//     weight refinement w += W (M32^-1 r) until ||r|| <= tol_stop.
+// Nodes whose refinement does not reach tol_pass are appended to a per-order
+// retry list and recomputed by the FP64 kernels.
+//
+// Launch shape: one 64-lane wavefront per node system, persistent over the
+// per-order work list.  M tiles: lane l of the 16x16x4 MFMA holds A[l%16][l/16]
+// and B[l/16][l%16]; the 16x16 result lane l, register i is row 4(l/16)+i,
+// column l%16.
+#include "weights_common.hpp"
+
+namespace labfm {
+
+namespace {
+using namespace wk;
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int CHM = 16;  // neighbours per basis chunk (four MFMA k-steps)
+
+template <int K, int FAM>
+__global__ __launch_bounds__(64) void k_weights_mixed(WeightArgs a, OpList ops, const int32_t* list,
+                                                      const int32_t* list_off, const int32_t* list_cnt,
+                                                      int32_t* retry_list, int32_t* retry_cnt) {
+    constexpr int P = p_of_k(K);
+    constexpr int T = (P + 15) / 16;  // MFMA tiles per dimension
+    constexpr int PP = 16 * T;
+    constexpr int LD = P + 1;
+    constexpr int JS = NMAX / 64;
+
+    __shared__ float sM[cmax(P * LD, 2 * CHM * PP)];  // M / LU factors, aliased with the FP32 basis chunk
+    __shared__ double sD[2][NMAX];
+    __shared__ double sWl[MAXOPS][NMAX];
+    __shared__ double sPsi[MAXOPS][PP];
+    __shared__ float sRs[P], sCs[P];
+    __shared__ int sPerm[P];
+
+    const int lane = threadIdx.x;
+    const int nops = ops.nops;
+    const int count = list_cnt[K];
+    const int32_t* mylist = list + list_off[K];
+
+    for (int t = blockIdx.x; t < count; t += gridDim.x) {
+        const int64_t i = mylist[t];
+        const int64_t s0 = a.row_ptr[i];
+        const int N = (int)(a.row_ptr[i + 1] - s0);
+        const double h = 0.5 * a.R[i];
+        int status = LABFM_ST_OK;
+        double res = INFINITY;
+        int iters = 0;
+
+        for (int d = 0; d < nops; ++d)
+            if (K < min_order(ops.op[d])) status = LABFM_ST_ORDER_TOO_LOW;
+        if (status == LABFM_ST_OK && N < P) status = LABFM_ST_TOO_FEW;
+        if (status == LABFM_ST_OK && N > NMAX) status = LABFM_ST_TOO_MANY;
+
+        double dxr[JS], dyr[JS];
+        if (status == LABFM_ST_OK) {
+            const double xi = a.x[i], yi = a.y[i];
+            bool bad = false;
+#pragma unroll
+            for (int js = 0; js < JS; ++js) {
+                const int q = lane + 64 * js;
+                dxr[js] = 0.0;
+                dyr[js] = 0.0;
+                if (q < N) {
+                    const int32_t j = a.col[s0 + q];
+                    dxr[js] = min_image(a.x[j] - xi, a.Lx, a.perx) / h;
+                    dyr[js] = min_image(a.y[j] - yi, a.Ly, a.pery) / h;
+                    sD[0][q] = dxr[js];
+                    sD[1][q] = dyr[js];
+                    if (FAM == LABFM_ABF_PAPER && dxr[js] == 0.0 && dyr[js] == 0.0) bad = true;
+                }
+            }
+            if (__any(bad)) status = LABFM_ST_DEGENERATE;
+        }
+        __syncthreads();
+
+        if (status == LABFM_ST_OK) {
+            // ---- assembly on the matrix cores: M = X^T W, K-dimension = neighbours
+            floatx4 acc[T][T];
+#pragma unroll
+            for (int ti = 0; ti < T; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < T; ++tj) acc[ti][tj] = floatx4{0.f, 0.f, 0.f, 0.f};
+            float* sX = sM;
+            float* sW = sM + CHM * PP;
+            for (int j0 = 0; j0 < N; j0 += CHM) {
+                if (lane < 2 * CHM) {
+                    const int jj = lane % CHM;
+                    const int j = j0 + jj;
+                    float* dst = (lane < CHM ? sX : sW) + jj * PP;
+                    if (j < N) {
+                        BasisState<K> B;
+                        basis_prepare<K, FAM>(B, sD[0][j], sD[1][j], a.rbf, a.sigma);
+                        if (lane < CHM) {
+#pragma unroll
+                            for (int m = 0; m < P; ++m) dst[m] = (float)monomial<K>(B, m);
+                        } else {
+#pragma unroll
+                            for (int m = 0; m < P; ++m) dst[m] = (float)abf<K, FAM>(B, m);
+                        }
+                    } else {
+#pragma unroll
+                        for (int m = 0; m < P; ++m) dst[m] = 0.f;
+                    }
+#pragma unroll
+                    for (int m = P; m < PP; ++m) dst[m] = 0.f;
+                }
+                __syncthreads();
+#pragma unroll
+                for (int ks = 0; ks < CHM / 4; ++ks) {
+                    const int jb = ks * 4 + lane / 16;
+                    float av[T], bv[T];
+#pragma unroll
+                    for (int ti = 0; ti < T; ++ti) av[ti] = sX[jb * PP + 16 * ti + lane % 16];
+#pragma unroll
+                    for (int tj = 0; tj < T; ++tj) bv[tj] = sW[jb * PP + 16 * tj + lane % 16];
+#pragma unroll
+                    for (int ti = 0; ti < T; ++ti)
+#pragma unroll
+                        for (int tj = 0; tj < T; ++tj)
+                            acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ti], bv[tj], acc[ti][tj], 0, 0, 0);
+                }
+                __syncthreads();
+            }
+#pragma unroll
+            for (int ti = 0; ti < T; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < T; ++tj)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int m = 16 * ti + 4 * (lane / 16) + e, nn = 16 * tj + lane % 16;
+                        if (m < P && nn < P) sM[m * LD + nn] = acc[ti][tj][e];
+                    }
+            __syncthreads();
+
+            // ---- FP32 equilibration
+            bool sing = false;
+            if (lane < P) {
+                float mx = 0.f;
+                for (int c = 0; c < P; ++c) mx = fmaxf(mx, fabsf(sM[lane * LD + c]));
+                if (!(mx > 0.f) || !isfinite(mx)) sing = true;
+                const float rs = 1.f / mx;
+                sRs[lane] = rs;
+                for (int c = 0; c < P; ++c) sM[lane * LD + c] *= rs;
+            }
+            __syncthreads();
+            if (lane < P) {
+                float mx = 0.f;
+                for (int r = 0; r < P; ++r) mx = fmaxf(mx, fabsf(sM[r * LD + lane]));
+                if (!(mx > 0.f) || !isfinite(mx)) sing = true;
+                const float cs = 1.f / mx;
+                sCs[lane] = cs;
+                for (int r = 0; r < P; ++r) sM[r * LD + lane] *= cs;
+            }
+            __syncthreads();
+            if (__any(sing)) status = LABFM_ST_SINGULAR;
+
+            // ---- FP32 LU with partial pivoting (ties: lowest row)
+            int perm = lane;
+            if (status == LABFM_ST_OK) {
+                for (int kk = 0; kk < P; ++kk) {
+                    float v = (lane >= kk && lane < P) ? fabsf(sM[lane * LD + kk]) : -1.f;
+                    int ir = lane;
+#pragma unroll
+                    for (int off = 32; off >= 1; off >>= 1) {
+                        const float v2 = __shfl_xor(v, off, 64);
+                        const int i2 = __shfl_xor(ir, off, 64);
+                        const bool take = (v2 > v) | ((v2 == v) & (i2 < ir));
+                        v = take ? v2 : v;
+                        ir = take ? i2 : ir;
+                    }
+                    if (!(v > 0.f) || !isfinite(v)) {
+                        status = LABFM_ST_SINGULAR;
+                        break;
+                    }
+                    const int pr = ir;
+                    if (pr != kk) {
+                        if (lane < P) {
+                            const float u = sM[kk * LD + lane];
+                            sM[kk * LD + lane] = sM[pr * LD + lane];
+                            sM[pr * LD + lane] = u;
+                        }
+                        const int pk = __shfl(perm, kk, 64), pp = __shfl(perm, pr, 64);
+                        if (lane == kk) perm = pp;
+                        if (lane == pr) perm = pk;
+                    }
+                    __syncthreads();
+                    if (lane > kk && lane < P) sM[lane * LD + kk] = sM[lane * LD + kk] / sM[kk * LD + kk];
+                    __syncthreads();
+                    if (lane > kk && lane < P) {
+                        // rows in groups of four: all loads issued before the stores
+                        const float u = sM[kk * LD + lane];
+                        int r = kk + 1;
+                        for (; r + 4 <= P; r += 4) {
+                            const float l0 = sM[r * LD + kk], l1 = sM[(r + 1) * LD + kk];
+                            const float l2 = sM[(r + 2) * LD + kk], l3 = sM[(r + 3) * LD + kk];
+                            const float a0 = sM[r * LD + lane], a1 = sM[(r + 1) * LD + lane];
+                            const float a2 = sM[(r + 2) * LD + lane], a3 = sM[(r + 3) * LD + lane];
+                            sM[r * LD + lane] = fmaf(-l0, u, a0);
+                            sM[(r + 1) * LD + lane] = fmaf(-l1, u, a1);
+                            sM[(r + 2) * LD + lane] = fmaf(-l2, u, a2);
+                            sM[(r + 3) * LD + lane] = fmaf(-l3, u, a3);
+                        }
+                        for (; r < P; ++r) sM[r * LD + lane] = fmaf(-sM[r * LD + kk], u, sM[r * LD + lane]);
+                    }
+                    __syncthreads();
+                }
+            }
+            if (lane < P) sPerm[lane] = perm;
+            __syncthreads();
+
+            if (status == LABFM_ST_OK) {
+                // ---- Psi from the FP32 factors, weights in FP64
+                double b[MAXOPS];
+#pragma unroll
+                for (int d = 0; d < MAXOPS; ++d) b[d] = (d < nops && lane < P) ? target(ops.op[d], lane) : 0.0;
+                lu_solve<P, LD, float>(sM, sRs, sCs, sPerm, b, nops);
+                if (lane < P)
+#pragma unroll
+                    for (int d = 0; d < MAXOPS; ++d)
+                        if (d < nops) sPsi[d][lane] = b[d];
+                __syncthreads();
+                double wreg[JS][MAXOPS];
+#pragma unroll
+                for (int js = 0; js < JS; ++js) {
+                    const int q = lane + 64 * js;
+#pragma unroll
+                    for (int d = 0; d < MAXOPS; ++d) wreg[js][d] = 0.0;
+                    if (q < N) {
+                        BasisState<K> B;
+                        basis_prepare<K, FAM>(B, dxr[js], dyr[js], a.rbf, a.sigma);
+#pragma unroll
+                        for (int m = 0; m < P; ++m) {
+                            const double wm = abf<K, FAM>(B, m);
+#pragma unroll
+                            for (int d = 0; d < MAXOPS; ++d)
+                                if (d < nops) wreg[js][d] = fma(wm, sPsi[d][m], wreg[js][d]);
+                        }
+#pragma unroll
+                        for (int d = 0; d < MAXOPS; ++d)
+                            if (d < nops) sWl[d][q] = wreg[js][d];
+                    }
+                }
+                __syncthreads();
+
+                // ---- FP64 refinement with FP32 correction solves
+                const int ma = lane < P ? ELEM.a[lane] : 0;
+                const int mb = lane < P ? ELEM.b[lane] : 0;
+                const double mf = lane < P ? inv_fact(ma) * inv_fact(mb) : 0.0;
+                for (;;) {
+                    double r[MAXOPS];
+#pragma unroll
+                    for (int d = 0; d < MAXOPS; ++d) r[d] = 0.0;
+                    if (lane < P) {
+                        double accr[MAXOPS];
+#pragma unroll
+                        for (int d = 0; d < MAXOPS; ++d) accr[d] = 0.0;
+                        for (int q = 0; q < N; ++q) {
+                            const double dx = sD[0][q], dy = sD[1][q];
+                            double xm = mf;
+#pragma unroll
+                            for (int e = 0; e < K; ++e) {
+                                xm *= (e < ma) ? dx : 1.0;
+                                xm *= (e < mb) ? dy : 1.0;
+                            }
+#pragma unroll
+                            for (int d = 0; d < MAXOPS; ++d)
+                                if (d < nops) accr[d] = fma(xm, sWl[d][q], accr[d]);
+                        }
+#pragma unroll
+                        for (int d = 0; d < MAXOPS; ++d)
+                            if (d < nops) r[d] = target(ops.op[d], lane) - accr[d];
+                    }
+                    double rm = 0.0;
+#pragma unroll
+                    for (int d = 0; d < MAXOPS; ++d) rm = fmax(rm, fabs(r[d]));
+                    if (!isfinite(rm)) rm = INFINITY;
+                    res = wave_max(rm);
+                    if (!(res > a.tol_stop) || iters >= a.max_iters32) break;
+                    lu_solve<P, LD, float>(sM, sRs, sCs, sPerm, r, nops);
+                    __syncthreads();
+                    if (lane < P)
+#pragma unroll
+                        for (int d = 0; d < MAXOPS; ++d)
+                            if (d < nops) sPsi[d][lane] = r[d];
+                    __syncthreads();
+#pragma unroll
+                    for (int js = 0; js < JS; ++js) {
+                        const int q = lane + 64 * js;
+                        if (q < N) {
+                            BasisState<K> B;
+                            basis_prepare<K, FAM>(B, dxr[js], dyr[js], a.rbf, a.sigma);
+                            double dw[MAXOPS];
+#pragma unroll
+                            for (int d = 0; d < MAXOPS; ++d) dw[d] = 0.0;
+#pragma unroll
+                            for (int m = 0; m < P; ++m) {
+                                const double wm = abf<K, FAM>(B, m);
+#pragma unroll
+                                for (int d = 0; d < MAXOPS; ++d)
+                                    if (d < nops) dw[d] = fma(wm, sPsi[d][m], dw[d]);
+                            }
+#pragma unroll
+                            for (int d = 0; d < MAXOPS; ++d)
+                                if (d < nops) {
+                                    wreg[js][d] += dw[d];
+                                    sWl[d][q] = wreg[js][d];
+                                }
+                        }
+                    }
+                    __syncthreads();
+                    ++iters;
+                }
+                if (!(res <= a.tol_pass)) {
+                    status = LABFM_ST_NOT_CONVERGED;
+                } else {
+#pragma unroll
+                    for (int d = 0; d < MAXOPS; ++d) {
+                        if (d >= nops) continue;
+                        double hl = 1.0;
+                        for (int e = 0; e < deriv_order(ops.op[d]); ++e) hl *= h;
+#pragma unroll
+                        for (int js = 0; js < JS; ++js) {
+                            const int q = lane + 64 * js;
+                            if (q < N) {
+                                const double wv = wreg[js][d] / hl;
+                                if (a.w64) a.w64[(int64_t)d * a.nnz + s0 + q] = wv;
+                                if (a.w32) a.w32[(int64_t)d * a.nnz + s0 + q] = (float)wv;
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        // nodes the mixed path could not finish (singular FP32 factors or no
+        // convergence) are recomputed on the FP64 path; other failures are final
+        const bool retry = status == LABFM_ST_NOT_CONVERGED || status == LABFM_ST_SINGULAR;
+        if (retry) {
+            if (lane == 0) {
+                const int pos = atomicAdd(&retry_cnt[K], 1);
+                retry_list[list_off[K] + pos] = (int32_t)i;
+            }
+        } else {
+            const bool failed = status != LABFM_ST_OK;
+            if (failed) {
+                for (int d = 0; d < nops; ++d)
+                    for (int q = lane; q < N; q += 64) {
+                        if (a.w64) a.w64[(int64_t)d * a.nnz + s0 + q] = 0.0;
+                        if (a.w32) a.w32[(int64_t)d * a.nnz + s0 + q] = 0.0f;
+                    }
+                res = INFINITY;
+                iters = 0;
+            }
+            if (lane == 0) {
+                a.status[i] = (int8_t)status;
+                if (a.resid) a.resid[i] = (float)res;
+                if (a.iters) a.iters[i] = (int8_t)iters;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <int K, int FAM>
+int grid_for_mixed() {
+    static int g = 0;
+    if (g == 0) {
+        int dev = 0, ncu = 0, per = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_weights_mixed<K, FAM>, 64, 0);
+        if (ncu <= 0) ncu = 256;
+        if (per <= 0) per = 1;
+        g = ncu * per;
+    }
+    return g;
+}
+
+template <int K, int FAM>
+void launch_mixed_one(Context* c, const WeightArgs& a, const OpList& ops, const int32_t* list, const int32_t* off,
+                      const int32_t* cnt, int32_t* rlist, int32_t* rcnt, hipStream_t st) {
+    static const char* names[KMAX + 1] = {"", "weights32_k1", "weights32_k2", "weights32_k3", "weights32_k4",
+                                          "weights32_k5", "weights32_k6", "weights32_k7", "weights32_k8"};
+    KernelTimer timer(c, names[K], st);
+    k_weights_mixed<K, FAM><<<grid_for_mixed<K, FAM>(), 64, 0, st>>>(a, ops, list, off, cnt, rlist, rcnt);
+}
+
+template <int FAM>
+void launch_mixed_all(Context* c, const WeightArgs& a, const OpList& ops, const int32_t* list, const int32_t* off,
+                      const int32_t* cnt, int32_t* rlist, int32_t* rcnt, hipStream_t st) {
+    launch_mixed_one<1, FAM>(c, a, ops, list, off, cnt, rlist, rcnt, st);
+    launch_mixed_one<2, FAM>(c, a, ops, list, off, cnt, rlist, rcnt, st);
+    launch_mixed_one<3, FAM>(c, a, ops, list, off, cnt, rlist, rcnt, st);
+    launch_mixed_one<4, FAM>(c, a, ops, list, off, cnt, rlist, rcnt, st);
+    launch_mixed_one<5, FAM>(c, a, ops, list, off, cnt, rlist, rcnt, st);
+    launch_mixed_one<6, FAM>(c, a, ops, list, off, cnt, rlist, rcnt, st);
+    launch_mixed_one<7, FAM>(c, a, ops, list, off, cnt, rlist, rcnt, st);
+    launch_mixed_one<8, FAM>(c, a, ops, list, off, cnt, rlist, rcnt, st);
+}
+
+}  // namespace
+
+labfm_err weights_mixed(Context* c, const WeightArgs& a0, hipStream_t st) {
+    int32_t *list, *off, *cnt;
+    labfm_err e = build_order_lists(c, a0.order, a0.n, st, &list, &off, &cnt);
+    if (e != LABFM_OK) return e;
+    if ((e = weights_invalid_orders(a0, list, off, cnt, st)) != LABFM_OK) return e;
+    if ((e = ensure(c->mixed, sizeof(int32_t) * (size_t)(a0.n + KMAX + 2))) != LABFM_OK) return e;
+    int32_t* rcnt = (int32_t*)c->mixed.p;
+    int32_t* rlist = rcnt + (KMAX + 2);
+    LABFM_HIP_CHECK(hipMemsetAsync(rcnt, 0, sizeof(int32_t) * (KMAX + 2), st));
+    OpList ops{};
+    ops.nops = 0;
+    for (int b = 0; b < 5; ++b)
+        if (a0.ops & (1u << b)) ops.op[ops.nops++] = 1u << b;
+    if (a0.abf == LABFM_ABF_HERMITE)
+        launch_mixed_all<LABFM_ABF_HERMITE>(c, a0, ops, list, off, cnt, rlist, rcnt, st);
+    else
+        launch_mixed_all<LABFM_ABF_PAPER>(c, a0, ops, list, off, cnt, rlist, rcnt, st);
+    LABFM_HIP_CHECK(hipGetLastError());
+    // FP64 recomputation of the retry list; iters of those nodes are offset by 64
+    WeightArgs a = a0;
+    a.iters_offset = 64;
+    return weights_fp64_lists(c, a, rlist, off, rcnt, st);
+}
+
+}  // namespace labfm

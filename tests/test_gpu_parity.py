@@ -354,3 +354,73 @@ def test_step_fp32_vs_fp64_oracle(env, adv_ops):
     err = np.abs(u.double().cpu().numpy() - ref).max() / np.abs(ref).max()
     _say("  rk4 fp32 rel err %.3e" % err)
     assert err <= 1e-4
+
+
+# --------------------------------------------------------------------------- mixed precision
+@pytest.mark.parametrize("case", ["c1", "order8_96", "order6_periodic_5ops", "paper_quadratic_k4"])
+def test_weights_mixed_parity(env, case):
+    """FP32 matrix-core assembly + FP32 LU + FP64 refinement: the refined weights
+    are the FP64 system's solution, so the gate is the FP64 path's (moment
+    residual <= 1e-10, per-node parity <= 1e-10 on these sets); nodes the
+    mixed path hands to the FP64 path are flagged by iters >= 64."""
+    O = env["O"]
+    _say("mixed weights case %s" % case)
+    kw = {}
+    if case == "c1":
+        nd = WL.make_nodes(WL.config("c1"))
+        x, y, R, order, dom = nd["x"], nd["y"], nd["R"], nd["order"], nd["domain"]
+    elif case == "order8_96":
+        nd = WL.make_nodes(WL.config("c2"), n_side=96)
+        x, y, R, order, dom = nd["x"], nd["y"], nd["R"], nd["order"], nd["domain"]
+    elif case == "order6_periodic_5ops":
+        x, y, s = WL.jittered_lattice(40, eps=0.3, seed=3, periodic=True)
+        R, order, dom = np.full(x.size, 4.0 * s), np.full(x.size, 6, np.int8), WL.unit_domain(True)
+        kw = dict(ops=1 | 2 | 4 | 8 | 16)
+    else:
+        x, y, s = WL.jittered_lattice(40, eps=0.3, seed=6, periodic=True)
+        R, order, dom = np.full(x.size, 3.2 * s), np.full(x.size, 4, np.int8), WL.unit_domain(True)
+        kw = dict(family=1, rbf=2)
+    rp_o, col_o, R_o = O.neighbours(x, y, dom, R, order)
+    w_o, st_o, res_o, _ = O.weights(x, y, dom, R_o, order, rp_o, col_o, **kw)
+    xt, yt, Rt, ot, rp, col = _gpu_neigh(env, x, y, R, order, dom)
+    gkw = dict(kw)
+    if "family" in gkw:
+        gkw["abf"] = gkw.pop("family")
+    w64, _, st, res, it = env["ctx"].weights(xt, yt, Rt, ot, rp, col, dom, prec=1, **gkw)
+    env["torch"].cuda.synchronize()
+    st, res, it, w = st.cpu().numpy(), res.cpu().numpy(), it.cpu().numpy(), w64.cpu().numpy()
+    assert np.array_equal(st, st_o)
+    ok = st_o == 0
+    assert res[ok].max() <= 1e-10
+    par = _per_node_parity(rp_o, w, w_o, mask=ok)
+    _say("  mixed parity %.3e, fallback nodes %d, mean iters %.2f" % (par, int((it >= 64).sum()),
+                                                                      float(it[it < 64].mean())))
+    assert par <= 1e-10
+
+
+def test_weights_mixed_full_c2(env):
+    """512x512 workload on the mixed path: every node passes the 1e-10 gate;
+    weight parity as on the FP64 path (outliers of cond >= 1e8 allowed)."""
+    O = env["O"]
+    _say("mixed weights full c2")
+    nd = WL.make_nodes(WL.config("c2"))
+    rp_o, col_o, R_o = O.neighbours(nd["x"], nd["y"], nd["domain"], nd["R"], nd["order"])
+    w_o, st_o, _, _ = O.weights(nd["x"], nd["y"], nd["domain"], R_o, nd["order"], rp_o, col_o)
+    xt, yt, Rt, ot, rp, col = _gpu_neigh(env, nd["x"], nd["y"], nd["R"], nd["order"], nd["domain"])
+    w64, _, st, res, it = env["ctx"].weights(xt, yt, Rt, ot, rp, col, nd["domain"], prec=1)
+    env["torch"].cuda.synchronize()
+    st, res, it, w = st.cpu().numpy(), res.cpu().numpy(), it.cpu().numpy(), w64.cpu().numpy()
+    assert np.all(st == 0) and res.max() <= 1e-10
+    n = rp_o.size - 1
+    seg = np.repeat(np.arange(n), np.diff(rp_o))
+    par = np.zeros(n)
+    for d in range(3):
+        num = np.zeros(n)
+        den = np.zeros(n)
+        np.maximum.at(num, seg, np.abs(w[d] - w_o[d]))
+        np.maximum.at(den, seg, np.abs(w_o[d]))
+        par = np.maximum(par, num / den)
+    _say("  mixed c2: median parity %.2e, max %.2e, above 1e-10: %d, fallback %d, mean iters %.2f"
+         % (np.median(par), par.max(), int((par > 1e-10).sum()), int((it >= 64).sum()), float(it[it < 64].mean())))
+    assert (par > 1e-10).sum() <= max(1, n // 10000)
+    assert par.max() <= 1e-8
