@@ -3,9 +3,10 @@
 // Operator (Sec. 2 eq. general_do of King, Lind & Nasar):
 //   L^d_i(u) = sum_{j in row i} w^d_ij (u_j - u_i).
 // The gather-multiply-reduce is HBM-bound: G lanes share a CSR row, the
-// index and weight streams of a row are read once, contiguously, and the
-// partial sums are reduced across the G lanes with DPP/shuffles.  Several
-// operators on the same neighbour structure share the index stream.
+// index and weight streams of a row are read once, contiguously, U loads per
+// lane in flight before the gathers, and the partial sums are reduced across
+// the G lanes with shuffles.  Several operators on the same neighbour
+// structure share the index stream.
 //
 // Time stepping: classical RK4 (Sec. 4.1) on du/dt = L_lin(u) - gamma B(B(u)).
 // With B present each stage is two passes: A computes L_lin(u_s) and B(u_s)
@@ -21,6 +22,21 @@ namespace {
 
 constexpr int AOPS = 5;
 
+// Lanes per row (G) and loads in flight per lane (U): G*U entries of a row
+// are requested before the first gather result is used.  Swept on the
+// 512x512 (N~60) and 1024x1024 (N~49) neighbour structures: FP64 streams
+// favour G=16, U=4; FP32 streams G=8, U=8.
+template <typename T>
+struct Shape;
+template <>
+struct Shape<double> {
+    static constexpr int G = 16, U = 4;
+};
+template <>
+struct Shape<float> {
+    static constexpr int G = 8, U = 8;
+};
+
 template <typename T, int G>
 __device__ inline T group_sum(T v) {
 #pragma unroll
@@ -28,31 +44,60 @@ __device__ inline T group_sum(T v) {
     return v;
 }
 
-template <typename T, int G>
+// NW weight streams over one CSR row, lane `sub` of G:
+//   acc[d] += sum_{q in row, q = sub mod G} w_d[q] (x[col[q]] - xi).
+// Every index and weight load of a U-block is issued before its gathers.
+template <typename T, int NW>
+struct WPtrs {
+    const T* p[NW];
+};
+
+template <typename T, int G, int U, int NW>
+__device__ inline void row_sums(const int32_t* __restrict__ col, int64_t s, int64_t e, int sub, const WPtrs<T, NW>& w,
+                                const T* __restrict__ x, T xi, T (&acc)[NW]) {
+    for (int64_t q0 = s + sub; q0 < e; q0 += (int64_t)G * U) {
+        int c[U];
+        T wv[U][NW];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int64_t q = q0 + (int64_t)k * G;
+            c[k] = q < e ? col[q] : -1;
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int64_t q = q0 + (int64_t)k * G;
+#pragma unroll
+            for (int d = 0; d < NW; ++d) wv[k][d] = q < e ? w.p[d][q] : T(0);
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const T dx = c[k] >= 0 ? x[c[k]] - xi : T(0);
+#pragma unroll
+            for (int d = 0; d < NW; ++d) acc[d] += wv[k][d] * dx;
+        }
+    }
+}
+
+template <typename T, int NOPS>
 __global__ __launch_bounds__(256) void k_apply(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
-                                               int64_t n, int64_t nnz, int nops, const T* __restrict__ w,
+                                               int64_t n, int64_t nnz, const T* __restrict__ w,
                                                const T* __restrict__ u, T* __restrict__ out) {
+    constexpr int G = Shape<T>::G, U = Shape<T>::U;
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t row = gid / G;
     const int sub = (int)(gid % G);
     if (row >= n) return;  // whole groups exit together
-    const int64_t s = rp[row], e = rp[row + 1];
-    const T ui = u[row];
-    T acc[AOPS];
+    WPtrs<T, NOPS> wp;
 #pragma unroll
-    for (int d = 0; d < AOPS; ++d) acc[d] = T(0);
-    for (int64_t q = s + sub; q < e; q += G) {
-        const T du = u[col[q]] - ui;
+    for (int d = 0; d < NOPS; ++d) wp.p[d] = w + (int64_t)d * nnz;
+    T acc[NOPS];
 #pragma unroll
-        for (int d = 0; d < AOPS; ++d)
-            if (d < nops) acc[d] += w[(int64_t)d * nnz + q] * du;
-    }
+    for (int d = 0; d < NOPS; ++d) acc[d] = T(0);
+    row_sums<T, G, U, NOPS>(col, rp[row], rp[row + 1], sub, wp, u, u[row], acc);
 #pragma unroll
-    for (int d = 0; d < AOPS; ++d) {
-        if (d < nops) {
-            T v = group_sum<T, G>(acc[d]);
-            if (sub == 0) out[(int64_t)d * n + row] = v;
-        }
+    for (int d = 0; d < NOPS; ++d) {
+        const T v = group_sum<T, G>(acc[d]);
+        if (sub == 0) out[(int64_t)d * n + row] = v;
     }
 }
 
@@ -87,68 +132,65 @@ __device__ inline void rk4_update(int stage, T k, T dt, int64_t i, T* u, T* acc,
 }
 
 // single pass: k = L_lin(us_in), then the stage update
-template <typename T, int G>
+template <typename T>
 __global__ __launch_bounds__(256) void k_step_single(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                                                      int64_t n, const T* __restrict__ wl, const T* us_in, T dt,
                                                      int stage, T* u, T* acc, T* us_out) {
+    constexpr int G = Shape<T>::G, U = Shape<T>::U;
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t row = gid / G;
     const int sub = (int)(gid % G);
     if (row >= n) return;
-    const int64_t s = rp[row], e = rp[row + 1];
-    const T ui = us_in[row];
-    T a = T(0);
-    for (int64_t q = s + sub; q < e; q += G) a += wl[q] * (us_in[col[q]] - ui);
-    a = group_sum<T, G>(a);
-    if (sub == 0) rk4_update<T>(stage, a, dt, row, u, acc, us_out);
+    WPtrs<T, 1> wp{{wl}};
+    T a[1] = {T(0)};
+    row_sums<T, G, U, 1>(col, rp[row], rp[row + 1], sub, wp, us_in, us_in[row], a);
+    const T k = group_sum<T, G>(a[0]);
+    if (sub == 0) rk4_update<T>(stage, k, dt, row, u, acc, us_out);
 }
 
-// pass A: ra = L_lin(us_in), b1 = B(us_in)
-template <typename T, int G>
+// pass A: ra = L_lin(us_in), b1 = B(us_in), one read of the index stream
+template <typename T>
 __global__ __launch_bounds__(256) void k_step_a(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                                                 int64_t n, const T* __restrict__ wl, const T* __restrict__ wb,
                                                 const T* __restrict__ us_in, T* __restrict__ ra, T* __restrict__ b1) {
+    constexpr int G = Shape<T>::G, U = Shape<T>::U;
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t row = gid / G;
     const int sub = (int)(gid % G);
     if (row >= n) return;
-    const int64_t s = rp[row], e = rp[row + 1];
-    const T ui = us_in[row];
-    T a = T(0), b = T(0);
-    for (int64_t q = s + sub; q < e; q += G) {
-        const T du = us_in[col[q]] - ui;
-        a += wl[q] * du;
-        b += wb[q] * du;
-    }
-    a = group_sum<T, G>(a);
-    b = group_sum<T, G>(b);
+    WPtrs<T, 2> wp{{wl, wb}};
+    T a[2] = {T(0), T(0)};
+    row_sums<T, G, U, 2>(col, rp[row], rp[row + 1], sub, wp, us_in, us_in[row], a);
+    const T la = group_sum<T, G>(a[0]);
+    const T lb = group_sum<T, G>(a[1]);
     if (sub == 0) {
-        ra[row] = a;
-        b1[row] = b;
+        ra[row] = la;
+        b1[row] = lb;
     }
 }
 
 // pass B: k = ra - gamma B(b1), then the stage update
-template <typename T, int G>
+template <typename T>
 __global__ __launch_bounds__(256) void k_step_b(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                                                 int64_t n, const T* __restrict__ wb, const T* __restrict__ b1,
                                                 const T* __restrict__ ra, T gamma, T dt, int stage, T* u, T* acc,
                                                 T* us_out) {
+    constexpr int G = Shape<T>::G, U = Shape<T>::U;
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t row = gid / G;
     const int sub = (int)(gid % G);
     if (row >= n) return;
-    const int64_t s = rp[row], e = rp[row + 1];
-    const T bi = b1[row];
-    T c = T(0);
-    for (int64_t q = s + sub; q < e; q += G) c += wb[q] * (b1[col[q]] - bi);
-    c = group_sum<T, G>(c);
-    if (sub == 0) rk4_update<T>(stage, ra[row] - gamma * c, dt, row, u, acc, us_out);
+    WPtrs<T, 1> wp{{wb}};
+    T c[1] = {T(0)};
+    row_sums<T, G, U, 1>(col, rp[row], rp[row + 1], sub, wp, b1, b1[row], c);
+    const T bb = group_sum<T, G>(c[0]);
+    if (sub == 0) rk4_update<T>(stage, ra[row] - gamma * bb, dt, row, u, acc, us_out);
 }
 
-constexpr int GAPPLY = 16;
-
-inline unsigned blocks_for(int64_t n, int G) { return (unsigned)((n * G + 255) / 256); }
+template <typename T>
+inline unsigned blocks_for(int64_t n) {
+    return (unsigned)((n * Shape<T>::G + 255) / 256);
+}
 
 template <typename T>
 labfm_err enqueue_step(const labfm_step_plan* p, T* u, T* scratch, hipStream_t st) {
@@ -162,20 +204,33 @@ labfm_err enqueue_step(const labfm_step_plan* p, T* u, T* scratch, hipStream_t s
     T* outs[4] = {usA, usB, usA, u};
     const T dt = (T)p->dt;
     const T gamma = (T)p->gamma;
-    const unsigned nb = blocks_for(n, GAPPLY);
+    const unsigned nb = blocks_for<T>(n);
     for (int stage = 0; stage < 4; ++stage) {
         if (p->w_bh) {
-            k_step_a<T, GAPPLY><<<nb, 256, 0, st>>>(p->row_ptr, p->col, n, (const T*)p->w_lin, (const T*)p->w_bh,
-                                                   in[stage], ra, b1);
-            k_step_b<T, GAPPLY><<<nb, 256, 0, st>>>(p->row_ptr, p->col, n, (const T*)p->w_bh, b1, ra, gamma, dt,
-                                                   stage, u, acc, outs[stage]);
+            k_step_a<T><<<nb, 256, 0, st>>>(p->row_ptr, p->col, n, (const T*)p->w_lin, (const T*)p->w_bh, in[stage],
+                                            ra, b1);
+            k_step_b<T><<<nb, 256, 0, st>>>(p->row_ptr, p->col, n, (const T*)p->w_bh, b1, ra, gamma, dt, stage, u,
+                                            acc, outs[stage]);
         } else {
-            k_step_single<T, GAPPLY><<<nb, 256, 0, st>>>(p->row_ptr, p->col, n, (const T*)p->w_lin, in[stage], dt,
-                                                        stage, u, acc, outs[stage]);
+            k_step_single<T><<<nb, 256, 0, st>>>(p->row_ptr, p->col, n, (const T*)p->w_lin, in[stage], dt, stage, u,
+                                                 acc, outs[stage]);
         }
     }
     LABFM_HIP_CHECK(hipGetLastError());
     return LABFM_OK;
+}
+
+template <typename T>
+void launch_apply(const int64_t* row_ptr, const int32_t* col, int64_t n, int64_t nnz, int nops, const T* w,
+                  const T* u, T* out, hipStream_t st) {
+    const unsigned nb = blocks_for<T>(n);
+    switch (nops) {
+        case 1: k_apply<T, 1><<<nb, 256, 0, st>>>(row_ptr, col, n, nnz, w, u, out); break;
+        case 2: k_apply<T, 2><<<nb, 256, 0, st>>>(row_ptr, col, n, nnz, w, u, out); break;
+        case 3: k_apply<T, 3><<<nb, 256, 0, st>>>(row_ptr, col, n, nnz, w, u, out); break;
+        case 4: k_apply<T, 4><<<nb, 256, 0, st>>>(row_ptr, col, n, nnz, w, u, out); break;
+        default: k_apply<T, AOPS><<<nb, 256, 0, st>>>(row_ptr, col, n, nnz, w, u, out); break;
+    }
 }
 
 }  // namespace
@@ -183,14 +238,11 @@ labfm_err enqueue_step(const labfm_step_plan* p, T* u, T* scratch, hipStream_t s
 labfm_err apply_launch(Context* c, const int64_t* row_ptr, const int32_t* col, int64_t n, int64_t nnz, int nops,
                        const void* w, int dtype, const void* u, void* out, hipStream_t st) {
     if (n == 0) return LABFM_OK;
-    const unsigned nb = blocks_for(n, GAPPLY);
     KernelTimer timer(c, dtype == 0 ? "apply_f32" : "apply_f64", st);
     if (dtype == 0)
-        k_apply<float, GAPPLY><<<nb, 256, 0, st>>>(row_ptr, col, n, nnz, nops, (const float*)w, (const float*)u,
-                                                   (float*)out);
+        launch_apply<float>(row_ptr, col, n, nnz, nops, (const float*)w, (const float*)u, (float*)out, st);
     else
-        k_apply<double, GAPPLY><<<nb, 256, 0, st>>>(row_ptr, col, n, nnz, nops, (const double*)w, (const double*)u,
-                                                    (double*)out);
+        launch_apply<double>(row_ptr, col, n, nnz, nops, (const double*)w, (const double*)u, (double*)out, st);
     LABFM_HIP_CHECK(hipGetLastError());
     return LABFM_OK;
 }
