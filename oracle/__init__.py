@@ -57,6 +57,9 @@ def lib():
                                       C.POINTER(C.c_int), dp, dp]
         L.or_weights.argtypes = [C.c_int64, dp, dp, C.POINTER(_Domain), dp, i8, i64, i32,
                                  C.POINTER(_WOpts), dp, i8, dp, i8]
+        L.or_targets.argtypes = [C.c_uint, C.c_int, dp]
+        L.or_stencils_psi.argtypes = [C.c_int64, C.c_int, C.c_int, i32, dp, dp, C.POINTER(_WOpts), dp, i8, dp, dp]
+        L.or_stencils_psi.restype = None
         L.or_apply.argtypes = [C.c_int64, i64, i32, dp, dp, dp]
         L.or_combine.argtypes = [C.c_int64, C.c_int, dp, dp, dp]
         L.or_rk4.argtypes = [C.c_int64, i64, i32, dp, dp, C.c_double, C.c_double, C.c_int, dp]
@@ -165,6 +168,36 @@ def node_weights(k, dxh, dyh, **kw):
                                _p(what, C.c_double), C.byref(res), C.byref(it), _p(M, C.c_double),
                                C.byref(cond))
     return dict(what=what[:, :N], status=st, resid=res.value, iters=it.value, M=M, cond1=cond.value)
+
+
+def targets(ops, k):
+    """Target vectors C^d (Sec. 2, Sec. 3.3) of the operators in `ops`, [nops, p]."""
+    C_ = np.zeros((nops(ops), p_of_k(k)))
+    if lib().or_targets(int(ops), int(k), _p(C_, C.c_double)) != 0:
+        raise ValueError("order %d cannot express the requested operators" % k)
+    return C_
+
+
+def stencils_psi(k, dxh, dyh, N, want_M=False, **kw):
+    """ABF coefficients Psi^d (eq. lsys, refined) of a batch of stencils.
+
+    dxh, dyh: [n, Nmax] scaled offsets (rows padded beyond N[s]); N: [n].
+    Returns (psi [n, nops, p], status [n], resid [n]) and, with want_M, the
+    moment matrices [n, p, p] (row = monomial) as a fourth element."""
+    o = wopts(**kw)
+    dxh = np.ascontiguousarray(dxh, np.float64)
+    dyh = np.ascontiguousarray(dyh, np.float64)
+    n, Nmax = dxh.shape
+    N = np.ascontiguousarray(N, np.int32)
+    p = p_of_k(k)
+    psi = np.zeros((n, nops(o.ops), p))
+    st = np.zeros(n, np.int8)
+    res = np.zeros(n)
+    M = np.zeros((n, p, p)) if want_M else None
+    lib().or_stencils_psi(n, int(k), int(Nmax), _p(N, C.c_int32), _p(dxh, C.c_double), _p(dyh, C.c_double),
+                          C.byref(o), _p(psi, C.c_double), _p(st, C.c_int8), _p(res, C.c_double),
+                          _p(M, C.c_double) if want_M else None)
+    return (psi, st, res, M) if want_M else (psi, st, res)
 
 
 def weights(x, y, domain, R, order, row_ptr, col, **kw):

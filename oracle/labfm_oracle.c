@@ -451,6 +451,17 @@ static int or_target(unsigned op, int p, double* C, int* l) {
     return -1;
 }
 
+/* Target vectors C^d of the requested operators, [nops][p] for order k. */
+int or_targets(unsigned ops, int k, double* C) {
+    int p = or_p_of_k(k), op_i = 0, l;
+    for (int b = 0; b < 5; ++b) {
+        if (!((ops >> b) & 1u)) continue;
+        if (or_target(1u << b, p, C + (size_t)op_i * p, &l) != 0) return -1;
+        ++op_i;
+    }
+    return 0;
+}
+
 /* Dense LU with partial pivoting on a p x p row-major matrix, after row then
  * column max-abs equilibration (a reading: the paper does not name a solver).
  * Ties in the pivot search go to the lowest row index. */
@@ -592,14 +603,20 @@ static int or_nops(unsigned ops) {
  * the final moment residual max_o ||C^o - X^T w^o||_inf and the number of
  * refinement updates.  Refinement (a reading, for FP64 round-off at k = 8):
  *   r = C - X^T w;  stop if ||r|| <= tol_stop;  w += W (M^-1 r). */
-int or_node_weights(int k, int N, const double* dxh, const double* dyh, const or_wopts* o,
-                    double* what, double* resid, int* iters, double* Mhat, double* cond1) {
+/* One node system.  psi (optional, [nops][p]) receives the ABF coefficients
+ * Psi^d of eq. (lsys) including every refinement correction, so that
+ * w = W Psi holds for the returned weights. */
+static int node_weights_impl(int k, int N, const double* dxh, const double* dyh, const or_wopts* o,
+                             double* what, double* resid, int* iters, double* Mhat, double* cond1,
+                             double* psi) {
     int p = or_p_of_k(k);
     int nops = or_nops(o->ops);
     *resid = INFINITY;
     *iters = 0;
     if (cond1) *cond1 = INFINITY;
     for (int i = 0; i < nops * N; ++i) what[i] = 0.0;
+    if (psi)
+        for (int i = 0; i < nops * p; ++i) psi[i] = 0.0;
     if (k < 1 || k > OR_MAXK) return OR_ST_ORDER_TOO_LOW;
     {
         int op_i = 0;
@@ -667,6 +684,7 @@ int or_node_weights(int k, int N, const double* dxh, const double* dyh, const or
             if (!(res > o->tol_stop) || it >= o->max_iters) break;
             double dPsi[OR_MAXP];
             or_lu_solve(&F, r, dPsi);
+            for (int nn = 0; nn < p; ++nn) Psi[nn] += dPsi[nn];
             for (int j = 0; j < N; ++j) {
                 double acc = 0.0;
                 for (int nn = 0; nn < p; ++nn) acc += W[(size_t)j * p + nn] * dPsi[nn];
@@ -675,6 +693,7 @@ int or_node_weights(int k, int N, const double* dxh, const double* dyh, const or
             ++it;
         }
         if (!isfinite(res)) res = INFINITY;
+        if (psi) memcpy(psi + (size_t)op_i * p, Psi, sizeof(double) * (size_t)p);
         worst = fmax(worst, res);
         if (it > maxit) maxit = it;
         ++op_i;
@@ -685,6 +704,32 @@ int or_node_weights(int k, int N, const double* dxh, const double* dyh, const or
     *iters = maxit;
     if (!(worst <= 1e-10)) return OR_ST_NOT_CONVERGED;
     return OR_ST_OK;
+}
+
+int or_node_weights(int k, int N, const double* dxh, const double* dyh, const or_wopts* o,
+                    double* what, double* resid, int* iters, double* Mhat, double* cond1) {
+    return node_weights_impl(k, N, dxh, dyh, o, what, resid, iters, Mhat, cond1, NULL);
+}
+
+/* ABF coefficients of a batch of stencils given by scaled offsets:
+ * stencil s has N[s] <= Nmax offsets dxh[s*Nmax + j], dyh[s*Nmax + j]; psi
+ * [n][nops][p] (p of order k), status[n], resid[n], Mhat (optional) [n][p][p]
+ * the moment matrices of eq. (disc_form). */
+void or_stencils_psi(int64_t n, int k, int Nmax, const int32_t* N, const double* dxh, const double* dyh,
+                     const or_wopts* o, double* psi, int8_t* status, double* resid, double* Mhat) {
+    int nops = or_nops(o->ops);
+    int p = or_p_of_k(k);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t s = 0; s < n; ++s) {
+        double* wh = (double*)malloc(sizeof(double) * (size_t)(N[s] > 0 ? N[s] : 1) * nops);
+        double res;
+        int it;
+        status[s] = (int8_t)node_weights_impl(k, N[s], dxh + (size_t)s * Nmax, dyh + (size_t)s * Nmax, o, wh, &res,
+                                              &it, Mhat ? Mhat + (size_t)s * p * p : NULL, NULL,
+                                              psi + (size_t)s * nops * p);
+        resid[s] = res;
+        free(wh);
+    }
 }
 
 int or_weights(int64_t n, const double* x, const double* y, const or_domain* dom, const double* R,

@@ -65,6 +65,10 @@ int64_t or_neighbours_cells(int64_t n, const double* x, const double* y, const o
 int or_node_weights(int k, int N, const double* dxh, const double* dyh, const or_wopts* o,
                     double* what /* [nops][N] scaled weights */, double* resid, int* iters,
                     double* Mhat /* optional p*p (row = monomial) */, double* cond1 /* optional */);
+int or_targets(unsigned ops, int k, double* C /* [nops][p] */);
+void or_stencils_psi(int64_t n, int k, int Nmax, const int32_t* N, const double* dxh, const double* dyh,
+                     const or_wopts* o, double* psi /* [n][nops][p] */, int8_t* status, double* resid,
+                     double* Mhat /* optional [n][p][p] */);
 int or_weights(int64_t n, const double* x, const double* y, const or_domain* dom, const double* R,
                const int8_t* order, const int64_t* row_ptr, const int32_t* col, const or_wopts* o,
                double* w /* [nops][nnz] */, int8_t* status, double* resid, int8_t* iters);
