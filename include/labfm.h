@@ -73,8 +73,11 @@ enum {
  * FP64: basis, moment matrix, LU and refinement all in FP64.
  * MIXED: basis and moment matrix in FP32 on matrix cores (FP32 accumulate),
  *        FP32 LU, FP64 residual and FP64 weight refinement; nodes whose
- *        refinement does not converge are recomputed on the FP64 path. */
-typedef enum { LABFM_PREC_FP64 = 0, LABFM_PREC_MIXED = 1 } labfm_prec;
+ *        refinement does not converge are recomputed on the FP64 path.
+ * MLP: as MIXED, but nodes of the network's order start the refinement from
+ *        the network's Psi0 (labfm_wopts.mlp) instead of from a first solve
+ *        with the FP32 factors. */
+typedef enum { LABFM_PREC_FP64 = 0, LABFM_PREC_MIXED = 1, LABFM_PREC_MLP = 2 } labfm_prec;
 
 /* Per-node status written by labfm_weights. */
 enum {
@@ -96,6 +99,38 @@ typedef struct {
     int periodic[2];
 } labfm_domain;
 
+/* Learned warm start (not part of the paper): a fully connected network from
+ * stencil features (labfm_mlp_features, dims[0] = 3 kmax) to the ABF
+ * coefficients Psi^d of eq. (lsys), dims[n_layers] = nops(ops) * p(order),
+ * in operator-major order (Psi^d_m at index d p + m).  Hidden layers apply
+ * SiLU, z * sigmoid(z); the last layer is linear, and with de-normalisation
+ * its output y becomes Psi = mu + sd * y.  Products use BF16 operands with
+ * FP32 accumulation; biases and activations are FP32.  All arrays are device
+ * memory owned by the caller. */
+#define LABFM_MLP_MAX_LAYERS 8
+typedef struct {
+    int n_layers;                         /* weight layers, 1..8                          */
+    int dims[LABFM_MLP_MAX_LAYERS + 1];   /* widths, each 1..4096                         */
+    const void* W[LABFM_MLP_MAX_LAYERS];  /* BF16 [dims[l+1]][dims[l]], row-major         */
+    const float* b[LABFM_MLP_MAX_LAYERS]; /* FP32 [dims[l+1]]                             */
+    const float* mu;                      /* FP32 [dims[n_layers]] output shift           */
+    const float* sd;                      /* FP32 [dims[n_layers]] output scale           */
+    int order;                            /* stencil order the network serves (1..8)      */
+    unsigned ops;                         /* LABFM_OP_* bits of its output                */
+    int kmax;                             /* neighbours per input, 1..128                 */
+} labfm_mlp;
+
+/* Gradient buffers (device FP32, layouts of W and b). */
+typedef struct {
+    float* W[LABFM_MLP_MAX_LAYERS];
+    float* b[LABFM_MLP_MAX_LAYERS];
+} labfm_mlp_grads;
+
+/* Adam hyper-parameters (Kingma & Ba 2015). */
+typedef struct {
+    double lr, beta1, beta2, eps;
+} labfm_adam;
+
 typedef struct {
     int abf;           /* labfm_abf                                        */
     int rbf;           /* labfm_rbf                                        */
@@ -105,6 +140,7 @@ typedef struct {
     double tol_stop;   /* refinement stops when ||C - X^T w||_inf <= this  */
     double tol_pass;   /* status OK when the final residual <= this        */
     int max_iters;     /* FP64 refinement updates at most                  */
+    const labfm_mlp* mlp; /* network for LABFM_PREC_MLP (host struct), else NULL */
 } labfm_wopts;
 
 /* Message of the last failed call on this thread ("" if none). */
@@ -140,6 +176,9 @@ labfm_err labfm_build_neighbours(void* ctx, const double* x, const double* y, in
  * solved by row-then-column max equilibration and LU with partial
  * pivoting, refined on the weights (r = C - X^T w; w += W M^-1 r) in FP64,
  * and unscaled by h^l (l = 1, 1, 2, 4, 6 for DX, DY, LAP, BIHARM, TRIHARM).
+ * With LABFM_PREC_MLP the network must serve exactly opt->ops; its features
+ * and outputs for every node are computed first (library scratch of
+ * 4 n dims[n_layers] bytes plus a chunk of 65536 nodes' activations).
  * Outputs (device): w64 [nops][nnz] FP64 and/or w32 [nops][nnz] FP32 (either
  * may be NULL, not both); status int8 [n]; resid FP32 [n] (final
  * max-norm moment residual over the operators); iters int8 [n] (FP64
@@ -187,13 +226,55 @@ typedef struct {
 labfm_err labfm_step(void* ctx, const labfm_step_plan* plan, void* u, void* scratch, int nsteps,
                      int use_graph, void* stream);
 
+/* ---- learned warm start: features, network, training --------------------
+ * Features of every node i < n (Sec. 2 stencil, scaled offsets d = r_ji / h_i,
+ * h_i = R_i / 2): the row's neighbours ranked by (d_x^2 + d_y^2, j), the
+ * nearest kmax written as feat[i][3t..3t+2] = (d_x, d_y, 1), missing slots
+ * (0, 0, 0); rows with more than LABFM_MAX_NEIGHBOURS entries get all zeros.
+ * feat: device FP32 [n][3 kmax].  Asynchronous. */
+labfm_err labfm_mlp_features(void* ctx, const double* x, const double* y, int64_t n, const labfm_domain* dom,
+                             const double* R, const int64_t* row_ptr, const int32_t* col, int kmax, float* feat,
+                             void* stream);
+
+/* Forward pass of B rows: in FP32 [B][dims[0]] -> out FP32 [B][dims[n_layers]]
+ * (de-normalised when denorm != 0).  cache (device FP32, NULL for inference):
+ * receives, per hidden layer l, the pre-activations Z_l then the activations
+ * H_l, each [B][dims[l+1]] (labfm_mlp_cache_floats gives the size); the
+ * backward pass reads it.  Asynchronous. */
+labfm_err labfm_mlp_forward(void* ctx, const labfm_mlp* net, const float* in, int64_t B, float* out, float* cache,
+                            int denorm, void* stream);
+int64_t labfm_mlp_cache_floats(const labfm_mlp* net, int64_t B);
+
+/* Backward pass: given dLoss/d(out) (dout, FP32 [B][dims[n_layers]], the
+ * output before de-normalisation) and the forward cache of the same in,
+ * writes dLoss/dW_l and dLoss/db_l (overwritten, not accumulated).
+ * Asynchronous. */
+labfm_err labfm_mlp_backward(void* ctx, const labfm_mlp* net, const float* in, const float* cache, const float* dout,
+                             int64_t B, const labfm_mlp_grads* grads, void* stream);
+
+/* Moment-residual loss of eq. (lsys) for the network output y [B][nops p]:
+ * Psi_s = mu + sd * y_s, loss[s] = sum_d |M_s Psi^d_s - C^d|^2 (FP64, [B]),
+ * dy = d(mean_s loss[s]) / dy (FP32 [B][nops p]).  M: FP32 [B][p][p], row =
+ * monomial (M = sum_j X(d_j) W(d_j)^T, eq. disc_form).  Asynchronous. */
+labfm_err labfm_mlp_moment_loss(void* ctx, const float* y, const float* M, const float* mu, const float* sd,
+                                int order, unsigned ops, int64_t B, float* dy, double* loss, void* stream);
+
+/* One Adam step (step number t >= 1) on count FP32 parameters with their
+ * moments m, v; param_bf16 (optional) receives the updated values in BF16.
+ * Asynchronous. */
+labfm_err labfm_mlp_adam(void* ctx, float* param, const float* grad, float* m, float* v, void* param_bf16,
+                         int64_t count, const labfm_adam* hp, int64_t t, void* stream);
+
+/* dst (BF16) = src (FP32, round to nearest even), count elements.  Asynchronous. */
+labfm_err labfm_mlp_cast_bf16(void* ctx, const float* src, void* dst, int64_t count, void* stream);
+
 /* Kernel timing for measurement: while enabled, HIP events are recorded on
  * the launch stream around each kernel the library launches (outside graph
  * capture).  labfm_timing_read waits for the recorded kernels whose name
  * contains `filter` (NULL: all), returns their count and summed duration in
  * milliseconds, and forgets them.  Kernel names: neigh_count, neigh_fill,
  * weights64_k1..k8, weights32_k1..k8, apply_f32, apply_f64, step_graph,
- * step_direct. */
+ * step_direct, mlp_features, mlp_forward, mlp_backward, mlp_loss, mlp_adam. */
 labfm_err labfm_timing_enable(void* ctx, int enable);
 labfm_err labfm_timing_read(void* ctx, const char* filter, int64_t* launches, double* total_ms);
 

@@ -18,12 +18,14 @@ LIB_PATH = os.path.join(HERE, "liblabfm.so")
 ABF_HERMITE, ABF_PAPER = 0, 1
 RBF_WENDLAND_C2, RBF_CONE, RBF_QUADRATIC, RBF_WENDLAND_C6, RBF_GAUSSIAN = 0, 1, 2, 3, 4
 OP_DX, OP_DY, OP_LAP, OP_BIHARM, OP_TRIHARM = 1, 2, 4, 8, 16
-PREC_FP64, PREC_MIXED = 0, 1
+PREC_FP64, PREC_MIXED, PREC_MLP = 0, 1, 2
 ST_OK, ST_NOT_CONVERGED, ST_SINGULAR, ST_TOO_FEW, ST_DEGENERATE, ST_ORDER_TOO_LOW, ST_TOO_MANY = range(7)
 MAX_NEIGHBOURS = 128
 EXPORTED = sorted(["labfm_last_error", "labfm_create", "labfm_destroy", "labfm_build_neighbours", "labfm_weights",
                    "labfm_combine", "labfm_apply_operator", "labfm_step", "labfm_timing_enable",
-                   "labfm_timing_read"])
+                   "labfm_timing_read", "labfm_mlp_features", "labfm_mlp_forward", "labfm_mlp_cache_floats",
+                   "labfm_mlp_backward", "labfm_mlp_moment_loss", "labfm_mlp_adam", "labfm_mlp_cast_bf16"])
+MLP_MAX_LAYERS = 8
 
 
 class LabfmError(RuntimeError):
@@ -34,9 +36,24 @@ class Domain(C.Structure):
     _fields_ = [("lo", C.c_double * 2), ("hi", C.c_double * 2), ("periodic", C.c_int * 2)]
 
 
+class MLPDesc(C.Structure):
+    _fields_ = [("n_layers", C.c_int), ("dims", C.c_int * (MLP_MAX_LAYERS + 1)), ("W", C.c_void_p * MLP_MAX_LAYERS),
+                ("b", C.c_void_p * MLP_MAX_LAYERS), ("mu", C.c_void_p), ("sd", C.c_void_p), ("order", C.c_int),
+                ("ops", C.c_uint), ("kmax", C.c_int)]
+
+
+class MLPGrads(C.Structure):
+    _fields_ = [("W", C.c_void_p * MLP_MAX_LAYERS), ("b", C.c_void_p * MLP_MAX_LAYERS)]
+
+
+class Adam(C.Structure):
+    _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double)]
+
+
 class WOpts(C.Structure):
     _fields_ = [("abf", C.c_int), ("rbf", C.c_int), ("sigma", C.c_double), ("ops", C.c_uint),
-                ("prec", C.c_int), ("tol_stop", C.c_double), ("tol_pass", C.c_double), ("max_iters", C.c_int)]
+                ("prec", C.c_int), ("tol_stop", C.c_double), ("tol_pass", C.c_double), ("max_iters", C.c_int),
+                ("mlp", C.POINTER(MLPDesc))]
 
 
 class StepPlan(C.Structure):
@@ -67,11 +84,19 @@ def load_library(path=LIB_PATH):
     L.labfm_combine.argtypes = [vp, vp, C.c_int, C.POINTER(dp), i64, vp, vp, vp]
     L.labfm_apply_operator.argtypes = [vp, vp, vp, i64, i64, C.c_int, vp, C.c_int, vp, vp, vp]
     L.labfm_step.argtypes = [vp, C.POINTER(StepPlan), vp, vp, C.c_int, C.c_int, vp]
+    L.labfm_mlp_features.argtypes = [vp, vp, vp, i64, C.POINTER(Domain), vp, vp, vp, C.c_int, vp, vp]
+    L.labfm_mlp_forward.argtypes = [vp, C.POINTER(MLPDesc), vp, i64, vp, vp, C.c_int, vp]
+    L.labfm_mlp_cache_floats.argtypes = [C.POINTER(MLPDesc), i64]
+    L.labfm_mlp_backward.argtypes = [vp, C.POINTER(MLPDesc), vp, vp, vp, i64, C.POINTER(MLPGrads), vp]
+    L.labfm_mlp_moment_loss.argtypes = [vp, vp, vp, vp, vp, C.c_int, C.c_uint, i64, vp, vp, vp]
+    L.labfm_mlp_adam.argtypes = [vp, vp, vp, vp, vp, vp, i64, C.POINTER(Adam), i64, vp]
+    L.labfm_mlp_cast_bf16.argtypes = [vp, vp, vp, i64, vp]
     L.labfm_timing_enable.argtypes = [vp, C.c_int]
     L.labfm_timing_read.argtypes = [vp, C.c_char_p, C.POINTER(i64), C.POINTER(dp)]
     for name in EXPORTED:
         if name != "labfm_last_error":
             getattr(L, name).restype = C.c_int
+    L.labfm_mlp_cache_floats.restype = C.c_int64
     _lib = L
     return L
 
@@ -165,8 +190,11 @@ class Context:
     # ------------------------------------------------------------------ weights
     def weights(self, x, y, R, order, row_ptr, col, domain, ops=OP_DX | OP_DY | OP_LAP, abf=ABF_HERMITE,
                 rbf=RBF_WENDLAND_C2, sigma=1.0, prec=PREC_FP64, tol_stop=1e-13, tol_pass=1e-10, max_iters=5,
-                want64=True, want32=False, out=None):
-        """Weights [nops, nnz] (FP64 and/or FP32), status[n] int8, resid[n] f32, iters[n] int8."""
+                want64=True, want32=False, out=None, mlp=None):
+        """Weights [nops, nnz] (FP64 and/or FP32), status[n] int8, resid[n] f32, iters[n] int8.
+
+        prec=PREC_MLP starts the refinement of the network's order from
+        `mlp` (an MLP) instead of from a first solve."""
         torch = self.torch
         n = x.numel()
         nnz = col.numel()
@@ -181,7 +209,13 @@ class Context:
         else:
             w64, w32, status, resid, iters = out
         o = WOpts(int(abf), int(rbf), float(sigma), int(ops), int(prec), float(tol_stop), float(tol_pass),
-                  int(max_iters))
+                  int(max_iters), None)
+        desc = None
+        if prec == PREC_MLP:
+            if mlp is None:
+                raise LabfmError("PREC_MLP needs a network (mlp=...)")
+            desc = mlp.desc()
+            o.mlp = C.pointer(desc)
         dom = make_domain(domain)
         _check(self.lib.labfm_weights(self.h, _ptr(x), _ptr(y), n, C.byref(dom), _ptr(R), _ptr(order),
                                       _ptr(row_ptr), _ptr(col), nnz, C.byref(o), _ptr(w64), _ptr(w32),
@@ -214,6 +248,17 @@ class Context:
                                              _ptr(u), _ptr(out), _stream(torch)), "labfm_apply_operator")
         return out if w.dim() == 2 else out[0]
 
+    # ------------------------------------------------------------------ learned warm start
+    def mlp_features(self, x, y, R, row_ptr, col, domain, kmax=64, out=None):
+        """[n, 3 kmax] FP32 stencil features (nearest kmax neighbours by scaled distance)."""
+        torch = self.torch
+        n = x.numel()
+        feat = out if out is not None else torch.empty((n, 3 * kmax), dtype=torch.float32, device=x.device)
+        dom = make_domain(domain)
+        _check(self.lib.labfm_mlp_features(self.h, _ptr(x), _ptr(y), n, C.byref(dom), _ptr(R), _ptr(row_ptr),
+                                           _ptr(col), int(kmax), _ptr(feat), _stream(torch)), "labfm_mlp_features")
+        return feat
+
     # ------------------------------------------------------------------ time stepping
     def step(self, row_ptr, col, w_lin, w_bh, gamma, dt, u, nsteps, scratch=None, use_graph=True):
         """Advance u in place by nsteps RK4 steps of du/dt = L_lin u - gamma B(B u)."""
@@ -227,3 +272,128 @@ class Context:
         _check(self.lib.labfm_step(self.h, C.byref(plan), _ptr(u), _ptr(scratch), int(nsteps), int(bool(use_graph)),
                                    _stream(torch)), "labfm_step")
         return u
+
+
+class MLP:
+    """Warm-start network for the weight solve (parameters as device tensors).
+
+    dims = (3 kmax, hidden..., nops * p(order)); SiLU between layers.  FP32
+    master weights with BF16 copies for the matrix cores, FP32 biases, Adam
+    moments, and the output de-normalisation Psi = mu + sd * y.  Every step
+    (forward, backward, loss, Adam, cast) runs in liblabfm.so."""
+
+    def __init__(self, ctx, dims=(192, 256, 256, 256, 132), order=8, ops=OP_DX | OP_DY | OP_LAP, kmax=64, seed=0,
+                 out_scale=0.01):
+        torch = ctx.torch
+        self.ctx = ctx
+        self.dims = tuple(int(d) for d in dims)
+        self.L = len(self.dims) - 1
+        if self.L < 1 or self.L > MLP_MAX_LAYERS:
+            raise LabfmError("1..8 layers")
+        self.order, self.ops, self.kmax = int(order), int(ops), int(kmax)
+        dev = torch.device("cuda", ctx.device)
+        g = torch.Generator().manual_seed(int(seed))
+        # He-normal initial weights (the last layer scaled by out_scale, so that
+        # an untrained network starts near Psi = mu), zero biases
+        self.W = [(torch.randn((self.dims[l + 1], self.dims[l]), generator=g, dtype=torch.float64) *
+                   (2.0 / self.dims[l]) ** 0.5 * (out_scale if l == self.L - 1 else 1.0)).to(torch.float32).to(dev)
+                  for l in range(self.L)]
+        self.b = [torch.zeros(self.dims[l + 1], dtype=torch.float32, device=dev) for l in range(self.L)]
+        self.Wb = [torch.empty(w.shape, dtype=torch.bfloat16, device=dev) for w in self.W]
+        self.mu = torch.zeros(self.dims[-1], dtype=torch.float32, device=dev)
+        self.sd = torch.ones(self.dims[-1], dtype=torch.float32, device=dev)
+        self.mW = [torch.zeros_like(w) for w in self.W]
+        self.vW = [torch.zeros_like(w) for w in self.W]
+        self.mb = [torch.zeros_like(b) for b in self.b]
+        self.vb = [torch.zeros_like(b) for b in self.b]
+        self.gW = [torch.empty_like(w) for w in self.W]
+        self.gb = [torch.empty_like(b) for b in self.b]
+        self.t = 0
+        self.sync_bf16()
+
+    def sync_bf16(self):
+        """BF16 copies of the FP32 master weights."""
+        for w, wb in zip(self.W, self.Wb):
+            _check(self.ctx.lib.labfm_mlp_cast_bf16(self.ctx.h, _ptr(w), _ptr(wb), w.numel(),
+                                                    _stream(self.ctx.torch)), "labfm_mlp_cast_bf16")
+
+    def set_output_scaling(self, mu, sd):
+        torch = self.ctx.torch
+        self.mu.copy_(torch.as_tensor(mu, dtype=torch.float32))
+        self.sd.copy_(torch.as_tensor(sd, dtype=torch.float32))
+
+    def desc(self):
+        d = MLPDesc()
+        d.n_layers = self.L
+        for l, v in enumerate(self.dims):
+            d.dims[l] = v
+        for l in range(self.L):
+            d.W[l] = self.Wb[l].data_ptr()
+            d.b[l] = self.b[l].data_ptr()
+        d.mu, d.sd = self.mu.data_ptr(), self.sd.data_ptr()
+        d.order, d.ops, d.kmax = self.order, self.ops, self.kmax
+        self._desc = d  # keep alive while the call is enqueued
+        return d
+
+    def cache_for(self, B):
+        torch = self.ctx.torch
+        d = self.desc()
+        nf = self.ctx.lib.labfm_mlp_cache_floats(C.byref(d), int(B))
+        return torch.empty(max(nf, 1), dtype=torch.float32, device=self.W[0].device)
+
+    def forward(self, X, cache=None, denorm=False, out=None):
+        torch = self.ctx.torch
+        B = X.shape[0]
+        if out is None:
+            out = torch.empty((B, self.dims[-1]), dtype=torch.float32, device=X.device)
+        d = self.desc()
+        _check(self.ctx.lib.labfm_mlp_forward(self.ctx.h, C.byref(d), _ptr(X), B, _ptr(out), _ptr(cache),
+                                              int(bool(denorm)), _stream(torch)), "labfm_mlp_forward")
+        return out
+
+    def backward(self, X, cache, dout):
+        """Fills self.gW / self.gb with dLoss/dW, dLoss/db."""
+        d = self.desc()
+        gr = MLPGrads()
+        for l in range(self.L):
+            gr.W[l] = self.gW[l].data_ptr()
+            gr.b[l] = self.gb[l].data_ptr()
+        _check(self.ctx.lib.labfm_mlp_backward(self.ctx.h, C.byref(d), _ptr(X), _ptr(cache), _ptr(dout), X.shape[0],
+                                               C.byref(gr), _stream(self.ctx.torch)), "labfm_mlp_backward")
+        return self.gW, self.gb
+
+    def moment_loss(self, y, M, loss=None, dy=None):
+        """Per-sample moment residual |M (mu + sd y) - C|^2 (FP64 [B]) and d(mean)/dy."""
+        torch = self.ctx.torch
+        B = y.shape[0]
+        if loss is None:
+            loss = torch.empty(B, dtype=torch.float64, device=y.device)
+        if dy is None:
+            dy = torch.empty_like(y)
+        _check(self.ctx.lib.labfm_mlp_moment_loss(self.ctx.h, _ptr(y), _ptr(M), _ptr(self.mu), _ptr(self.sd),
+                                                  self.order, self.ops, B, _ptr(dy), _ptr(loss), _stream(torch)),
+               "labfm_mlp_moment_loss")
+        return loss, dy
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        """One Adam step on every parameter (gradients from the last backward)."""
+        self.t += 1
+        hp = Adam(float(lr), float(beta1), float(beta2), float(eps))
+        st = _stream(self.ctx.torch)
+        for l in range(self.L):
+            _check(self.ctx.lib.labfm_mlp_adam(self.ctx.h, _ptr(self.W[l]), _ptr(self.gW[l]), _ptr(self.mW[l]),
+                                               _ptr(self.vW[l]), _ptr(self.Wb[l]), self.W[l].numel(), C.byref(hp),
+                                               self.t, st), "labfm_mlp_adam")
+            _check(self.ctx.lib.labfm_mlp_adam(self.ctx.h, _ptr(self.b[l]), _ptr(self.gb[l]), _ptr(self.mb[l]),
+                                               _ptr(self.vb[l]), None, self.b[l].numel(), C.byref(hp), self.t, st),
+                   "labfm_mlp_adam")
+
+    def train_step(self, X, M, lr, cache=None):
+        """forward -> moment loss -> backward -> Adam on one batch; returns the per-sample losses."""
+        if cache is None:
+            cache = self.cache_for(X.shape[0])
+        y = self.forward(X, cache=cache)
+        loss, dy = self.moment_loss(y, M)
+        self.backward(X, cache, dy)
+        self.adam(lr)
+        return loss

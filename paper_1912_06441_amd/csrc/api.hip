@@ -53,6 +53,36 @@ GridSpec make_grid(const labfm_domain* d, int64_t n) {
     return g;
 }
 
+int popcount5(unsigned ops) {
+    int k = 0;
+    for (int b = 0; b < 5; ++b) k += (ops >> b) & 1u;
+    return k;
+}
+
+// structural checks of a network description (device pointers non-NULL, sizes in range)
+bool mlp_ok(const labfm_mlp* net, std::string& why) {
+    if (!net) return why = "network is NULL", false;
+    if (net->n_layers < 1 || net->n_layers > LABFM_MLP_MAX_LAYERS) return why = "n_layers must be 1..8", false;
+    for (int l = 0; l <= net->n_layers; ++l)
+        if (net->dims[l] < 1 || net->dims[l] > 4096) return why = "layer widths must be 1..4096", false;
+    for (int l = 0; l < net->n_layers; ++l)
+        if (!net->W[l] || !net->b[l]) return why = "NULL weight or bias", false;
+    return true;
+}
+
+// a network that serves the weight solve: features in, Psi of `ops` at `order` out
+bool mlp_serves(const labfm_mlp* net, std::string& why) {
+    if (!mlp_ok(net, why)) return false;
+    if (net->kmax < 1 || net->kmax > LABFM_MAX_NEIGHBOURS) return why = "kmax must be 1..128", false;
+    if (net->dims[0] != 3 * net->kmax) return why = "dims[0] must be 3 kmax", false;
+    if (net->order < 1 || net->order > LABFM_MAX_ORDER) return why = "order must be 1..8", false;
+    if (net->ops == 0 || (net->ops & ~31u)) return why = "bad ops", false;
+    const int p = (net->order * net->order + 3 * net->order) / 2;
+    if (net->dims[net->n_layers] != popcount5(net->ops) * p) return why = "output width must be nops * p(order)", false;
+    if (!net->mu || !net->sd) return why = "mu and sd are required", false;
+    return true;
+}
+
 bool domain_ok(const labfm_domain* d) {
     return d && std::isfinite(d->lo[0]) && std::isfinite(d->lo[1]) && std::isfinite(d->hi[0]) &&
            std::isfinite(d->hi[1]) && d->hi[0] > d->lo[0] && d->hi[1] > d->lo[1];
@@ -107,7 +137,8 @@ labfm_err labfm_destroy(void* ctx) {
         hipEventDestroy(t.a);
         hipEventDestroy(t.b);
     }
-    Scratch* all[] = {&c->grid_count, &c->grid_idx, &c->node_cell, &c->counts, &c->scan_tmp, &c->worklist, &c->mixed};
+    Scratch* all[] = {&c->grid_count, &c->grid_idx, &c->node_cell, &c->counts, &c->scan_tmp, &c->worklist,
+                      &c->mixed,      &c->mlp_act,  &c->mlp_feat,  &c->mlp_psi, &c->mlp_part};
     for (Scratch* s : all)
         if (s->p) hipFree(s->p);
     delete c;
@@ -158,7 +189,13 @@ labfm_err labfm_weights(void* ctx, const double* x, const double* y, int64_t n, 
     if (!w64 && !w32) return fail(LABFM_EINVAL, "labfm_weights: w64 and w32 are both NULL");
     if (n > 0 && (!x || !y || !R || !order || !row_ptr || !status || (nnz > 0 && !col)))
         return fail(LABFM_EINVAL, "labfm_weights: NULL array");
-    if (opt->prec != LABFM_PREC_FP64 && opt->prec != LABFM_PREC_MIXED) return fail(LABFM_EINVAL, "labfm_weights: bad prec");
+    if (opt->prec != LABFM_PREC_FP64 && opt->prec != LABFM_PREC_MIXED && opt->prec != LABFM_PREC_MLP)
+        return fail(LABFM_EINVAL, "labfm_weights: bad prec");
+    if (opt->prec == LABFM_PREC_MLP) {
+        std::string why;
+        if (!mlp_serves(opt->mlp, why)) return fail(LABFM_EINVAL, "labfm_weights: network: " + why);
+        if (opt->mlp->ops != opt->ops) return fail(LABFM_EINVAL, "labfm_weights: network ops differ from opt->ops");
+    }
     Context* c = (Context*)ctx;
     DeviceGuard g(c->device);
     if (!g.ok) return fail(LABFM_EHIP, "labfm_weights: hipSetDevice failed");
@@ -187,13 +224,18 @@ labfm_err labfm_weights(void* ctx, const double* x, const double* y, int64_t n, 
     a.max_iters = opt->max_iters;
     a.iters_offset = 0;
     a.max_iters32 = 30;
+    a.psi0 = nullptr;
+    a.psi0_order = 0;
+    a.psi0_ld = 0;
     a.w64 = w64;
     a.w32 = w32;
     a.status = status;
     a.resid = resid;
     a.iters = iters;
     hipStream_t st = (hipStream_t)stream;
-    return opt->prec == LABFM_PREC_FP64 ? weights_fp64(c, a, st) : weights_mixed(c, a, st);
+    if (opt->prec == LABFM_PREC_FP64) return weights_fp64(c, a, st);
+    if (opt->prec == LABFM_PREC_MIXED) return weights_mixed(c, a, st);
+    return weights_mlp(c, a, opt->mlp, st);
 }
 
 labfm_err labfm_combine(void* ctx, const double* w64, int nsets, const double* coef, int64_t nnz, double* out64,
@@ -231,6 +273,92 @@ labfm_err labfm_step(void* ctx, const labfm_step_plan* plan, void* u, void* scra
     Context* c = (Context*)ctx;
     DeviceGuard g(c->device);
     return step_launch(c, plan, u, scratch, nsteps, use_graph, (hipStream_t)stream);
+}
+
+labfm_err labfm_mlp_features(void* ctx, const double* x, const double* y, int64_t n, const labfm_domain* dom,
+                             const double* R, const int64_t* row_ptr, const int32_t* col, int kmax, float* feat,
+                             void* stream) {
+    if (!ctx) return fail(LABFM_EINVAL, "labfm_mlp_features: ctx is NULL");
+    if (n < 0 || n > INT32_MAX) return fail(LABFM_EINVAL, "labfm_mlp_features: n out of range");
+    if (kmax < 1 || kmax > LABFM_MAX_NEIGHBOURS) return fail(LABFM_EINVAL, "labfm_mlp_features: kmax must be 1..128");
+    if (!domain_ok(dom)) return fail(LABFM_EINVAL, "labfm_mlp_features: bad domain");
+    if (n > 0 && (!x || !y || !R || !row_ptr || !col || !feat)) return fail(LABFM_EINVAL, "labfm_mlp_features: NULL array");
+    Context* c = (Context*)ctx;
+    DeviceGuard g(c->device);
+    return mlp_features(c, x, y, R, row_ptr, col, 0, n, dom->hi[0] - dom->lo[0], dom->hi[1] - dom->lo[1],
+                        dom->periodic[0] != 0, dom->periodic[1] != 0, kmax, feat, (hipStream_t)stream);
+}
+
+int64_t labfm_mlp_cache_floats(const labfm_mlp* net, int64_t B) {
+    std::string why;
+    if (!mlp_ok(net, why) || B < 0) return -1;
+    return (int64_t)mlp_cache_floats(net, B);
+}
+
+labfm_err labfm_mlp_forward(void* ctx, const labfm_mlp* net, const float* in, int64_t B, float* out, float* cache,
+                            int denorm, void* stream) {
+    std::string why;
+    if (!ctx) return fail(LABFM_EINVAL, "labfm_mlp_forward: ctx is NULL");
+    if (!mlp_ok(net, why)) return fail(LABFM_EINVAL, "labfm_mlp_forward: " + why);
+    if (B < 0 || B > INT32_MAX) return fail(LABFM_EINVAL, "labfm_mlp_forward: B out of range");
+    if (B > 0 && (!in || !out)) return fail(LABFM_EINVAL, "labfm_mlp_forward: NULL array");
+    if (denorm && (!net->mu || !net->sd)) return fail(LABFM_EINVAL, "labfm_mlp_forward: denorm needs mu and sd");
+    Context* c = (Context*)ctx;
+    DeviceGuard g(c->device);
+    return mlp_forward(c, net, in, B, out, cache, denorm, (hipStream_t)stream);
+}
+
+labfm_err labfm_mlp_backward(void* ctx, const labfm_mlp* net, const float* in, const float* cache, const float* dout,
+                             int64_t B, const labfm_mlp_grads* grads, void* stream) {
+    std::string why;
+    if (!ctx || !grads) return fail(LABFM_EINVAL, "labfm_mlp_backward: ctx or grads is NULL");
+    if (!mlp_ok(net, why)) return fail(LABFM_EINVAL, "labfm_mlp_backward: " + why);
+    if (B < 0 || B > INT32_MAX) return fail(LABFM_EINVAL, "labfm_mlp_backward: B out of range");
+    if (B > 0 && (!in || !dout || (net->n_layers > 1 && !cache)))
+        return fail(LABFM_EINVAL, "labfm_mlp_backward: NULL array");
+    for (int l = 0; l < net->n_layers; ++l)
+        if (!grads->W[l] || !grads->b[l]) return fail(LABFM_EINVAL, "labfm_mlp_backward: NULL gradient buffer");
+    Context* c = (Context*)ctx;
+    DeviceGuard g(c->device);
+    return mlp_backward(c, net, in, cache, dout, B, grads, (hipStream_t)stream);
+}
+
+labfm_err labfm_mlp_moment_loss(void* ctx, const float* y, const float* M, const float* mu, const float* sd,
+                                int order, unsigned ops, int64_t B, float* dy, double* loss, void* stream) {
+    if (!ctx) return fail(LABFM_EINVAL, "labfm_mlp_moment_loss: ctx is NULL");
+    if (order < 1 || order > LABFM_MAX_ORDER) return fail(LABFM_EINVAL, "labfm_mlp_moment_loss: order must be 1..8");
+    if (ops == 0 || (ops & ~31u)) return fail(LABFM_EINVAL, "labfm_mlp_moment_loss: bad ops");
+    if (B < 0) return fail(LABFM_EINVAL, "labfm_mlp_moment_loss: B < 0");
+    if (B > 0 && (!y || !M || !mu || !sd || !dy || !loss)) return fail(LABFM_EINVAL, "labfm_mlp_moment_loss: NULL array");
+    const int minord[5] = {1, 1, 2, 4, 6};
+    for (int b = 0; b < 5; ++b)
+        if (((ops >> b) & 1u) && order < minord[b])
+            return fail(LABFM_EINVAL, "labfm_mlp_moment_loss: order too low for the operators");
+    Context* c = (Context*)ctx;
+    DeviceGuard g(c->device);
+    return mlp_moment_loss(c, y, M, mu, sd, order, ops, B, dy, loss, (hipStream_t)stream);
+}
+
+labfm_err labfm_mlp_adam(void* ctx, float* param, const float* grad, float* m, float* v, void* param_bf16,
+                         int64_t count, const labfm_adam* hp, int64_t t, void* stream) {
+    if (!ctx || !hp) return fail(LABFM_EINVAL, "labfm_mlp_adam: ctx or hp is NULL");
+    if (count < 0 || t < 1) return fail(LABFM_EINVAL, "labfm_mlp_adam: count < 0 or t < 1");
+    if (count > 0 && (!param || !grad || !m || !v)) return fail(LABFM_EINVAL, "labfm_mlp_adam: NULL array");
+    if (!(hp->beta1 >= 0.0 && hp->beta1 < 1.0 && hp->beta2 >= 0.0 && hp->beta2 < 1.0 && hp->eps > 0.0 &&
+          std::isfinite(hp->lr)))
+        return fail(LABFM_EINVAL, "labfm_mlp_adam: bad hyper-parameters");
+    Context* c = (Context*)ctx;
+    DeviceGuard g(c->device);
+    return mlp_adam(c, param, grad, m, v, param_bf16, count, hp, t, (hipStream_t)stream);
+}
+
+labfm_err labfm_mlp_cast_bf16(void* ctx, const float* src, void* dst, int64_t count, void* stream) {
+    if (!ctx) return fail(LABFM_EINVAL, "labfm_mlp_cast_bf16: ctx is NULL");
+    if (count < 0) return fail(LABFM_EINVAL, "labfm_mlp_cast_bf16: count < 0");
+    if (count > 0 && (!src || !dst)) return fail(LABFM_EINVAL, "labfm_mlp_cast_bf16: NULL array");
+    Context* c = (Context*)ctx;
+    DeviceGuard g(c->device);
+    return mlp_cast_bf16(src, dst, count, (hipStream_t)stream);
 }
 
 labfm_err labfm_timing_enable(void* ctx, int enable) {

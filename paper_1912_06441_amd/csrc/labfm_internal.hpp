@@ -38,6 +38,10 @@ struct Context {
     Scratch scan_tmp;     // block sums for scans
     Scratch worklist;     // per-order work lists (int32) + counters
     Scratch mixed;        // mixed-precision retry list
+    Scratch mlp_act;      // network activations (two [B][max width] FP32 buffers)
+    Scratch mlp_feat;     // stencil features of one chunk of nodes
+    Scratch mlp_psi;      // network output Psi0 of every node [n][outputs]
+    Scratch mlp_part;     // column-sum partials of the bias gradients
     // cached RK4 step graph (replayed while plan, buffers and stream are unchanged)
     hipGraphExec_t step_exec = nullptr;
     hipStream_t step_stream = nullptr;
@@ -120,6 +124,9 @@ struct WeightArgs {
     int8_t* iters;
     int iters_offset;  // added to iters (marks nodes recomputed on the FP64 path)
     int max_iters32;   // refinement updates allowed on the mixed path
+    const float* psi0; // warm start of the mixed path: Psi0 of node i at psi0[i * psi0_ld] (or NULL)
+    int psi0_order;    // order of the nodes that use psi0
+    int psi0_ld;
 };
 labfm_err weights_fp64(Context* c, const WeightArgs& a, hipStream_t st);
 labfm_err build_order_lists(Context* c, const int8_t* order, int64_t n, hipStream_t st, int32_t** list,
@@ -130,6 +137,22 @@ labfm_err weights_invalid_orders(const WeightArgs& a, const int32_t* list, const
 labfm_err weights_fp64_lists(Context* c, const WeightArgs& a, const int32_t* list, const int32_t* off,
                              const int32_t* cnt, hipStream_t st);
 labfm_err weights_mixed(Context* c, const WeightArgs& a, hipStream_t st);
+
+// ---- learned warm start
+labfm_err mlp_features(Context* c, const double* x, const double* y, const double* R, const int64_t* row_ptr,
+                       const int32_t* col, int64_t first, int64_t count, double Lx, double Ly, int perx, int pery,
+                       int kmax, float* feat, hipStream_t st);
+size_t mlp_cache_floats(const labfm_mlp* net, int64_t B);
+labfm_err mlp_forward(Context* c, const labfm_mlp* net, const float* in, int64_t B, float* out, float* cache,
+                      int denorm, hipStream_t st);
+labfm_err mlp_backward(Context* c, const labfm_mlp* net, const float* in, const float* cache, const float* dout,
+                       int64_t B, const labfm_mlp_grads* gr, hipStream_t st);
+labfm_err mlp_moment_loss(Context* c, const float* y, const float* M, const float* mu, const float* sd, int order,
+                          unsigned opbits, int64_t B, float* dy, double* loss, hipStream_t st);
+labfm_err mlp_adam(Context* c, float* p, const float* g, float* m, float* v, void* pb, int64_t n, const labfm_adam* hp,
+                   int64_t t, hipStream_t st);
+labfm_err mlp_cast_bf16(const float* src, void* dst, int64_t n, hipStream_t st);
+labfm_err weights_mlp(Context* c, const WeightArgs& a, const labfm_mlp* net, hipStream_t st);
 
 // ---- application and time stepping
 labfm_err apply_launch(Context* c, const int64_t* row_ptr, const int32_t* col, int64_t n, int64_t nnz, int nops,

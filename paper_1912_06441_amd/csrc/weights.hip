@@ -277,7 +277,10 @@ __global__ __launch_bounds__(64) void k_weights_fp64(WeightArgs a, OpList ops, c
                     }
                     double rm = 0.0;
 #pragma unroll
-                    for (int d = 0; d < MAXOPS; ++d) rm = fmax(rm, fabs(r[d]));
+                    for (int d = 0; d < MAXOPS; ++d) {
+                        const double ar = fabs(r[d]);
+                        rm = (ar > rm || ar != ar) ? ar : rm;  // NaN propagates (fmax would drop it)
+                    }
                     if (!isfinite(rm)) rm = INFINITY;
                     res = wave_max(rm);
                     if (!(res > a.tol_stop) || iters >= a.max_iters) break;

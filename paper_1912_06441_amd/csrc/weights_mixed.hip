@@ -8,7 +8,9 @@
 //   * FP64 weights w = W Psi, FP64 moment residual r = C - X^T w and FP64
 //     weight refinement w += W (M32^-1 r) until ||r|| <= tol_stop.
 // Nodes whose refinement does not reach tol_pass are appended to a per-order
-// retry list and recomputed by the FP64 kernels.
+// retry list and recomputed by the FP64 kernels.  With a warm start (psi0),
+// nodes of that order begin the refinement from W Psi0 instead of from a
+// first solve with the FP32 factors.
 //
 // Launch shape: one 64-lane wavefront per node system, persistent over the
 // per-order work list.  M tiles: lane l of the 16x16x4 MFMA holds A[l%16][l/16]
@@ -219,15 +221,21 @@ __global__ __launch_bounds__(64) void k_weights_mixed(WeightArgs a, OpList ops, 
             __syncthreads();
 
             if (status == LABFM_ST_OK) {
-                // ---- Psi from the FP32 factors, weights in FP64
-                double b[MAXOPS];
+                // ---- Psi from the FP32 factors (or the warm start), weights in FP64
+                if (a.psi0 && a.psi0_order == K) {
+                    if (lane < P)
+                        for (int d = 0; d < nops; ++d)
+                            sPsi[d][lane] = (double)a.psi0[i * (int64_t)a.psi0_ld + d * P + lane];
+                } else {
+                    double b[MAXOPS];
 #pragma unroll
-                for (int d = 0; d < MAXOPS; ++d) b[d] = (d < nops && lane < P) ? target(ops.op[d], lane) : 0.0;
-                lu_solve<P, LD, float>(sM, sRs, sCs, sPerm, b, nops);
-                if (lane < P)
+                    for (int d = 0; d < MAXOPS; ++d) b[d] = (d < nops && lane < P) ? target(ops.op[d], lane) : 0.0;
+                    lu_solve<P, LD, float>(sM, sRs, sCs, sPerm, b, nops);
+                    if (lane < P)
 #pragma unroll
-                    for (int d = 0; d < MAXOPS; ++d)
-                        if (d < nops) sPsi[d][lane] = b[d];
+                        for (int d = 0; d < MAXOPS; ++d)
+                            if (d < nops) sPsi[d][lane] = b[d];
+                }
                 __syncthreads();
                 double wreg[JS][MAXOPS];
 #pragma unroll
@@ -282,7 +290,10 @@ __global__ __launch_bounds__(64) void k_weights_mixed(WeightArgs a, OpList ops, 
                     }
                     double rm = 0.0;
 #pragma unroll
-                    for (int d = 0; d < MAXOPS; ++d) rm = fmax(rm, fabs(r[d]));
+                    for (int d = 0; d < MAXOPS; ++d) {
+                        const double ar = fabs(r[d]);
+                        rm = (ar > rm || ar != ar) ? ar : rm;  // NaN propagates (fmax would drop it)
+                    }
                     if (!isfinite(rm)) rm = INFINITY;
                     res = wave_max(rm);
                     if (!(res > a.tol_stop) || iters >= a.max_iters32) break;

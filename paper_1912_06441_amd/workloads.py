@@ -109,6 +109,14 @@ def config(name):
         # composed nabla^8 hyperviscosity gamma = beta h^8 / dt.  dt = 0.1 s: at 0.2 s the RK4
         # step map of this node set grows (power iteration: x3.7 per step, a mode localised on
         # the stencils of largest amplification); at 0.1 s every mode decays.
+        # learned warm start, order 8 (p = 44) Hermite x Wendland C2, {dx, dy, lap}: training stencils
+        # from periodic jittered lattices of side train_side, eps ~ U(0, eps_max) per lattice (seeds
+        # train_seed0 + i), R0 = 4.4 s + growth; the network sees the nearest kmax = 64 neighbours.
+        # Evaluation: 1024x1024, eps 0.3, seed 4 (the GPU tests use test_sets lattices and a
+        # test_eval_side^2 evaluation set).
+        "c4": dict(k=8, R_s=4.4, kmax=64, ops=7, dims=(192, 256, 256, 256, 132), train_side=96,
+                   train_seed0=4000, eps_max=0.45, train_sets=218, eval_side=1024, eval_eps=0.3, eval_seed=4,
+                   lr=1e-3, batch=512, test_sets=16, test_epochs=10, test_eval_side=96),
         "c5": dict(n_side=1024, eps=0.3, seed=5, k=6, k_boundary=6, R_s=4.0, periodic=True,
                    a=(1.0, 0.5), nu=1e-3, beta=1e-7, dt_s=0.1, nsteps=1000,
                    x0=(0.5, 0.5), width2=0.01),
