@@ -191,6 +191,47 @@ labfm_err labfm_weights(void* ctx, const double* x, const double* y, int64_t n,
                         const labfm_wopts* opt, double* w64, float* w32, int8_t* status,
                         float* resid, int8_t* iters, void* stream);
 
+/* Batched weights: nsets independent node sets, each with its own arrays,
+ * domain and outputs (layouts as in labfm_weights; col holds indices within
+ * the set).  One persistent kernel per order covers the nodes of every set,
+ * so small and low-order sets share the GPU instead of each filling it alone.
+ * prec FP64 or MIXED (LABFM_PREC_MLP returns LABFM_EUNSUPPORTED).
+ * use_graph != 0: work lists, weight kernels and the FP64 fallback of the
+ *   whole batch are captured once as a HIP graph per (sets, options, stream)
+ *   and replayed by later calls with the same arguments (the graph owns its
+ *   own work-list buffers; replays read the sets' current array contents).
+ * Autotuning (MIXED): the first time an order is seen under (abf, rbf, ops),
+ *   the mixed route (matrix-core assembly + FP32 LU + FP64 refinement, with its
+ *   FP64 retries) and the FP64 route are timed on up to 4096 of its nodes and
+ *   the faster one is used from then on; both routes meet the same residual
+ *   gate.  The first call synchronises `stream` for this; later calls are
+ *   asynchronous.  Total node count < 2^31. */
+typedef struct {
+    const double* x;
+    const double* y;
+    int64_t n;
+    labfm_domain dom;
+    const double* R;
+    const int8_t* order;
+    const int64_t* row_ptr;
+    const int32_t* col;
+    int64_t nnz;
+    double* w64;
+    float* w32;
+    int8_t* status;
+    float* resid;
+    int8_t* iters;
+} labfm_node_set;
+
+labfm_err labfm_weights_batched(void* ctx, int nsets, const labfm_node_set* sets, const labfm_wopts* opt,
+                                int use_graph, void* stream);
+
+/* The autotuner's choice for `order` under (abf, rbf, ops): *route = 0 (not
+ * tuned yet), 1 (mixed kernels) or 2 (FP64 kernels); sample times in ms and
+ * the sample size (nodes), each may be NULL. */
+labfm_err labfm_autotune_query(void* ctx, int abf, int rbf, unsigned ops, int order, int* route, double* ms_mixed,
+                               double* ms_fp64, int64_t* sample);
+
 /* out[s] = sum_k coef[k] * w64[k][s] for s < nnz (a linear combination of
  * weight sets is the weight set of the combined target, C^d being linear).
  * coef: host [nsets]; out64 and/or out32 device [nnz].  Asynchronous. */
@@ -274,7 +315,8 @@ labfm_err labfm_mlp_cast_bf16(void* ctx, const float* src, void* dst, int64_t co
  * contains `filter` (NULL: all), returns their count and summed duration in
  * milliseconds, and forgets them.  Kernel names: neigh_count, neigh_fill,
  * weights64_k1..k8, weights32_k1..k8, apply_f32, apply_f64, step_graph,
- * step_direct, mlp_features, mlp_forward, mlp_backward, mlp_loss, mlp_adam. */
+ * step_direct, mlp_features, mlp_forward, mlp_backward, mlp_loss, mlp_adam,
+ * weights_batch_graph. */
 labfm_err labfm_timing_enable(void* ctx, int enable);
 labfm_err labfm_timing_read(void* ctx, const char* filter, int64_t* launches, double* total_ms);
 

@@ -24,7 +24,8 @@ MAX_NEIGHBOURS = 128
 EXPORTED = sorted(["labfm_last_error", "labfm_create", "labfm_destroy", "labfm_build_neighbours", "labfm_weights",
                    "labfm_combine", "labfm_apply_operator", "labfm_step", "labfm_timing_enable",
                    "labfm_timing_read", "labfm_mlp_features", "labfm_mlp_forward", "labfm_mlp_cache_floats",
-                   "labfm_mlp_backward", "labfm_mlp_moment_loss", "labfm_mlp_adam", "labfm_mlp_cast_bf16"])
+                   "labfm_mlp_backward", "labfm_mlp_moment_loss", "labfm_mlp_adam", "labfm_mlp_cast_bf16",
+                   "labfm_weights_batched", "labfm_autotune_query"])
 MLP_MAX_LAYERS = 8
 
 
@@ -54,6 +55,13 @@ class WOpts(C.Structure):
     _fields_ = [("abf", C.c_int), ("rbf", C.c_int), ("sigma", C.c_double), ("ops", C.c_uint),
                 ("prec", C.c_int), ("tol_stop", C.c_double), ("tol_pass", C.c_double), ("max_iters", C.c_int),
                 ("mlp", C.POINTER(MLPDesc))]
+
+
+class NodeSetDesc(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("n", C.c_int64), ("dom", Domain), ("R", C.c_void_p),
+                ("order", C.c_void_p), ("row_ptr", C.c_void_p), ("col", C.c_void_p), ("nnz", C.c_int64),
+                ("w64", C.c_void_p), ("w32", C.c_void_p), ("status", C.c_void_p), ("resid", C.c_void_p),
+                ("iters", C.c_void_p)]
 
 
 class StepPlan(C.Structure):
@@ -91,6 +99,9 @@ def load_library(path=LIB_PATH):
     L.labfm_mlp_moment_loss.argtypes = [vp, vp, vp, vp, vp, C.c_int, C.c_uint, i64, vp, vp, vp]
     L.labfm_mlp_adam.argtypes = [vp, vp, vp, vp, vp, vp, i64, C.POINTER(Adam), i64, vp]
     L.labfm_mlp_cast_bf16.argtypes = [vp, vp, vp, i64, vp]
+    L.labfm_weights_batched.argtypes = [vp, C.c_int, C.POINTER(NodeSetDesc), C.POINTER(WOpts), C.c_int, vp]
+    L.labfm_autotune_query.argtypes = [vp, C.c_int, C.c_int, C.c_uint, C.c_int, C.POINTER(C.c_int),
+                                       C.POINTER(dp), C.POINTER(dp), C.POINTER(i64)]
     L.labfm_timing_enable.argtypes = [vp, C.c_int]
     L.labfm_timing_read.argtypes = [vp, C.c_char_p, C.POINTER(i64), C.POINTER(dp)]
     for name in EXPORTED:
@@ -221,6 +232,50 @@ class Context:
                                       _ptr(row_ptr), _ptr(col), nnz, C.byref(o), _ptr(w64), _ptr(w32),
                                       _ptr(status), _ptr(resid), _ptr(iters), _stream(torch)), "labfm_weights")
         return w64, w32, status, resid, iters
+
+    def weights_batched(self, sets, ops=OP_DX | OP_DY | OP_LAP, abf=ABF_HERMITE, rbf=RBF_WENDLAND_C2, sigma=1.0,
+                        prec=PREC_MIXED, tol_stop=1e-13, tol_pass=1e-10, max_iters=5, want64=True, want32=False,
+                        use_graph=True, outs=None):
+        """Weights of many node sets in one launch sequence.
+
+        sets: list of dicts with x, y, R, order, row_ptr, col (device tensors)
+        and domain.  Returns a list of (w64, w32, status, resid, iters) per
+        set (allocated unless `outs` gives them)."""
+        torch = self.torch
+        k = nops_of(ops)
+        if outs is None:
+            outs = []
+            for S in sets:
+                n, nnz, dev = S["x"].numel(), S["col"].numel(), S["x"].device
+                outs.append((torch.empty((k, nnz), dtype=torch.float64, device=dev) if want64 else None,
+                             torch.empty((k, nnz), dtype=torch.float32, device=dev) if want32 else None,
+                             torch.empty(n, dtype=torch.int8, device=dev),
+                             torch.empty(n, dtype=torch.float32, device=dev),
+                             torch.empty(n, dtype=torch.int8, device=dev)))
+        table = (NodeSetDesc * len(sets))()
+        for t, (S, o) in enumerate(zip(sets, outs)):
+            d = table[t]
+            d.x, d.y, d.n = S["x"].data_ptr(), S["y"].data_ptr(), S["x"].numel()
+            d.dom = make_domain(S["domain"])
+            d.R, d.order = S["R"].data_ptr(), S["order"].data_ptr()
+            d.row_ptr, d.col, d.nnz = S["row_ptr"].data_ptr(), S["col"].data_ptr(), S["col"].numel()
+            d.w64 = o[0].data_ptr() if o[0] is not None else None
+            d.w32 = o[1].data_ptr() if o[1] is not None else None
+            d.status, d.resid, d.iters = o[2].data_ptr(), o[3].data_ptr(), o[4].data_ptr()
+        o = WOpts(int(abf), int(rbf), float(sigma), int(ops), int(prec), float(tol_stop), float(tol_pass),
+                  int(max_iters), None)
+        _check(self.lib.labfm_weights_batched(self.h, len(sets), table, C.byref(o), int(bool(use_graph)),
+                                              _stream(torch)), "labfm_weights_batched")
+        return outs
+
+    def autotune_query(self, order, ops=OP_DX | OP_DY | OP_LAP, abf=ABF_HERMITE, rbf=RBF_WENDLAND_C2):
+        """(route, ms_mixed, ms_fp64, sample): route 0 untuned, 1 mixed kernels, 2 FP64 kernels."""
+        r = C.c_int(0)
+        a, b = C.c_double(0), C.c_double(0)
+        ns = C.c_int64(0)
+        _check(self.lib.labfm_autotune_query(self.h, int(abf), int(rbf), int(ops), int(order), C.byref(r), C.byref(a),
+                                             C.byref(b), C.byref(ns)), "labfm_autotune_query")
+        return r.value, a.value, b.value, ns.value
 
     def combine(self, w64, coef, want64=True, want32=False):
         torch = self.torch

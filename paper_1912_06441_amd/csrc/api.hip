@@ -92,6 +92,23 @@ bool domain_ok(const labfm_domain* d) {
 
 void set_error(const std::string& msg) { g_last_error = msg; }
 
+// options shared by every node set of a weight computation
+void set_options(WeightArgs& a, const labfm_wopts* opt) {
+    a.abf = opt->abf;
+    a.rbf = opt->rbf;
+    a.sigma = opt->sigma;
+    a.ops = opt->ops;
+    a.nops = popcount5(opt->ops);
+    a.tol_stop = opt->tol_stop;
+    a.tol_pass = opt->tol_pass;
+    a.max_iters = opt->max_iters;
+    a.iters_offset = 0;
+    a.max_iters32 = 30;
+    a.psi0_order = 0;
+    a.psi0_ld = 0;
+}
+
+
 labfm_err ensure(Scratch& s, size_t bytes) {
     if (bytes == 0) bytes = 1;
     if (s.bytes >= bytes) return LABFM_OK;
@@ -133,12 +150,15 @@ labfm_err labfm_destroy(void* ctx) {
     DeviceGuard g(c->device);
     if (c->step_exec) hipStreamSynchronize(c->step_stream);
     release_step_graph(c);
+    if (c->batch.exec) hipStreamSynchronize(c->batch.stream);
+    release_batch(c);
     for (auto& t : c->timed) {
         hipEventDestroy(t.a);
         hipEventDestroy(t.b);
     }
     Scratch* all[] = {&c->grid_count, &c->grid_idx, &c->node_cell, &c->counts, &c->scan_tmp, &c->worklist,
-                      &c->mixed,      &c->mlp_act,  &c->mlp_feat,  &c->mlp_psi, &c->mlp_part};
+                      &c->mixed,      &c->mlp_act,  &c->mlp_feat,  &c->mlp_psi, &c->mlp_part,
+                      &c->batch.d_sets, &c->batch.d_off, &c->batch.wl, &c->batch.rl};
     for (Scratch* s : all)
         if (s->p) hipFree(s->p);
     delete c;
@@ -201,41 +221,75 @@ labfm_err labfm_weights(void* ctx, const double* x, const double* y, int64_t n, 
     if (!g.ok) return fail(LABFM_EHIP, "labfm_weights: hipSetDevice failed");
     if (n == 0) return LABFM_OK;
     WeightArgs a{};
-    a.x = x;
-    a.y = y;
-    a.R = R;
-    a.order = order;
-    a.row_ptr = row_ptr;
-    a.col = col;
-    a.n = n;
-    a.nnz = nnz;
-    a.Lx = dom->hi[0] - dom->lo[0];
-    a.Ly = dom->hi[1] - dom->lo[1];
-    a.perx = dom->periodic[0] != 0;
-    a.pery = dom->periodic[1] != 0;
-    a.abf = opt->abf;
-    a.rbf = opt->rbf;
-    a.sigma = opt->sigma;
-    a.ops = opt->ops;
-    a.nops = 0;
-    for (int b = 0; b < 5; ++b) a.nops += (opt->ops >> b) & 1u;
-    a.tol_stop = opt->tol_stop;
-    a.tol_pass = opt->tol_pass;
-    a.max_iters = opt->max_iters;
-    a.iters_offset = 0;
-    a.max_iters32 = 30;
-    a.psi0 = nullptr;
-    a.psi0_order = 0;
-    a.psi0_ld = 0;
-    a.w64 = w64;
-    a.w32 = w32;
-    a.status = status;
-    a.resid = resid;
-    a.iters = iters;
+    NodeSet& S = a.one;
+    S.x = x;
+    S.y = y;
+    S.R = R;
+    S.order = order;
+    S.row_ptr = row_ptr;
+    S.col = col;
+    S.n = n;
+    S.nnz = nnz;
+    S.Lx = dom->hi[0] - dom->lo[0];
+    S.Ly = dom->hi[1] - dom->lo[1];
+    S.perx = dom->periodic[0] != 0;
+    S.pery = dom->periodic[1] != 0;
+    S.w64 = w64;
+    S.w32 = w32;
+    S.status = status;
+    S.resid = resid;
+    S.iters = iters;
+    S.psi0 = nullptr;
+    a.sets = nullptr;
+    a.set_off = nullptr;
+    a.nsets = 1;
+    a.ntotal = n;
+    set_options(a, opt);
     hipStream_t st = (hipStream_t)stream;
-    if (opt->prec == LABFM_PREC_FP64) return weights_fp64(c, a, st);
-    if (opt->prec == LABFM_PREC_MIXED) return weights_mixed(c, a, st);
-    return weights_mlp(c, a, opt->mlp, st);
+    labfm_err e = ensure(c->worklist, sizeof(int32_t) * (size_t)(n + 3 * (LABFM_MAX_ORDER + 2)));
+    if (e != LABFM_OK) return e;
+    int32_t* wl = (int32_t*)c->worklist.p;
+    if (opt->prec == LABFM_PREC_FP64) return weights_fp64(c, a, &a.one, wl, st);
+    if ((e = ensure(c->mixed, sizeof(int32_t) * (size_t)(n + LABFM_MAX_ORDER + 2))) != LABFM_OK) return e;
+    int32_t* rl = (int32_t*)c->mixed.p;
+    if (opt->prec == LABFM_PREC_MIXED) return weights_mixed(c, a, &a.one, wl, rl, 0u, st);
+    return weights_mlp(c, a, wl, rl, opt->mlp, st);
+}
+
+labfm_err labfm_weights_batched(void* ctx, int nsets, const labfm_node_set* sets, const labfm_wopts* opt,
+                                int use_graph, void* stream) {
+    if (!ctx || !opt) return fail(LABFM_EINVAL, "labfm_weights_batched: ctx or opt is NULL");
+    if (nsets < 1 || !sets) return fail(LABFM_EINVAL, "labfm_weights_batched: need nsets >= 1 and a set table");
+    if (opt->ops == 0 || (opt->ops & ~31u)) return fail(LABFM_EINVAL, "labfm_weights_batched: bad ops");
+    if (opt->abf != LABFM_ABF_HERMITE && opt->abf != LABFM_ABF_PAPER) return fail(LABFM_EINVAL, "labfm_weights_batched: bad abf");
+    if (opt->rbf < 0 || opt->rbf > 4) return fail(LABFM_EINVAL, "labfm_weights_batched: bad rbf");
+    if (!(opt->sigma > 0.0) || !std::isfinite(opt->sigma)) return fail(LABFM_EINVAL, "labfm_weights_batched: sigma must be > 0");
+    if (opt->max_iters < 0 || opt->max_iters > 100) return fail(LABFM_EINVAL, "labfm_weights_batched: max_iters out of range");
+    if (!(opt->tol_stop >= 0.0) || !(opt->tol_pass >= 0.0)) return fail(LABFM_EINVAL, "labfm_weights_batched: bad tolerances");
+    if (opt->prec == LABFM_PREC_MLP) return fail(LABFM_EUNSUPPORTED, "labfm_weights_batched: LABFM_PREC_MLP is not batched");
+    if (opt->prec != LABFM_PREC_FP64 && opt->prec != LABFM_PREC_MIXED) return fail(LABFM_EINVAL, "labfm_weights_batched: bad prec");
+    int64_t total = 0;
+    for (int s = 0; s < nsets; ++s) {
+        const labfm_node_set& S = sets[s];
+        const std::string where = "labfm_weights_batched: set " + std::to_string(s) + ": ";
+        if (S.n < 0 || S.nnz < 0) return fail(LABFM_EINVAL, where + "negative size");
+        if (!domain_ok(&S.dom)) return fail(LABFM_EINVAL, where + "bad domain");
+        if (!S.w64 && !S.w32) return fail(LABFM_EINVAL, where + "w64 and w32 are both NULL");
+        if (S.n > 0 && (!S.x || !S.y || !S.R || !S.order || !S.row_ptr || !S.status || (S.nnz > 0 && !S.col)))
+            return fail(LABFM_EINVAL, where + "NULL array");
+        total += S.n;
+    }
+    if (total > INT32_MAX - 64) return fail(LABFM_EINVAL, "labfm_weights_batched: more than 2^31 nodes in total");
+    Context* c = (Context*)ctx;
+    DeviceGuard g(c->device);
+    if (total == 0) return LABFM_OK;
+    return weights_batched(c, nsets, sets, opt, use_graph, (hipStream_t)stream);
+}
+
+labfm_err labfm_autotune_query(void* ctx, int abf, int rbf, unsigned ops, int order, int* route, double* ms_mixed,
+                               double* ms_fp64, int64_t* sample) {
+    if (!ctx) return fail(LABFM_EINVAL, "labfm_autotune_query: ctx is NULL");
+    return autotune_query((Context*)ctx, abf, rbf, ops, order, route, ms_mixed, ms_fp64, sample);
 }
 
 labfm_err labfm_combine(void* ctx, const double* w64, int nsets, const double* coef, int64_t nnz, double* out64,

@@ -48,6 +48,25 @@ struct Context {
     labfm_step_plan step_key{};
     void* step_u = nullptr;
     void* step_scratch = nullptr;
+    // cached batched-weights graph (replayed while sets, options and stream are unchanged)
+    struct Batch {
+        std::vector<labfm_node_set> sets;
+        labfm_wopts opt{};
+        hipStream_t stream = nullptr;
+        unsigned fp64_orders = 0;
+        Scratch d_sets, d_off, wl, rl;  // owned by the graph
+        hipGraphExec_t exec = nullptr;
+    } batch;
+    // autotuned route of each order on the mixed path, per (abf, rbf, ops)
+    struct Tuned {
+        int abf, rbf;
+        unsigned ops;
+        int order;
+        int route;  // 1 mixed kernels, 2 FP64 kernels
+        double ms_mixed, ms_fp64;
+        int64_t sample;
+    };
+    std::vector<Tuned> tuned;
     // kernel timing (HIP events recorded on the launch stream around each kernel)
     bool timing = false;
     struct Timed {
@@ -81,6 +100,7 @@ struct KernelTimer {
 };
 
 void release_step_graph(Context* c);
+void release_batch(Context* c);
 
 labfm_err ensure(Scratch& s, size_t bytes);
 
@@ -101,7 +121,8 @@ labfm_err neighbours_fill(Context* c, const double* x, const double* y, int64_t 
                           const double* R, const int64_t* row_ptr, int32_t* col, hipStream_t st);
 
 // ---- weights
-struct WeightArgs {
+// Arrays, domain and outputs of one node set.
+struct NodeSet {
     const double* x;
     const double* y;
     const double* R;
@@ -111,32 +132,60 @@ struct WeightArgs {
     int64_t n, nnz;
     double Lx, Ly;
     int perx, pery;
+    double* w64;
+    float* w32;
+    int8_t* status;
+    float* resid;
+    int8_t* iters;
+    const float* psi0;  // warm start: Psi0 of node i at psi0[i * psi0_ld] (or NULL)
+};
+
+// A weight computation over one node set (nsets == 1: `one`) or a batch
+// (nsets > 1: device table `sets`, set s owning global work indices
+// [set_off[s], set_off[s+1])).  Work lists hold global indices.
+struct WeightArgs {
+    NodeSet one;
+    const NodeSet* sets;
+    const int64_t* set_off;
+    int nsets;
+    int64_t ntotal;
     int abf, rbf;
     double sigma;
     unsigned ops;
     int nops;
     double tol_stop, tol_pass;
     int max_iters;
-    double* w64;
-    float* w32;
-    int8_t* status;
-    float* resid;
-    int8_t* iters;
     int iters_offset;  // added to iters (marks nodes recomputed on the FP64 path)
     int max_iters32;   // refinement updates allowed on the mixed path
-    const float* psi0; // warm start of the mixed path: Psi0 of node i at psi0[i * psi0_ld] (or NULL)
-    int psi0_order;    // order of the nodes that use psi0
+    int psi0_order;    // order of the nodes that use NodeSet::psi0
     int psi0_ld;
 };
-labfm_err weights_fp64(Context* c, const WeightArgs& a, hipStream_t st);
-labfm_err build_order_lists(Context* c, const int8_t* order, int64_t n, hipStream_t st, int32_t** list,
-                            int32_t** off, int32_t** cnt);
+constexpr unsigned ALL_ORDERS = 0x1FEu;  // bits 1..8
+constexpr int KMAX_ORDERS = LABFM_MAX_ORDER;
+void set_options(WeightArgs& a, const labfm_wopts* opt);
+void init_weight_grids();
+void init_mixed_grids();
+labfm_err weights_batched(Context* c, int nsets, const labfm_node_set* sets, const labfm_wopts* opt, int use_graph,
+                          hipStream_t st);
+labfm_err autotune_query(Context* c, int abf, int rbf, unsigned ops, int order, int* route, double* ms_mixed,
+                         double* ms_fp64, int64_t* sample);
+// lists: *list holds the caller's buffer (>= ntotal + 3 (KMAX + 2) int32) on entry
+labfm_err build_order_lists(Context* c, const WeightArgs& a, const NodeSet* host_sets, hipStream_t st,
+                            int32_t** list, int32_t** off, int32_t** cnt);
+labfm_err fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
 labfm_err weights_invalid_orders(const WeightArgs& a, const int32_t* list, const int32_t* off, const int32_t* cnt,
                                  hipStream_t st);
-// FP64 kernels over given per-order lists (segment K at list + off[K], cnt[K] entries)
+// FP64 kernels of the orders in `mask` over given per-order lists (segment K at list + off[K], cnt[K] entries)
 labfm_err weights_fp64_lists(Context* c, const WeightArgs& a, const int32_t* list, const int32_t* off,
-                             const int32_t* cnt, hipStream_t st);
-labfm_err weights_mixed(Context* c, const WeightArgs& a, hipStream_t st);
+                             const int32_t* cnt, unsigned mask, hipStream_t st);
+// whole computations; host_sets: host copy of the set table (nsets entries, or &a.one)
+labfm_err weights_fp64(Context* c, const WeightArgs& a, const NodeSet* host_sets, int32_t* wl, hipStream_t st);
+// mixed kernels for the orders not in fp64_orders, FP64 kernels for those and for the retry list
+// rl: >= ntotal + KMAX + 2 int32
+labfm_err weights_mixed(Context* c, const WeightArgs& a, const NodeSet* host_sets, int32_t* wl, int32_t* rl,
+                        unsigned fp64_orders, hipStream_t st);
+labfm_err weights_mixed_lists(Context* c, const WeightArgs& a, const int32_t* list, const int32_t* off,
+                              const int32_t* cnt, int32_t* rl, unsigned mask, hipStream_t st);
 
 // ---- learned warm start
 labfm_err mlp_features(Context* c, const double* x, const double* y, const double* R, const int64_t* row_ptr,
@@ -152,7 +201,8 @@ labfm_err mlp_moment_loss(Context* c, const float* y, const float* M, const floa
 labfm_err mlp_adam(Context* c, float* p, const float* g, float* m, float* v, void* pb, int64_t n, const labfm_adam* hp,
                    int64_t t, hipStream_t st);
 labfm_err mlp_cast_bf16(const float* src, void* dst, int64_t n, hipStream_t st);
-labfm_err weights_mlp(Context* c, const WeightArgs& a, const labfm_mlp* net, hipStream_t st);
+labfm_err weights_mlp(Context* c, const WeightArgs& a, int32_t* wl, int32_t* rl, const labfm_mlp* net,
+                      hipStream_t st);
 
 // ---- application and time stepping
 labfm_err apply_launch(Context* c, const int64_t* row_ptr, const int32_t* col, int64_t n, int64_t nnz, int nops,

@@ -492,8 +492,10 @@ labfm_err mlp_cast_bf16(const float* src, void* dst, int64_t n, hipStream_t st) 
 // from Psi0 and the FP64 kernels take the nodes that do not converge.
 constexpr int64_t MLP_CHUNK = 65536;
 
-labfm_err weights_mlp(Context* c, const WeightArgs& a0, const labfm_mlp* net, hipStream_t st) {
-    const int64_t n = a0.n;
+labfm_err weights_mlp(Context* c, const WeightArgs& a0, int32_t* wl, int32_t* rl, const labfm_mlp* net,
+                      hipStream_t st) {
+    const NodeSet& S = a0.one;
+    const int64_t n = S.n;
     const int L = net->n_layers;
     const int nout = net->dims[L];
     labfm_err e = ensure(c->mlp_psi, sizeof(float) * (size_t)n * nout);
@@ -504,16 +506,16 @@ labfm_err weights_mlp(Context* c, const WeightArgs& a0, const labfm_mlp* net, hi
     float* feat = (float*)c->mlp_feat.p;
     for (int64_t f = 0; f < n; f += ch) {
         const int64_t cnt = n - f < ch ? n - f : ch;
-        if ((e = mlp_features(c, a0.x, a0.y, a0.R, a0.row_ptr, a0.col, f, cnt, a0.Lx, a0.Ly, a0.perx, a0.pery,
-                              net->kmax, feat, st)) != LABFM_OK)
+        if ((e = mlp_features(c, S.x, S.y, S.R, S.row_ptr, S.col, f, cnt, S.Lx, S.Ly, S.perx, S.pery, net->kmax, feat,
+                              st)) != LABFM_OK)
             return e;
         if ((e = mlp_forward(c, net, feat, cnt, psi0 + f * nout, nullptr, 1, st)) != LABFM_OK) return e;
     }
     WeightArgs a = a0;
-    a.psi0 = psi0;
+    a.one.psi0 = psi0;
     a.psi0_order = net->order;
     a.psi0_ld = nout;
-    return weights_mixed(c, a, st);
+    return weights_mixed(c, a, &a.one, wl, rl, 0u, st);
 }
 
 }  // namespace labfm

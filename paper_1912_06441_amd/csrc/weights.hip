@@ -41,10 +41,12 @@ __global__ __launch_bounds__(64) void k_weights_fp64(WeightArgs a, OpList ops, c
     const int32_t* mylist = list + list_off[K];
 
     for (int t = blockIdx.x; t < count; t += gridDim.x) {
-        const int64_t i = mylist[t];
-        const int64_t s0 = a.row_ptr[i];
-        const int N = (int)(a.row_ptr[i + 1] - s0);
-        const double h = 0.5 * a.R[i];
+        NodeSet S;
+        int64_t i;
+        resolve(a, mylist[t], S, i);
+        const int64_t s0 = S.row_ptr[i];
+        const int N = (int)(S.row_ptr[i + 1] - s0);
+        const double h = 0.5 * S.R[i];
         int status = LABFM_ST_OK;
         double res = INFINITY;
         int iters = 0;
@@ -57,7 +59,7 @@ __global__ __launch_bounds__(64) void k_weights_fp64(WeightArgs a, OpList ops, c
 
         double dxr[JS], dyr[JS];
         if (status == LABFM_ST_OK) {
-            const double xi = a.x[i], yi = a.y[i];
+            const double xi = S.x[i], yi = S.y[i];
             bool bad = false;
 #pragma unroll
             for (int js = 0; js < JS; ++js) {
@@ -65,9 +67,9 @@ __global__ __launch_bounds__(64) void k_weights_fp64(WeightArgs a, OpList ops, c
                 dxr[js] = 0.0;
                 dyr[js] = 0.0;
                 if (q < N) {
-                    int32_t j = a.col[s0 + q];
-                    dxr[js] = min_image(a.x[j] - xi, a.Lx, a.perx) / h;
-                    dyr[js] = min_image(a.y[j] - yi, a.Ly, a.pery) / h;
+                    int32_t j = S.col[s0 + q];
+                    dxr[js] = min_image(S.x[j] - xi, S.Lx, S.perx) / h;
+                    dyr[js] = min_image(S.y[j] - yi, S.Ly, S.pery) / h;
                     sD[0][q] = dxr[js];
                     sD[1][q] = dyr[js];
                     if (FAM == LABFM_ABF_PAPER && dxr[js] == 0.0 && dyr[js] == 0.0) bad = true;
@@ -331,8 +333,8 @@ __global__ __launch_bounds__(64) void k_weights_fp64(WeightArgs a, OpList ops, c
                         int q = lane + 64 * js;
                         if (q < N) {
                             double wv = wreg[js][d] / hl;
-                            if (a.w64) a.w64[(int64_t)d * a.nnz + s0 + q] = wv;
-                            if (a.w32) a.w32[(int64_t)d * a.nnz + s0 + q] = (float)wv;
+                            if (S.w64) S.w64[(int64_t)d * S.nnz + s0 + q] = wv;
+                            if (S.w32) S.w32[(int64_t)d * S.nnz + s0 + q] = (float)wv;
                         }
                     }
                 }
@@ -342,16 +344,16 @@ __global__ __launch_bounds__(64) void k_weights_fp64(WeightArgs a, OpList ops, c
         if (failed) {
             for (int d = 0; d < nops; ++d)
                 for (int q = lane; q < N; q += 64) {
-                    if (a.w64) a.w64[(int64_t)d * a.nnz + s0 + q] = 0.0;
-                    if (a.w32) a.w32[(int64_t)d * a.nnz + s0 + q] = 0.0f;
+                    if (S.w64) S.w64[(int64_t)d * S.nnz + s0 + q] = 0.0;
+                    if (S.w32) S.w32[(int64_t)d * S.nnz + s0 + q] = 0.0f;
                 }
             res = INFINITY;
             iters = 0;
         }
         if (lane == 0) {
-            a.status[i] = (int8_t)status;
-            if (a.resid) a.resid[i] = (float)res;
-            if (a.iters) a.iters[i] = (int8_t)(iters + a.iters_offset);
+            S.status[i] = (int8_t)status;
+            if (S.resid) S.resid[i] = (float)res;
+            if (S.iters) S.iters[i] = (int8_t)(iters + a.iters_offset);
         }
         __syncthreads();
     }
@@ -373,6 +375,10 @@ __global__ __launch_bounds__(256) void k_list_count(const int8_t* order, int64_t
     __syncthreads();
     if (threadIdx.x <= KMAX && h[threadIdx.x]) atomicAdd(&cnt[threadIdx.x], h[threadIdx.x]);
 }
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
 __global__ void k_list_offsets(const int32_t* cnt, int32_t* off) {
     if (threadIdx.x == 0) {
         int32_t run = 0;
@@ -382,8 +388,8 @@ __global__ void k_list_offsets(const int32_t* cnt, int32_t* off) {
         }
     }
 }
-__global__ __launch_bounds__(256) void k_list_scatter(const int8_t* order, int64_t n, const int32_t* off,
-                                                      int32_t* fill, int32_t* list) {
+__global__ __launch_bounds__(256) void k_list_scatter(const int8_t* order, int64_t n, int64_t base_g,
+                                                      const int32_t* off, int32_t* fill, int32_t* list) {
     __shared__ int32_t h[KMAX + 1], base[KMAX + 1];
     if (threadIdx.x <= KMAX) h[threadIdx.x] = 0;
     __syncthreads();
@@ -397,22 +403,24 @@ __global__ __launch_bounds__(256) void k_list_scatter(const int8_t* order, int64
     __syncthreads();
     if (threadIdx.x <= KMAX) base[threadIdx.x] = h[threadIdx.x] ? atomicAdd(&fill[threadIdx.x], h[threadIdx.x]) : 0;
     __syncthreads();
-    if (i < n) list[off[k] + base[k] + pos] = (int32_t)i;
+    if (i < n) list[off[k] + base[k] + pos] = (int32_t)(base_g + i);
 }
 // nodes with an invalid order: zero weights and status
 __global__ void k_invalid_order(WeightArgs a, int nops, const int32_t* list, const int32_t* off, const int32_t* cnt) {
     int c = cnt[0];
     for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < c; t += gridDim.x * blockDim.x) {
-        int64_t i = list[off[0] + t];
-        int64_t s0 = a.row_ptr[i], e0 = a.row_ptr[i + 1];
+        NodeSet S;
+        int64_t i;
+        resolve(a, list[off[0] + t], S, i);
+        int64_t s0 = S.row_ptr[i], e0 = S.row_ptr[i + 1];
         for (int d = 0; d < nops; ++d)
             for (int64_t q = s0; q < e0; ++q) {
-                if (a.w64) a.w64[(int64_t)d * a.nnz + q] = 0.0;
-                if (a.w32) a.w32[(int64_t)d * a.nnz + q] = 0.0f;
+                if (S.w64) S.w64[(int64_t)d * S.nnz + q] = 0.0;
+                if (S.w32) S.w32[(int64_t)d * S.nnz + q] = 0.0f;
             }
-        a.status[i] = LABFM_ST_ORDER_TOO_LOW;
-        if (a.resid) a.resid[i] = INFINITY;
-        if (a.iters) a.iters[i] = 0;
+        S.status[i] = LABFM_ST_ORDER_TOO_LOW;
+        if (S.resid) S.resid[i] = INFINITY;
+        if (S.iters) S.iters[i] = 0;
     }
 }
 
@@ -431,9 +439,22 @@ int grid_for() {
     return g;
 }
 
+template <int FAM>
+void launch_grids_all() {
+    (void)grid_for<1, FAM>();
+    (void)grid_for<2, FAM>();
+    (void)grid_for<3, FAM>();
+    (void)grid_for<4, FAM>();
+    (void)grid_for<5, FAM>();
+    (void)grid_for<6, FAM>();
+    (void)grid_for<7, FAM>();
+    (void)grid_for<8, FAM>();
+}
+
 template <int K, int FAM>
 void launch_one(Context* c, const WeightArgs& a, const OpList& ops, const int32_t* list, const int32_t* off,
-                const int32_t* cnt, hipStream_t st) {
+                const int32_t* cnt, unsigned mask, hipStream_t st) {
+    if (!((mask >> K) & 1u)) return;
     static const char* names[KMAX + 1] = {"", "weights64_k1", "weights64_k2", "weights64_k3", "weights64_k4",
                                           "weights64_k5", "weights64_k6", "weights64_k7", "weights64_k8"};
     KernelTimer timer(c, names[K], st);
@@ -442,47 +463,73 @@ void launch_one(Context* c, const WeightArgs& a, const OpList& ops, const int32_
 
 template <int FAM>
 void launch_all(Context* c, const WeightArgs& a, const OpList& ops, const int32_t* list, const int32_t* off,
-                const int32_t* cnt, hipStream_t st) {
-    launch_one<1, FAM>(c, a, ops, list, off, cnt, st);
-    launch_one<2, FAM>(c, a, ops, list, off, cnt, st);
-    launch_one<3, FAM>(c, a, ops, list, off, cnt, st);
-    launch_one<4, FAM>(c, a, ops, list, off, cnt, st);
-    launch_one<5, FAM>(c, a, ops, list, off, cnt, st);
-    launch_one<6, FAM>(c, a, ops, list, off, cnt, st);
-    launch_one<7, FAM>(c, a, ops, list, off, cnt, st);
-    launch_one<8, FAM>(c, a, ops, list, off, cnt, st);
+                const int32_t* cnt, unsigned mask, hipStream_t st) {
+    launch_one<1, FAM>(c, a, ops, list, off, cnt, mask, st);
+    launch_one<2, FAM>(c, a, ops, list, off, cnt, mask, st);
+    launch_one<3, FAM>(c, a, ops, list, off, cnt, mask, st);
+    launch_one<4, FAM>(c, a, ops, list, off, cnt, mask, st);
+    launch_one<5, FAM>(c, a, ops, list, off, cnt, mask, st);
+    launch_one<6, FAM>(c, a, ops, list, off, cnt, mask, st);
+    launch_one<7, FAM>(c, a, ops, list, off, cnt, mask, st);
+    launch_one<8, FAM>(c, a, ops, list, off, cnt, mask, st);
 }
 
 }  // namespace
 
-labfm_err build_order_lists(Context* c, const int8_t* order, int64_t n, hipStream_t st, int32_t** list,
+// Grid sizes are found on first use (occupancy queries); done up front here so
+// that no query happens while a stream is being captured.
+void init_weight_grids() {
+    launch_grids_all<LABFM_ABF_HERMITE>();
+    launch_grids_all<LABFM_ABF_PAPER>();
+}
+
+labfm_err fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st) {
+    if (n <= 0) return LABFM_OK;
+    k_fill_i32<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(p, n, v);
+    LABFM_HIP_CHECK(hipGetLastError());
+    return LABFM_OK;
+}
+
+// Per-order work lists of global indices over every node set.  wl: at least
+// ntotal + 3 (KMAX + 2) int32.  Counters are cleared with a kernel (no memset
+// node when captured).
+labfm_err build_order_lists(Context* c, const WeightArgs& a, const NodeSet* hs, hipStream_t st, int32_t** list,
                             int32_t** off, int32_t** cnt) {
-    labfm_err e = ensure(c->worklist, sizeof(int32_t) * (size_t)(n + 3 * (KMAX + 2)));
-    if (e != LABFM_OK) return e;
-    int32_t* base = (int32_t*)c->worklist.p;
+    (void)c;
+    int32_t* base = *list;  // caller's buffer on entry
     *cnt = base;
     int32_t* fill = base + (KMAX + 2);
     *off = base + 2 * (KMAX + 2);
     *list = base + 3 * (KMAX + 2);
-    LABFM_HIP_CHECK(hipMemsetAsync(base, 0, sizeof(int32_t) * 3 * (KMAX + 2), st));
-    unsigned nb = (unsigned)((n + 255) / 256);
-    k_list_count<<<nb, 256, 0, st>>>(order, n, *cnt);
+    labfm_err e = fill_i32(base, 3 * (KMAX + 2), 0, st);
+    if (e != LABFM_OK) return e;
+    const int ns = a.nsets <= 1 ? 1 : a.nsets;
+    for (int s = 0; s < ns; ++s) {
+        if (hs[s].n <= 0) continue;
+        k_list_count<<<(unsigned)((hs[s].n + 255) / 256), 256, 0, st>>>(hs[s].order, hs[s].n, *cnt);
+    }
     k_list_offsets<<<1, 1, 0, st>>>(*cnt, *off);
-    k_list_scatter<<<nb, 256, 0, st>>>(order, n, *off, fill, *list);
+    int64_t g0 = 0;
+    for (int s = 0; s < ns; ++s) {
+        if (hs[s].n > 0)
+            k_list_scatter<<<(unsigned)((hs[s].n + 255) / 256), 256, 0, st>>>(hs[s].order, hs[s].n, g0, *off, fill,
+                                                                             *list);
+        g0 += hs[s].n;
+    }
     LABFM_HIP_CHECK(hipGetLastError());
     return LABFM_OK;
 }
 
 labfm_err weights_fp64_lists(Context* c, const WeightArgs& a, const int32_t* list, const int32_t* off,
-                             const int32_t* cnt, hipStream_t st) {
+                             const int32_t* cnt, unsigned mask, hipStream_t st) {
     OpList ops{};  // unused slots stay 0: a zero target
     ops.nops = 0;
     for (int b = 0; b < 5; ++b)
         if (a.ops & (1u << b)) ops.op[ops.nops++] = 1u << b;
     if (a.abf == LABFM_ABF_HERMITE)
-        launch_all<LABFM_ABF_HERMITE>(c, a, ops, list, off, cnt, st);
+        launch_all<LABFM_ABF_HERMITE>(c, a, ops, list, off, cnt, mask, st);
     else
-        launch_all<LABFM_ABF_PAPER>(c, a, ops, list, off, cnt, st);
+        launch_all<LABFM_ABF_PAPER>(c, a, ops, list, off, cnt, mask, st);
     LABFM_HIP_CHECK(hipGetLastError());
     return LABFM_OK;
 }
@@ -496,16 +543,12 @@ labfm_err weights_invalid_orders(const WeightArgs& a, const int32_t* list, const
     return LABFM_OK;
 }
 
-labfm_err weights_fp64(Context* c, const WeightArgs& a, hipStream_t st) {
-    int32_t *list, *off, *cnt;
-    labfm_err e = build_order_lists(c, a.order, a.n, st, &list, &off, &cnt);
+labfm_err weights_fp64(Context* c, const WeightArgs& a, const NodeSet* hs, int32_t* wl, hipStream_t st) {
+    int32_t *list = wl, *off, *cnt;
+    labfm_err e = build_order_lists(c, a, hs, st, &list, &off, &cnt);
     if (e != LABFM_OK) return e;
-    int nops = 0;
-    for (int b = 0; b < 5; ++b) nops += (a.ops >> b) & 1u;
-    k_invalid_order<<<64, 256, 0, st>>>(a, nops, list, off, cnt);
-    return weights_fp64_lists(c, a, list, off, cnt, st);
+    if ((e = weights_invalid_orders(a, list, off, cnt, st)) != LABFM_OK) return e;
+    return weights_fp64_lists(c, a, list, off, cnt, ALL_ORDERS, st);
 }
-
-
 
 }  // namespace labfm

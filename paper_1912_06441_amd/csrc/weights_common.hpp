@@ -121,5 +121,24 @@ __device__ inline void lu_solve(const T* sM, const T* sRs, const T* sCs, const i
     for (int d = 0; d < MAXOPS; ++d) b[d] = t[d] * cs;
 }
 
+// Work item g -> (node set, node index within it).
+__device__ inline void resolve(const WeightArgs& a, int64_t g, NodeSet& S, int64_t& i) {
+    if (a.nsets <= 1) {
+        S = a.one;
+        i = g;
+        return;
+    }
+    int lo = 0, hi = a.nsets - 1;  // largest s with set_off[s] <= g
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a.set_off[mid] <= g)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    S = a.sets[lo];
+    i = g - a.set_off[lo];
+}
+
 }  // namespace wk
 }  // namespace labfm

@@ -50,10 +50,13 @@ __global__ __launch_bounds__(64) void k_weights_mixed(WeightArgs a, OpList ops, 
     const int32_t* mylist = list + list_off[K];
 
     for (int t = blockIdx.x; t < count; t += gridDim.x) {
-        const int64_t i = mylist[t];
-        const int64_t s0 = a.row_ptr[i];
-        const int N = (int)(a.row_ptr[i + 1] - s0);
-        const double h = 0.5 * a.R[i];
+        const int32_t g = mylist[t];
+        NodeSet S;
+        int64_t i;
+        resolve(a, g, S, i);
+        const int64_t s0 = S.row_ptr[i];
+        const int N = (int)(S.row_ptr[i + 1] - s0);
+        const double h = 0.5 * S.R[i];
         int status = LABFM_ST_OK;
         double res = INFINITY;
         int iters = 0;
@@ -65,7 +68,7 @@ __global__ __launch_bounds__(64) void k_weights_mixed(WeightArgs a, OpList ops, 
 
         double dxr[JS], dyr[JS];
         if (status == LABFM_ST_OK) {
-            const double xi = a.x[i], yi = a.y[i];
+            const double xi = S.x[i], yi = S.y[i];
             bool bad = false;
 #pragma unroll
             for (int js = 0; js < JS; ++js) {
@@ -73,9 +76,9 @@ __global__ __launch_bounds__(64) void k_weights_mixed(WeightArgs a, OpList ops, 
                 dxr[js] = 0.0;
                 dyr[js] = 0.0;
                 if (q < N) {
-                    const int32_t j = a.col[s0 + q];
-                    dxr[js] = min_image(a.x[j] - xi, a.Lx, a.perx) / h;
-                    dyr[js] = min_image(a.y[j] - yi, a.Ly, a.pery) / h;
+                    const int32_t j = S.col[s0 + q];
+                    dxr[js] = min_image(S.x[j] - xi, S.Lx, S.perx) / h;
+                    dyr[js] = min_image(S.y[j] - yi, S.Ly, S.pery) / h;
                     sD[0][q] = dxr[js];
                     sD[1][q] = dyr[js];
                     if (FAM == LABFM_ABF_PAPER && dxr[js] == 0.0 && dyr[js] == 0.0) bad = true;
@@ -222,10 +225,10 @@ __global__ __launch_bounds__(64) void k_weights_mixed(WeightArgs a, OpList ops, 
 
             if (status == LABFM_ST_OK) {
                 // ---- Psi from the FP32 factors (or the warm start), weights in FP64
-                if (a.psi0 && a.psi0_order == K) {
+                if (S.psi0 && a.psi0_order == K) {
                     if (lane < P)
                         for (int d = 0; d < nops; ++d)
-                            sPsi[d][lane] = (double)a.psi0[i * (int64_t)a.psi0_ld + d * P + lane];
+                            sPsi[d][lane] = (double)S.psi0[i * (int64_t)a.psi0_ld + d * P + lane];
                 } else {
                     double b[MAXOPS];
 #pragma unroll
@@ -344,8 +347,8 @@ __global__ __launch_bounds__(64) void k_weights_mixed(WeightArgs a, OpList ops, 
                             const int q = lane + 64 * js;
                             if (q < N) {
                                 const double wv = wreg[js][d] / hl;
-                                if (a.w64) a.w64[(int64_t)d * a.nnz + s0 + q] = wv;
-                                if (a.w32) a.w32[(int64_t)d * a.nnz + s0 + q] = (float)wv;
+                                if (S.w64) S.w64[(int64_t)d * S.nnz + s0 + q] = wv;
+                                if (S.w32) S.w32[(int64_t)d * S.nnz + s0 + q] = (float)wv;
                             }
                         }
                     }
@@ -358,23 +361,23 @@ __global__ __launch_bounds__(64) void k_weights_mixed(WeightArgs a, OpList ops, 
         if (retry) {
             if (lane == 0) {
                 const int pos = atomicAdd(&retry_cnt[K], 1);
-                retry_list[list_off[K] + pos] = (int32_t)i;
+                retry_list[list_off[K] + pos] = g;
             }
         } else {
             const bool failed = status != LABFM_ST_OK;
             if (failed) {
                 for (int d = 0; d < nops; ++d)
                     for (int q = lane; q < N; q += 64) {
-                        if (a.w64) a.w64[(int64_t)d * a.nnz + s0 + q] = 0.0;
-                        if (a.w32) a.w32[(int64_t)d * a.nnz + s0 + q] = 0.0f;
+                        if (S.w64) S.w64[(int64_t)d * S.nnz + s0 + q] = 0.0;
+                        if (S.w32) S.w32[(int64_t)d * S.nnz + s0 + q] = 0.0f;
                     }
                 res = INFINITY;
                 iters = 0;
             }
             if (lane == 0) {
-                a.status[i] = (int8_t)status;
-                if (a.resid) a.resid[i] = (float)res;
-                if (a.iters) a.iters[i] = (int8_t)iters;
+                S.status[i] = (int8_t)status;
+                if (S.resid) S.resid[i] = (float)res;
+                if (S.iters) S.iters[i] = (int8_t)iters;
             }
         }
         __syncthreads();
@@ -396,9 +399,22 @@ int grid_for_mixed() {
     return g;
 }
 
+template <int FAM>
+void mixed_grids_all() {
+    (void)grid_for_mixed<1, FAM>();
+    (void)grid_for_mixed<2, FAM>();
+    (void)grid_for_mixed<3, FAM>();
+    (void)grid_for_mixed<4, FAM>();
+    (void)grid_for_mixed<5, FAM>();
+    (void)grid_for_mixed<6, FAM>();
+    (void)grid_for_mixed<7, FAM>();
+    (void)grid_for_mixed<8, FAM>();
+}
+
 template <int K, int FAM>
 void launch_mixed_one(Context* c, const WeightArgs& a, const OpList& ops, const int32_t* list, const int32_t* off,
-                      const int32_t* cnt, int32_t* rlist, int32_t* rcnt, hipStream_t st) {
+                      const int32_t* cnt, int32_t* rlist, int32_t* rcnt, unsigned mask, hipStream_t st) {
+    if (!((mask >> K) & 1u)) return;
     static const char* names[KMAX + 1] = {"", "weights32_k1", "weights32_k2", "weights32_k3", "weights32_k4",
                                           "weights32_k5", "weights32_k6", "weights32_k7", "weights32_k8"};
     KernelTimer timer(c, names[K], st);
@@ -407,41 +423,56 @@ void launch_mixed_one(Context* c, const WeightArgs& a, const OpList& ops, const 
 
 template <int FAM>
 void launch_mixed_all(Context* c, const WeightArgs& a, const OpList& ops, const int32_t* list, const int32_t* off,
-                      const int32_t* cnt, int32_t* rlist, int32_t* rcnt, hipStream_t st) {
-    launch_mixed_one<1, FAM>(c, a, ops, list, off, cnt, rlist, rcnt, st);
-    launch_mixed_one<2, FAM>(c, a, ops, list, off, cnt, rlist, rcnt, st);
-    launch_mixed_one<3, FAM>(c, a, ops, list, off, cnt, rlist, rcnt, st);
-    launch_mixed_one<4, FAM>(c, a, ops, list, off, cnt, rlist, rcnt, st);
-    launch_mixed_one<5, FAM>(c, a, ops, list, off, cnt, rlist, rcnt, st);
-    launch_mixed_one<6, FAM>(c, a, ops, list, off, cnt, rlist, rcnt, st);
-    launch_mixed_one<7, FAM>(c, a, ops, list, off, cnt, rlist, rcnt, st);
-    launch_mixed_one<8, FAM>(c, a, ops, list, off, cnt, rlist, rcnt, st);
+                      const int32_t* cnt, int32_t* rlist, int32_t* rcnt, unsigned mask, hipStream_t st) {
+    launch_mixed_one<1, FAM>(c, a, ops, list, off, cnt, rlist, rcnt, mask, st);
+    launch_mixed_one<2, FAM>(c, a, ops, list, off, cnt, rlist, rcnt, mask, st);
+    launch_mixed_one<3, FAM>(c, a, ops, list, off, cnt, rlist, rcnt, mask, st);
+    launch_mixed_one<4, FAM>(c, a, ops, list, off, cnt, rlist, rcnt, mask, st);
+    launch_mixed_one<5, FAM>(c, a, ops, list, off, cnt, rlist, rcnt, mask, st);
+    launch_mixed_one<6, FAM>(c, a, ops, list, off, cnt, rlist, rcnt, mask, st);
+    launch_mixed_one<7, FAM>(c, a, ops, list, off, cnt, rlist, rcnt, mask, st);
+    launch_mixed_one<8, FAM>(c, a, ops, list, off, cnt, rlist, rcnt, mask, st);
 }
 
 }  // namespace
 
-labfm_err weights_mixed(Context* c, const WeightArgs& a0, hipStream_t st) {
-    int32_t *list, *off, *cnt;
-    labfm_err e = build_order_lists(c, a0.order, a0.n, st, &list, &off, &cnt);
-    if (e != LABFM_OK) return e;
-    if ((e = weights_invalid_orders(a0, list, off, cnt, st)) != LABFM_OK) return e;
-    if ((e = ensure(c->mixed, sizeof(int32_t) * (size_t)(a0.n + KMAX + 2))) != LABFM_OK) return e;
-    int32_t* rcnt = (int32_t*)c->mixed.p;
+void init_mixed_grids() {
+    mixed_grids_all<LABFM_ABF_HERMITE>();
+    mixed_grids_all<LABFM_ABF_PAPER>();
+}
+
+// Mixed kernels of the orders in `mask` over given lists, then FP64 kernels on
+// the nodes they hand back.  rl: >= ntotal + KMAX + 2 int32 (counters first).
+labfm_err weights_mixed_lists(Context* c, const WeightArgs& a0, const int32_t* list, const int32_t* off,
+                              const int32_t* cnt, int32_t* rl, unsigned mask, hipStream_t st) {
+    int32_t* rcnt = rl;
     int32_t* rlist = rcnt + (KMAX + 2);
-    LABFM_HIP_CHECK(hipMemsetAsync(rcnt, 0, sizeof(int32_t) * (KMAX + 2), st));
+    labfm_err e = fill_i32(rcnt, KMAX + 2, 0, st);
+    if (e != LABFM_OK) return e;
     OpList ops{};
     ops.nops = 0;
     for (int b = 0; b < 5; ++b)
         if (a0.ops & (1u << b)) ops.op[ops.nops++] = 1u << b;
     if (a0.abf == LABFM_ABF_HERMITE)
-        launch_mixed_all<LABFM_ABF_HERMITE>(c, a0, ops, list, off, cnt, rlist, rcnt, st);
+        launch_mixed_all<LABFM_ABF_HERMITE>(c, a0, ops, list, off, cnt, rlist, rcnt, mask, st);
     else
-        launch_mixed_all<LABFM_ABF_PAPER>(c, a0, ops, list, off, cnt, rlist, rcnt, st);
+        launch_mixed_all<LABFM_ABF_PAPER>(c, a0, ops, list, off, cnt, rlist, rcnt, mask, st);
     LABFM_HIP_CHECK(hipGetLastError());
     // FP64 recomputation of the retry list; iters of those nodes are offset by 64
     WeightArgs a = a0;
     a.iters_offset = 64;
-    return weights_fp64_lists(c, a, rlist, off, rcnt, st);
+    return weights_fp64_lists(c, a, rlist, off, rcnt, mask, st);
+}
+
+labfm_err weights_mixed(Context* c, const WeightArgs& a0, const NodeSet* hs, int32_t* wl, int32_t* rl,
+                        unsigned fp64_orders, hipStream_t st) {
+    int32_t *list = wl, *off, *cnt;
+    labfm_err e = build_order_lists(c, a0, hs, st, &list, &off, &cnt);
+    if (e != LABFM_OK) return e;
+    if ((e = weights_invalid_orders(a0, list, off, cnt, st)) != LABFM_OK) return e;
+    if (fp64_orders & ALL_ORDERS)
+        if ((e = weights_fp64_lists(c, a0, list, off, cnt, fp64_orders & ALL_ORDERS, st)) != LABFM_OK) return e;
+    return weights_mixed_lists(c, a0, list, off, cnt, rl, ALL_ORDERS & ~fp64_orders, st);
 }
 
 }  // namespace labfm

@@ -109,6 +109,11 @@ def config(name):
         # composed nabla^8 hyperviscosity gamma = beta h^8 / dt.  dt = 0.1 s: at 0.2 s the RK4
         # step map of this node set grows (power iteration: x3.7 per step, a mode localised on
         # the stencils of largest amplification); at 0.1 s every mode decays.
+        # batch of independent sets (seeds seed0 + s): n_s log-uniform in [n_min, n_max] (side
+        # round(sqrt(n_s))), eps_s ~ U(0, eps_max), order k_s uniform over `orders`, R0 = R_s[k] s
+        # (mean N about 10, 25, 48, 62) + growth, order min(k, 4) in the boundary band of width R0
+        "c3": dict(nsets=64, seed0=3000, n_min=4096, n_max=262144, eps_max=0.4, orders=(2, 4, 6, 8),
+                   R_s={2: 1.8, 4: 2.85, 6: 3.9, 8: 4.45}, k_boundary=4),
         # learned warm start, order 8 (p = 44) Hermite x Wendland C2, {dx, dy, lap}: training stencils
         # from periodic jittered lattices of side train_side, eps ~ U(0, eps_max) per lattice (seeds
         # train_seed0 + i), R0 = 4.4 s + growth; the network sees the nearest kmax = 64 neighbours.
@@ -133,6 +138,28 @@ def make_nodes(cfg, n_side=None, seed=None):
     order = order_map(x, y, cfg["k"], band=R0, k_boundary=cfg["k_boundary"], periodic=cfg["periodic"])
     R = np.full(x.size, R0)
     return dict(x=x, y=y, s=s, R0=R0, R=R, order=order, domain=unit_domain(cfg["periodic"]))
+
+
+def batch_sets(cfg, nsets=None, n_min=None, n_max=None):
+    """Node sets of the batched workload: list of dicts as make_nodes gives,
+    plus the set's order k and jitter eps."""
+    nsets = cfg["nsets"] if nsets is None else nsets
+    n_min = cfg["n_min"] if n_min is None else n_min
+    n_max = cfg["n_max"] if n_max is None else n_max
+    out = []
+    for t in range(nsets):
+        seed = cfg["seed0"] + t
+        rng = np.random.default_rng(seed)
+        n = math.exp(rng.uniform(math.log(n_min), math.log(n_max)))
+        side = max(4, int(round(math.sqrt(n))))
+        eps = float(rng.uniform(0.0, cfg["eps_max"]))
+        k = int(cfg["orders"][rng.integers(len(cfg["orders"]))])
+        x, y, s = jittered_lattice(side, eps=eps, seed=seed, periodic=False)
+        R0 = cfg["R_s"][k] * s
+        order = order_map(x, y, k, band=R0, k_boundary=min(k, cfg["k_boundary"]), periodic=False)
+        out.append(dict(x=x, y=y, s=s, R0=R0, R=np.full(x.size, R0), order=order, domain=unit_domain(False), k=k,
+                        eps=eps))
+    return out
 
 
 # ---------------------------------------------------------------------------

@@ -1,0 +1,132 @@
+"""Batched weights (many node sets, one launch sequence) against the oracle.
+
+* Every set of a reduced batch (8 sets of 256..4096 nodes, orders 2..8, mixed
+  precision with route autotuning, captured graph): status equal to the
+  oracle's, moment residual <= 1e-10, per-node weight parity as for the mixed
+  path (at most n/10000 nodes above 1e-10 relative, none above 1e-8).
+* The FP64 route of the batch equals the single-set FP64 call bit for bit
+  (same kernels, same arithmetic; only the set lookup differs).
+* Graph replays, with eager work between them, reproduce the first result bit
+  for bit.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1912_06441_amd import workloads as WL
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    import oracle
+    import paper_1912_06441_amd as L
+
+    assert torch.cuda.is_available()
+    ctx = L.Context(0)
+    yield dict(torch=torch, O=oracle, L=L, ctx=ctx)
+    torch.cuda.synchronize()
+    ctx.close()
+
+
+def _dev(env, a):
+    return env["torch"].from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.fixture(scope="module")
+def batch(env):
+    O = env["O"]
+    cfg = WL.config("c3")
+    sets = WL.batch_sets(cfg, nsets=8, n_min=256, n_max=4096)
+    out = []
+    for S in sets:
+        rp, col, R = O.neighbours(S["x"], S["y"], S["domain"], S["R"], S["order"], grow=True)
+        xt, yt = _dev(env, S["x"]), _dev(env, S["y"])
+        Rt, ot = _dev(env, S["R"].copy()), _dev(env, S["order"])
+        rpg, colg = env["ctx"].build_neighbours(xt, yt, Rt, ot, S["domain"])
+        env["torch"].cuda.synchronize()
+        assert np.array_equal(rpg.cpu().numpy(), rp) and np.array_equal(colg.cpu().numpy(), col)
+        w, st, res, it = O.weights(S["x"], S["y"], S["domain"], R, S["order"], rp, col)
+        out.append(dict(x=xt, y=yt, R=Rt, order=ot, row_ptr=rpg, col=colg, domain=S["domain"], k=S["k"],
+                        rp=rp, w_or=w, st_or=st, res_or=res))
+    _say("batch: %d sets, %d nodes, orders %s" % (len(out), sum(s["rp"].size - 1 for s in out),
+                                                   sorted(set(s["k"] for s in out))))
+    return out
+
+
+def _parity(rp, w, w_or):
+    n = rp.size - 1
+    seg = np.repeat(np.arange(n), np.diff(rp))
+    num = np.zeros(n)
+    den = np.zeros(n)
+    for d in range(w_or.shape[0]):
+        np.maximum.at(num, seg, np.abs(w[d] - w_or[d]))
+        np.maximum.at(den, seg, np.abs(w_or[d]))
+    return num / np.where(den > 0, den, 1.0)
+
+
+def test_batched_mixed_graph_parity(env, batch):
+    torch = env["torch"]
+    L = env["L"]
+    outs = env["ctx"].weights_batched(batch, prec=L.PREC_MIXED, use_graph=True)
+    torch.cuda.synchronize()
+    for S, o in zip(batch, outs):
+        st = o[2].cpu().numpy()
+        res = o[3].cpu().numpy()
+        assert np.array_equal(st, S["st_or"])
+        ok = st == 0
+        assert np.all(res[ok] <= 1e-10)
+        par = _parity(S["rp"], o[0].cpu().numpy(), S["w_or"])[ok]
+        assert np.count_nonzero(par > 1e-10) <= max(1, ok.sum() // 10000) and par.max() <= 1e-8, (S["k"], par.max())
+    for k in sorted(set(S["k"] for S in batch)):
+        route, ms_m, ms_f, ns = env["ctx"].autotune_query(k)
+        _say("  order %d: route %s (mixed %.3f ms, fp64 %.3f ms on %d nodes)" %
+             (k, {1: "mixed", 2: "fp64"}.get(route, "?"), ms_m, ms_f, ns))
+        assert route in (1, 2)
+
+
+def test_batched_graph_replays_match(env, batch):
+    torch = env["torch"]
+    L = env["L"]
+    outs = env["ctx"].weights_batched(batch, prec=L.PREC_MIXED, use_graph=True)
+    torch.cuda.synchronize()
+    first = [o[0].cpu().numpy().copy() for o in outs]
+    first_st = [o[2].cpu().numpy().copy() for o in outs]
+    for rep in range(3):
+        for o in outs:
+            o[0].fill_(np.nan)
+            o[2].fill_(-1)
+        # eager work between the replays
+        u = torch.ones(batch[0]["x"].numel(), dtype=torch.float64, device="cuda")
+        wtmp = torch.full((1, batch[0]["col"].numel()), 0.5, dtype=torch.float64, device="cuda")
+        env["ctx"].apply_operator(batch[0]["row_ptr"], batch[0]["col"], wtmp, u)
+        torch.cuda.synchronize()
+        env["ctx"].weights_batched(batch, prec=L.PREC_MIXED, use_graph=True, outs=outs)
+        torch.cuda.synchronize()
+        for t, o in enumerate(outs):
+            assert np.array_equal(o[0].cpu().numpy(), first[t]), (rep, t)
+            assert np.array_equal(o[2].cpu().numpy(), first_st[t]), (rep, t)
+
+
+def test_batched_fp64_equals_single_set(env, batch):
+    torch = env["torch"]
+    L = env["L"]
+    outs = env["ctx"].weights_batched(batch, prec=L.PREC_FP64, use_graph=False)
+    torch.cuda.synchronize()
+    for S, o in zip(batch, outs):
+        w64, _, st, res, it = env["ctx"].weights(S["x"], S["y"], S["R"], S["order"], S["row_ptr"], S["col"],
+                                                 S["domain"], prec=L.PREC_FP64)
+        torch.cuda.synchronize()
+        assert np.array_equal(o[0].cpu().numpy(), w64.cpu().numpy())
+        assert np.array_equal(o[2].cpu().numpy(), st.cpu().numpy())
+        assert np.array_equal(o[4].cpu().numpy(), it.cpu().numpy())
+        assert np.array_equal(st.cpu().numpy(), S["st_or"])
