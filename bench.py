@@ -25,6 +25,7 @@ if ROOT not in sys.path:
 
 PEAK_FP64 = 78.6e12      # MI355X FP64 vector / matrix, FLOP/s
 PEAK_FP32_MFMA = 157.3e12
+PEAK_BF16 = 2.5e15       # dense BF16 matrix
 PEAK_HBM = 8.0e12        # bytes/s
 
 
@@ -219,6 +220,7 @@ def main():
         rec["rk4_c5"] = run_rk4(ctx, torch, np, L, WL, args.rk4_steps)
     if not args.no_batch:
         rec["batch_c3"] = run_batch(ctx, torch, np, L, WL, reps=3)
+    rec["mlp_bf16"] = run_mlp(ctx, torch, L, WL)
 
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = run_cpu_baseline(nd, cfg)
@@ -292,6 +294,29 @@ def run_rk4(ctx, torch, np, L, WL, nsteps):
             "operator_apps_nodes_per_s": 12 * n / (ms_step / 1e3),
             "GB_per_s": bytes_step / (ms_step / 1e3) / 1e9, "hbm_frac": bytes_step / (ms_step / 1e3) / PEAK_HBM,
             "weights_all_ok": bool((st == 0).all().item()), "u_max": float(u.abs().max().item())}
+
+
+def run_mlp(ctx, torch, L, WL, B=1 << 20, reps=5):
+    """Warm-start network inference on the matrix cores (BF16 operands, FP32
+    accumulation): 192 -> 256 -> 256 -> 256 -> 132 over 2^20 stencils."""
+    cfg = WL.config("c4")
+    net = L.MLP(ctx, dims=cfg["dims"], order=cfg["k"], ops=cfg["ops"], kmax=cfg["kmax"], seed=0)
+    g = torch.Generator(device="cuda").manual_seed(0)
+    X = torch.randn((B, cfg["dims"][0]), device="cuda", generator=g)
+    out = net.forward(X)
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    for _ in range(reps):
+        net.forward(X, out=out)
+    torch.cuda.synchronize()
+    ctx.timing(False)
+    nk, ms = ctx.timing_read("mlp_forward")
+    ctx.timing_read(None)
+    ms /= max(nk, 1)
+    d = cfg["dims"]
+    flops = 2.0 * B * sum(d[l] * d[l + 1] for l in range(len(d) - 1))
+    return {"rows": B, "dims": list(d), "ms_per_forward": ms, "tflops": flops / (ms / 1e3) / 1e12,
+            "frac_of_bf16_dense_peak": flops / (ms / 1e3) / PEAK_BF16, "rows_per_s": B / (ms / 1e3)}
 
 
 def run_batch(ctx, torch, np, L, WL, reps):

@@ -161,51 +161,53 @@ __global__ __launch_bounds__(64) void k_weights_fp64(WeightArgs a, OpList ops, c
             int perm = lane;
             if (status == LABFM_ST_OK) {
                 for (int kk = 0; kk < P; ++kk) {
-                    double v = (lane >= kk && lane < P) ? fabs(sM[lane * LD + kk]) : -1.0;
-                    int ir = lane;
-#pragma unroll
-                    for (int off = 32; off >= 1; off >>= 1) {
-                        double v2 = __shfl_xor(v, off, 64);
-                        int i2 = __shfl_xor(ir, off, 64);
-                        if (v2 > v || (v2 == v && i2 < ir)) {
-                            v = v2;
-                            ir = i2;
-                        }
-                    }
-                    if (!(v > 0.0) || !isfinite(v)) {
+                    // pivot: largest |M[r][kk]| over r >= kk, ties to the lowest row
+                    const double v = (lane >= kk && lane < P) ? fabs(sM[lane * LD + kk]) : -1.0;
+                    const double vmax = wave_max_double(v);
+                    const unsigned long long hit = __ballot(v == vmax);
+                    if (!(vmax > 0.0) || !isfinite(vmax) || hit == 0ull) {
                         status = LABFM_ST_SINGULAR;
                         break;
                     }
-                    const int pr = ir;
+                    const int pr = __ffsll((long long)hit) - 1;
                     if (pr != kk) {
                         if (lane < P) {
-                            double u = sM[kk * LD + lane];
+                            const double u = sM[kk * LD + lane];
                             sM[kk * LD + lane] = sM[pr * LD + lane];
                             sM[pr * LD + lane] = u;
                         }
                         // permutation bookkeeping: position kk <-> pr
-                        int pk = __shfl(perm, kk, 64), pp = __shfl(perm, pr, 64);
+                        const int pk = __builtin_amdgcn_readlane(perm, kk), pp = __builtin_amdgcn_readlane(perm, pr);
                         if (lane == kk) perm = pp;
                         if (lane == pr) perm = pk;
                     }
                     __syncthreads();
-                    if (lane > kk && lane < P) sM[lane * LD + kk] = sM[lane * LD + kk] / sM[kk * LD + kk];
-                    __syncthreads();
-                    if (lane > kk && lane < P) {
-                        // rows in groups of four: all loads issued before the stores
+                    // one pass: lane c > kk updates column c of the trailing rows, lane kk
+                    // stores the multipliers l_r = M[r][kk] / M[kk][kk] (every lane reads
+                    // M[r][kk] before lane kk overwrites it; rows in groups of eight)
+                    if (lane >= kk && lane < P) {
+                        const double inv = 1.0 / sM[kk * LD + kk];
                         const double u = sM[kk * LD + lane];
+                        const bool own = lane == kk;
                         int r = kk + 1;
-                        for (; r + 4 <= P; r += 4) {
-                            const double l0 = sM[r * LD + kk], l1 = sM[(r + 1) * LD + kk];
-                            const double l2 = sM[(r + 2) * LD + kk], l3 = sM[(r + 3) * LD + kk];
-                            const double a0 = sM[r * LD + lane], a1 = sM[(r + 1) * LD + lane];
-                            const double a2 = sM[(r + 2) * LD + lane], a3 = sM[(r + 3) * LD + lane];
-                            sM[r * LD + lane] = fma(-l0, u, a0);
-                            sM[(r + 1) * LD + lane] = fma(-l1, u, a1);
-                            sM[(r + 2) * LD + lane] = fma(-l2, u, a2);
-                            sM[(r + 3) * LD + lane] = fma(-l3, u, a3);
+                        for (; r + 8 <= P; r += 8) {
+                            double l[8], a[8];
+#pragma unroll
+                            for (int e = 0; e < 8; ++e) {
+                                l[e] = sM[(r + e) * LD + kk];
+                                a[e] = sM[(r + e) * LD + lane];
+                            }
+#pragma unroll
+                            for (int e = 0; e < 8; ++e) {
+                                const double m = l[e] * inv;
+                                sM[(r + e) * LD + lane] = own ? m : fma(-m, u, a[e]);
+                            }
                         }
-                        for (; r < P; ++r) sM[r * LD + lane] = fma(-sM[r * LD + kk], u, sM[r * LD + lane]);
+                        for (; r < P; ++r) {
+                            const double m = sM[r * LD + kk] * inv;
+                            const double a0 = sM[r * LD + lane];
+                            sM[r * LD + lane] = own ? m : fma(-m, u, a0);
+                        }
                     }
                     __syncthreads();
                 }

@@ -21,6 +21,12 @@ __device__ inline double wave_max(double v) {
     for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
     return v;
 }
+__device__ inline double wave_max_double(double v) { return wave_max(v); }
+__device__ inline float wave_max_float(float v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+    return v;
+}
 
 __device__ inline double min_image(double d, double L, int per) {
     if (!per) return d;

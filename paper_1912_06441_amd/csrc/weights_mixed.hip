@@ -173,49 +173,53 @@ __global__ __launch_bounds__(64) void k_weights_mixed(WeightArgs a, OpList ops, 
             int perm = lane;
             if (status == LABFM_ST_OK) {
                 for (int kk = 0; kk < P; ++kk) {
-                    float v = (lane >= kk && lane < P) ? fabsf(sM[lane * LD + kk]) : -1.f;
-                    int ir = lane;
-#pragma unroll
-                    for (int off = 32; off >= 1; off >>= 1) {
-                        const float v2 = __shfl_xor(v, off, 64);
-                        const int i2 = __shfl_xor(ir, off, 64);
-                        const bool take = (v2 > v) | ((v2 == v) & (i2 < ir));
-                        v = take ? v2 : v;
-                        ir = take ? i2 : ir;
-                    }
-                    if (!(v > 0.f) || !isfinite(v)) {
+                    // pivot: largest |M[r][kk]| over r >= kk, ties to the lowest row
+                    const float v = (lane >= kk && lane < P) ? fabsf(sM[lane * LD + kk]) : -1.f;
+                    const float vmax = wave_max_float(v);
+                    const unsigned long long hit = __ballot(v == vmax);
+                    if (!(vmax > 0.f) || !isfinite(vmax) || hit == 0ull) {
                         status = LABFM_ST_SINGULAR;
                         break;
                     }
-                    const int pr = ir;
+                    const int pr = __ffsll((long long)hit) - 1;
                     if (pr != kk) {
                         if (lane < P) {
                             const float u = sM[kk * LD + lane];
                             sM[kk * LD + lane] = sM[pr * LD + lane];
                             sM[pr * LD + lane] = u;
                         }
-                        const int pk = __shfl(perm, kk, 64), pp = __shfl(perm, pr, 64);
+                        // permutation bookkeeping: position kk <-> pr
+                        const int pk = __builtin_amdgcn_readlane(perm, kk), pp = __builtin_amdgcn_readlane(perm, pr);
                         if (lane == kk) perm = pp;
                         if (lane == pr) perm = pk;
                     }
                     __syncthreads();
-                    if (lane > kk && lane < P) sM[lane * LD + kk] = sM[lane * LD + kk] / sM[kk * LD + kk];
-                    __syncthreads();
-                    if (lane > kk && lane < P) {
-                        // rows in groups of four: all loads issued before the stores
+                    // one pass: lane c > kk updates column c of the trailing rows, lane kk
+                    // stores the multipliers l_r = M[r][kk] / M[kk][kk] (every lane reads
+                    // M[r][kk] before lane kk overwrites it; rows in groups of eight)
+                    if (lane >= kk && lane < P) {
+                        const float inv = 1.f / sM[kk * LD + kk];
                         const float u = sM[kk * LD + lane];
+                        const bool own = lane == kk;
                         int r = kk + 1;
-                        for (; r + 4 <= P; r += 4) {
-                            const float l0 = sM[r * LD + kk], l1 = sM[(r + 1) * LD + kk];
-                            const float l2 = sM[(r + 2) * LD + kk], l3 = sM[(r + 3) * LD + kk];
-                            const float a0 = sM[r * LD + lane], a1 = sM[(r + 1) * LD + lane];
-                            const float a2 = sM[(r + 2) * LD + lane], a3 = sM[(r + 3) * LD + lane];
-                            sM[r * LD + lane] = fmaf(-l0, u, a0);
-                            sM[(r + 1) * LD + lane] = fmaf(-l1, u, a1);
-                            sM[(r + 2) * LD + lane] = fmaf(-l2, u, a2);
-                            sM[(r + 3) * LD + lane] = fmaf(-l3, u, a3);
+                        for (; r + 8 <= P; r += 8) {
+                            float l[8], a[8];
+#pragma unroll
+                            for (int e = 0; e < 8; ++e) {
+                                l[e] = sM[(r + e) * LD + kk];
+                                a[e] = sM[(r + e) * LD + lane];
+                            }
+#pragma unroll
+                            for (int e = 0; e < 8; ++e) {
+                                const float m = l[e] * inv;
+                                sM[(r + e) * LD + lane] = own ? m : fmaf(-m, u, a[e]);
+                            }
                         }
-                        for (; r < P; ++r) sM[r * LD + lane] = fmaf(-sM[r * LD + kk], u, sM[r * LD + lane]);
+                        for (; r < P; ++r) {
+                            const float m = sM[r * LD + kk] * inv;
+                            const float a0 = sM[r * LD + lane];
+                            sM[r * LD + lane] = own ? m : fmaf(-m, u, a0);
+                        }
                     }
                     __syncthreads();
                 }
