@@ -246,10 +246,21 @@ def compare_precision(ctx, torch, np, L, x, y, R0, order, nd, prec, bufs, reps):
     res = bufs[3].cpu().numpy()
     good8 = int(((st == 0) & (nd["order"] == 8)).sum())
     ms = kw[1] / reps
-    return {"prec": "fp64" if prec == L.PREC_FP64 else "mixed", "weights_ms": ms,
-            "weight_sets_per_s_order8": good8 / (ms / 1e3), "nodes_passing_1e-10": int((st == 0).sum()),
-            "max_moment_residual": float(res.max()), "fp64_fallback_nodes": int((it >= 64).sum()),
-            "mean_refinement_iters": float(it[it < 64].mean())}
+    rec = {"prec": "fp64" if prec == L.PREC_FP64 else "mixed", "weights_ms": ms,
+           "weight_sets_per_s_order8": good8 / (ms / 1e3), "nodes_passing_1e-10": int((st == 0).sum()),
+           "max_moment_residual": float(res.max()), "fp64_fallback_nodes": int((it >= 64).sum()),
+           "mean_refinement_iters": float(it[it < 64].mean())}
+    if prec == L.PREC_MIXED:
+        # matrix-core work of the assembly as issued: neighbours in chunks of 16, p padded to 16-wide
+        # tiles (2 x ceil16(N) x ceil16(p)^2 per system), over the time of all weight kernels
+        N = np.diff(rp.cpu().numpy()).astype(np.float64)
+        k = nd["order"].astype(np.int64)
+        p = (k * k + 3 * k) // 2
+        pp = 16.0 * np.ceil(p / 16.0)
+        mf = float((2.0 * 16.0 * np.ceil(N / 16.0) * pp * pp).sum())
+        rec["matrix_core_flops"] = mf
+        rec["matrix_core_frac_of_fp32_peak"] = mf / (ms / 1e3) / PEAK_FP32_MFMA
+    return rec
 
 
 def run_rk4(ctx, torch, np, L, WL, nsteps):

@@ -202,6 +202,117 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
             }
 }
 
+// Forward layers (A FP32 [M][K] row-major, W BF16 [N][K] row-major, K a
+// multiple of 32, 16-byte aligned rows): 128 x 128 block tiles, each of the
+// four waves computes 64 x 64 (4 x 4 MFMA tiles); A and W tiles are loaded
+// 16 bytes per access and double-buffered in LDS, one barrier per k-step.
+constexpr int FBM = 128, FBN = 128, FBK = 32, FLD = FBK + 8;
+
+template <int EPI>
+__global__ __launch_bounds__(256) void k_gemm_fwd(GemmArgs g) {
+    __shared__ __bf16 As[2][FBM][FLD];
+    __shared__ __bf16 Bs[2][FBN][FLD];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int m0 = blockIdx.y * FBM, n0 = blockIdx.x * FBN;
+    const int wm = (w >> 1) * 64, wn = (w & 1) * 64;
+    const __bf16* W = (const __bf16*)g.B;
+    // loader: thread t covers row t/2, 16 consecutive k at (t%2)*16
+    const int lr = tid >> 1, lk = (tid & 1) * 16;
+    const int gm = m0 + lr, gn = n0 + lr;
+    const bool am = gm < g.M, bn = gn < g.N;
+    const float* arow = g.A + (int64_t)(am ? gm : 0) * g.lam + lk;
+    const __bf16* brow = W + (int64_t)(bn ? gn : 0) * g.lbn + lk;
+    floatx4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    floatx4 ra[4];
+    bf16x8 rb[2];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ra[q] = am ? *(const floatx4*)(arow + k0 + 4 * q) : floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            if (bn) {
+                rb[q] = *(const bf16x8*)(brow + k0 + 8 * q);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) rb[q][e] = (__bf16)0.f;
+            }
+        }
+    };
+    auto stash = [&](int buf) {
+        bf16x8 a0, a1;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            a0[e] = (__bf16)ra[0][e];
+            a0[4 + e] = (__bf16)ra[1][e];
+            a1[e] = (__bf16)ra[2][e];
+            a1[4 + e] = (__bf16)ra[3][e];
+        }
+        *(bf16x8*)&As[buf][lr][lk] = a0;
+        *(bf16x8*)&As[buf][lr][lk + 8] = a1;
+        *(bf16x8*)&Bs[buf][lr][lk] = rb[0];
+        *(bf16x8*)&Bs[buf][lr][lk + 8] = rb[1];
+    };
+    const int nk = g.K / FBK;
+    load(0);
+    stash(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        if (kt + 1 < nk) load((kt + 1) * FBK);  // next tile in flight during the products
+        bf16x8 af[4], bf[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) af[i] = *(const bf16x8*)&As[cur][wm + 16 * i + (lane & 15)][8 * (lane >> 4)];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bf[j] = *(const bf16x8*)&Bs[cur][wn + 16 * j + (lane & 15)][8 * (lane >> 4)];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
+        if (kt + 1 < nk) stash(cur ^ 1);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
+                const int cn = n0 + wn + 16 * j + (lane & 15);
+                if (row >= g.M || cn >= g.N) continue;
+                const float v = acc[i][j][r];
+                const int64_t o = (int64_t)row * g.ldc + cn;
+                if (EPI == EPI_SILU) {
+                    const float z = v + g.bias[cn];
+                    if (g.zout) g.zout[o] = z;
+                    g.C[o] = z / (1.f + expf(-z));
+                } else {
+                    float z = v + (g.bias ? g.bias[cn] : 0.f);
+                    if (g.mu) z = g.mu[cn] + g.sd[cn] * z;
+                    g.C[o] = z;
+                }
+            }
+}
+
+// forward layer: the tiled kernel when K and the row strides allow 16-byte loads
+template <int EPI>
+void gemm_forward(const GemmArgs& g, hipStream_t st) {
+    const bool fast = g.K % FBK == 0 && g.lak == 1 && g.lbk == 1 && g.lam % 4 == 0 && g.lbn % 8 == 0 &&
+                      ((uintptr_t)g.A & 15) == 0 && ((uintptr_t)g.B & 15) == 0;
+    if (fast) {
+        const dim3 grid((unsigned)((g.N + FBN - 1) / FBN), (unsigned)((g.M + FBM - 1) / FBM));
+        k_gemm_fwd<EPI><<<grid, 256, 0, st>>>(g);
+    } else {
+        const dim3 grid((unsigned)((g.N + GBN - 1) / GBN), (unsigned)((g.M + GBM - 1) / GBM));
+        k_gemm<__bf16, true, true, EPI><<<grid, 256, 0, st>>>(g);
+    }
+}
+
 template <typename TB, bool AK, bool BK, int EPI>
 void gemm(const GemmArgs& g, hipStream_t st) {
     const dim3 grid((unsigned)((g.N + GBN - 1) / GBN), (unsigned)((g.M + GBM - 1) / GBM));
@@ -379,14 +490,14 @@ labfm_err mlp_forward(Context* c, const labfm_mlp* net, const float* in, int64_t
             } else {
                 g.C = (l % 2 == 0) ? ping : pong;
             }
-            gemm<__bf16, true, true, EPI_SILU>(g, st);
+            gemm_forward<EPI_SILU>(g, st);
         } else {
             g.C = out;
             if (denorm) {
                 g.mu = net->mu;
                 g.sd = net->sd;
             }
-            gemm<__bf16, true, true, EPI_LINEAR>(g, st);
+            gemm_forward<EPI_LINEAR>(g, st);
         }
         H = g.C;
     }

@@ -119,6 +119,32 @@ def test_gemm_layouts_exact(env):
     assert np.array_equal(net.gb[0].cpu().numpy().astype(np.float64), dY.sum(0))
 
 
+def test_gemm_forward_tiled_exact(env):
+    """Layers whose K is a multiple of 32 take the 128 x 128 tiled kernel: exact
+    on BF16-representable inputs with ragged M and N; a SiLU layer within the
+    BF16 bound of the FP64 reference."""
+    rng = np.random.default_rng(11)
+    torch = env["torch"]
+    B = 300
+    net = _net(env, (64, 136), seed=5, ops=1, order=1, kmax=1)
+    W = rng.integers(-16, 17, (136, 64)) / 16.0
+    b = rng.integers(-8, 9, 136) / 8.0
+    net.W[0].copy_(torch.from_numpy(W).float())
+    net.b[0].copy_(torch.from_numpy(b).float())
+    net.sync_bf16()
+    X = rng.integers(-8, 9, (B, 64)) / 8.0
+    out = net.forward(_dev(env, X.astype(np.float32)))
+    ref = X @ W.T + b
+    assert np.max(np.abs(out.cpu().numpy() - ref)) <= 1e-6 * np.max(np.abs(ref))
+    net2 = _net(env, (32, 256, 40), seed=6, ops=1, order=1, kmax=1)
+    X2 = rng.standard_normal((B, 32))
+    cache = net2.cache_for(B)
+    out2 = net2.forward(_dev(env, X2.astype(np.float32)), cache=cache)
+    Ws, bs = _params64(net2)
+    ref2, _ = OM.forward(Ws, bs, X2)
+    assert _relF(out2.cpu().numpy(), ref2) < 1e-2
+
+
 def test_gemm_two_layers_backward(env):
     """Hidden SiLU layer: the dH = dZ W path and the SiLU derivative."""
     torch = env["torch"]
