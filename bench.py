@@ -367,6 +367,26 @@ def run_batch(ctx, torch, np, L, WL, reps):
         del outs
     res["routes"] = {str(k): {1: "mixed", 2: "fp64"}.get(ctx.autotune_query(k)[0], "untuned")
                      for k in cfg["orders"]}
+    # per order class: the same batch launched eagerly, each order's kernel timed on its own
+    outs = ctx.weights_batched(sets, prec=L.PREC_FP64, use_graph=False)
+    torch.cuda.synchronize()
+    counts = np.zeros(9, dtype=np.int64)
+    for S in sets:
+        counts += np.bincount(S["order"].cpu().numpy().astype(np.int64), minlength=9)[:9]
+    ctx.timing(True)
+    for _ in range(reps):
+        ctx.weights_batched(sets, prec=L.PREC_FP64, use_graph=False, outs=outs)
+    torch.cuda.synchronize()
+    ctx.timing(False)
+    per = {}
+    for k in range(1, 9):
+        nk, ms_k = ctx.timing_read("weights64_k%d" % k)
+        if counts[k] and nk:
+            per[str(k)] = {"nodes": int(counts[k]), "ms": ms_k / reps,
+                           "weight_sets_per_s": int(counts[k]) / (ms_k / reps / 1e3)}
+    ctx.timing_read(None)
+    res["per_order_fp64"] = per
+    del outs
     single = [None] * len(sets)
 
     def per_set():

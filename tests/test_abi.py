@@ -55,3 +55,27 @@ def test_last_error_on_bad_arguments(lib):
     rc = lib.labfm_apply_operator(None, None, None, ctypes.c_int64(0), ctypes.c_int64(0), 1, None, 0, None, None, None)
     assert rc == -1
     assert b"ctx" in lib.labfm_last_error()
+
+
+def test_new_entry_points_validate_before_device_work(lib):
+    """Batched weights, autotune query and the warm-start calls reject a NULL
+    context (or network) with LABFM_EINVAL and a message, without a GPU."""
+    c = ctypes
+    lib.labfm_last_error.restype = c.c_char_p
+    calls = {
+        "labfm_weights_batched": (None, 1, None, None, 0, None),
+        "labfm_autotune_query": (None, 0, 0, c.c_uint(7), 8, None, None, None, None),
+        "labfm_mlp_features": (None, None, None, c.c_int64(0), None, None, None, None, 64, None, None),
+        "labfm_mlp_forward": (None, None, None, c.c_int64(0), None, None, 0, None),
+        "labfm_mlp_backward": (None, None, None, None, None, c.c_int64(0), None, None),
+        "labfm_mlp_moment_loss": (None, None, None, None, None, 8, c.c_uint(7), c.c_int64(0), None, None, None),
+        "labfm_mlp_adam": (None, None, None, None, None, None, c.c_int64(0), None, c.c_int64(1), None),
+        "labfm_mlp_cast_bf16": (None, None, None, c.c_int64(0), None),
+    }
+    for name, args in calls.items():
+        fn = getattr(lib, name)
+        fn.restype = c.c_int
+        assert fn(*args) == -1, name
+        assert lib.labfm_last_error(), name
+    lib.labfm_mlp_cache_floats.restype = c.c_int64
+    assert lib.labfm_mlp_cache_floats(None, c.c_int64(10)) == -1
