@@ -299,6 +299,112 @@ __global__ __launch_bounds__(256) void k_gemm_fwd(GemmArgs g) {
             }
 }
 
+// Inference through every layer in one kernel: a block takes 64 rows, keeps
+// their activations in LDS as BF16 (two 64 x 256 buffers), and each wave
+// computes 64 output columns of a layer (4 x 4 MFMA tiles), its weight
+// fragments read from L2 one k-step ahead.  Widths <= 256; the input width and
+// every hidden width a multiple of 32.
+constexpr int FMB = 64, FMW = 256, FALD = FMW + 8;
+
+struct FusedArgs {
+    const float* in;
+    int64_t B;
+    float* out;
+    int L;
+    int dims[LABFM_MLP_MAX_LAYERS + 1];
+    const __bf16* W[LABFM_MLP_MAX_LAYERS];
+    const float* b[LABFM_MLP_MAX_LAYERS];
+    const float* mu;
+    const float* sd;
+};
+
+__global__ __launch_bounds__(256) void k_mlp_fused(FusedArgs f) {
+    __shared__ __bf16 act[2][FMB][FALD];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t r0 = (int64_t)blockIdx.x * FMB;
+    const int K0 = f.dims[0];
+    for (int e = tid * 4; e < FMB * K0; e += 256 * 4) {  // K0 % 4 == 0: a float4 never straddles rows
+        const int r = e / K0, k = e % K0;
+        floatx4 v = floatx4{0.f, 0.f, 0.f, 0.f};
+        if (r0 + r < f.B) v = *(const floatx4*)(f.in + (r0 + r) * K0 + k);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) act[0][r][k + q] = (__bf16)v[q];
+    }
+    __syncthreads();
+    int cur = 0;
+    for (int l = 0; l < f.L; ++l) {
+        const int K = f.dims[l], N = f.dims[l + 1];
+        const __bf16* W = f.W[l];
+        const int wn = 64 * w;
+        floatx4 acc[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+        if (wn < N) {  // wave-uniform
+            bf16x8 bf[4], bn[4];
+            auto wload = [&](int k0, bf16x8(&dst)[4]) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int n = wn + 16 * j + (lane & 15);
+                    if (n < N) {
+                        dst[j] = *(const bf16x8*)(W + (int64_t)n * K + k0 + 8 * (lane >> 4));
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) dst[j][e] = (__bf16)0.f;
+                    }
+                }
+            };
+            wload(0, bf);
+            for (int k0 = 0; k0 < K; k0 += 32) {
+                if (k0 + 32 < K) wload(k0 + 32, bn);
+                bf16x8 af[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) af[i] = *(const bf16x8*)&act[cur][16 * i + (lane & 15)][k0 + 8 * (lane >> 4)];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) bf[j] = bn[j];
+            }
+        }
+        const bool last = l + 1 == f.L;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = 16 * i + 4 * (lane >> 4) + r;
+                    const int cn = wn + 16 * j + (lane & 15);
+                    if (cn >= N) continue;
+                    const float z = acc[i][j][r] + f.b[l][cn];
+                    if (!last) {
+                        act[cur ^ 1][row][cn] = (__bf16)(z / (1.f + expf(-z)));
+                    } else if (r0 + row < f.B) {
+                        f.out[(r0 + row) * N + cn] = f.mu ? f.mu[cn] + f.sd[cn] * z : z;
+                    }
+                }
+        __syncthreads();
+        cur ^= 1;
+    }
+}
+
+bool fused_ok(const labfm_mlp* net, const float* in) {
+    const int L = net->n_layers;
+    if (net->dims[0] % 32 != 0 || net->dims[0] > FMW || ((uintptr_t)in & 15) != 0) return false;
+    for (int l = 1; l <= L; ++l) {
+        if (net->dims[l] > FMW) return false;
+        if (l < L && net->dims[l] % 32 != 0) return false;
+    }
+    for (int l = 0; l < L; ++l)
+        if (((uintptr_t)net->W[l] & 15) != 0) return false;
+    return true;
+}
+
+// forward layer: the tiled kernel when K and the row strides allow 16-byte loads
 // forward layer: the tiled kernel when K and the row strides allow 16-byte loads
 template <int EPI>
 void gemm_forward(const GemmArgs& g, hipStream_t st) {
@@ -456,6 +562,24 @@ labfm_err mlp_forward(Context* c, const labfm_mlp* net, const float* in, int64_t
                       int denorm, hipStream_t st) {
     if (B <= 0) return LABFM_OK;
     const int L = net->n_layers;
+    if (!cache && fused_ok(net, in)) {
+        KernelTimer timer(c, "mlp_forward", st);
+        FusedArgs f{};
+        f.in = in;
+        f.B = B;
+        f.out = out;
+        f.L = L;
+        for (int l = 0; l <= L; ++l) f.dims[l] = net->dims[l];
+        for (int l = 0; l < L; ++l) {
+            f.W[l] = (const __bf16*)net->W[l];
+            f.b[l] = net->b[l];
+        }
+        f.mu = denorm ? net->mu : nullptr;
+        f.sd = denorm ? net->sd : nullptr;
+        k_mlp_fused<<<(unsigned)((B + FMB - 1) / FMB), 256, 0, st>>>(f);
+        LABFM_HIP_CHECK(hipGetLastError());
+        return LABFM_OK;
+    }
     float* ping = nullptr;
     float* pong = nullptr;
     if (!cache && L > 1) {

@@ -133,9 +133,10 @@ def test_gemm_forward_tiled_exact(env):
     net.b[0].copy_(torch.from_numpy(b).float())
     net.sync_bf16()
     X = rng.integers(-8, 9, (B, 64)) / 8.0
-    out = net.forward(_dev(env, X.astype(np.float32)))
+    Xt = _dev(env, X.astype(np.float32))
     ref = X @ W.T + b
-    assert np.max(np.abs(out.cpu().numpy() - ref)) <= 1e-6 * np.max(np.abs(ref))
+    for out in (net.forward(Xt), net.forward(Xt, cache=net.cache_for(B))):  # fused inference, tiled layer
+        assert np.max(np.abs(out.cpu().numpy() - ref)) <= 1e-6 * np.max(np.abs(ref))
     net2 = _net(env, (32, 256, 40), seed=6, ops=1, order=1, kmax=1)
     X2 = rng.standard_normal((B, 32))
     cache = net2.cache_for(B)
@@ -178,6 +179,23 @@ def small_set():
     assert np.all(st == 0)
     feat = OM.stencil_features(L["x"], L["y"], L["domain"], L["R"], L["rp"], L["col"], kmax=cfg["kmax"])
     return dict(L=L, psi=psi, M=M, feat=feat, cfg=cfg)
+
+
+def test_fused_inference_matches_layers(env, small_set):
+    """Inference through all layers in one kernel (activations kept in LDS as
+    BF16) against the layer-by-layer kernels and the FP64 reference."""
+    cfg = small_set["cfg"]
+    net = _net(env, cfg["dims"], seed=12)
+    mu, sd = MD.robust_scaling(small_set["psi"])
+    net.set_output_scaling(mu, sd)
+    X = small_set["feat"][:777]
+    Xt = _dev(env, X)
+    fused = net.forward(Xt, denorm=True).cpu().numpy()
+    layered = net.forward(Xt, cache=net.cache_for(X.shape[0]), denorm=True).cpu().numpy()
+    assert np.max(np.abs(fused - layered)) <= 1e-5 * np.max(np.abs(layered))
+    Ws, bs = _params64(net)
+    ref, _ = OM.forward(Ws, bs, X.astype(np.float64))
+    assert _relF(net.forward(Xt).cpu().numpy(), ref) < 1e-2
 
 
 def test_moment_loss_parity(env, small_set):
