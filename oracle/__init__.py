@@ -62,7 +62,7 @@ def lib():
         L.or_stencils_psi.restype = None
         L.or_apply.argtypes = [C.c_int64, i64, i32, dp, dp, dp]
         L.or_combine.argtypes = [C.c_int64, C.c_int, dp, dp, dp]
-        L.or_rk4.argtypes = [C.c_int64, i64, i32, dp, dp, C.c_double, C.c_double, C.c_int, dp]
+        L.or_rk4.argtypes = [C.c_int64, i64, i32, dp, dp, C.c_double, C.c_double, C.c_int, dp, i8]
         L.or_num_threads.restype = C.c_int
         L.or_set_num_threads.argtypes = [C.c_int]
         _lib = L
@@ -243,7 +243,9 @@ def combine(w, coef):
     return out
 
 
-def rk4(row_ptr, col, w_lin, w_bh, gamma, dt, nsteps, u0):
+def rk4(row_ptr, col, w_lin, w_bh, gamma, dt, nsteps, u0, fixed=None):
+    """Classical RK4 on du/dt = L_lin u - gamma B(B u); nodes with fixed != 0
+    keep their value (Dirichlet)."""
     row_ptr = np.ascontiguousarray(row_ptr, np.int64)
     col = np.ascontiguousarray(col, np.int32)
     w_lin = np.ascontiguousarray(w_lin, np.float64)
@@ -252,9 +254,13 @@ def rk4(row_ptr, col, w_lin, w_bh, gamma, dt, nsteps, u0):
     if w_bh is not None:
         w_bh = np.ascontiguousarray(w_bh, np.float64)
         wb = _p(w_bh, C.c_double)
+    fx = None
+    if fixed is not None:
+        fixed = np.ascontiguousarray(fixed, np.int8)
+        fx = _p(fixed, C.c_int8)
     n = row_ptr.size - 1
     lib().or_rk4(n, _p(row_ptr, C.c_int64), _p(col, C.c_int32), _p(w_lin, C.c_double), wb,
-                 float(gamma), float(dt), int(nsteps), _p(u, C.c_double))
+                 float(gamma), float(dt), int(nsteps), _p(u, C.c_double), fx)
     return u
 
 

@@ -814,19 +814,31 @@ static void or_rhs(int64_t n, const int64_t* rp, const int32_t* col, const doubl
     }
 }
 
+/* Dirichlet nodes (fixed[i] != 0, Sec. 4.1): u is prescribed there, so its
+ * time derivative is zero and only the other nodes are advanced. */
+static void or_pin(int64_t n, const int8_t* fixed, double* k) {
+    if (!fixed) return;
+    for (int64_t i = 0; i < n; ++i)
+        if (fixed[i]) k[i] = 0.0;
+}
+
 void or_rk4(int64_t n, const int64_t* row_ptr, const int32_t* col, const double* w_lin,
-            const double* w_bh, double gamma, double dt, int nsteps, double* u) {
+            const double* w_bh, double gamma, double dt, int nsteps, double* u, const int8_t* fixed) {
     size_t sz = sizeof(double) * (size_t)(n > 0 ? n : 1);
     double *k1 = malloc(sz), *k2 = malloc(sz), *k3 = malloc(sz), *k4 = malloc(sz);
     double *us = malloc(sz), *t1 = malloc(sz), *t2 = malloc(sz);
     for (int st = 0; st < nsteps; ++st) {
         or_rhs(n, row_ptr, col, w_lin, w_bh, gamma, u, k1, t1, t2);
+        or_pin(n, fixed, k1);
         for (int64_t i = 0; i < n; ++i) us[i] = u[i] + 0.5 * dt * k1[i];
         or_rhs(n, row_ptr, col, w_lin, w_bh, gamma, us, k2, t1, t2);
+        or_pin(n, fixed, k2);
         for (int64_t i = 0; i < n; ++i) us[i] = u[i] + 0.5 * dt * k2[i];
         or_rhs(n, row_ptr, col, w_lin, w_bh, gamma, us, k3, t1, t2);
+        or_pin(n, fixed, k3);
         for (int64_t i = 0; i < n; ++i) us[i] = u[i] + dt * k3[i];
         or_rhs(n, row_ptr, col, w_lin, w_bh, gamma, us, k4, t1, t2);
+        or_pin(n, fixed, k4);
         for (int64_t i = 0; i < n; ++i)
             u[i] = u[i] + dt / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
     }

@@ -77,7 +77,8 @@ void or_apply(int64_t n, const int64_t* row_ptr, const int32_t* col, const doubl
               const double* u, double* out);
 void or_combine(int64_t nnz, int nsets, const double* w, const double* coef, double* out);
 void or_rk4(int64_t n, const int64_t* row_ptr, const int32_t* col, const double* w_lin,
-            const double* w_bh, double gamma, double dt, int nsteps, double* u);
+            const double* w_bh, double gamma, double dt, int nsteps, double* u,
+            const int8_t* fixed /* optional [n]: Dirichlet nodes, not advanced */);
 int or_num_threads(void);
 void or_set_num_threads(int t);
 

@@ -272,8 +272,11 @@ labfm_err step_launch(Context* c, const labfm_step_plan* p, void* u, void* scrat
     }
     // capture one step on a private stream once per (plan, buffers, stream);
     // replay the graph nsteps times on `st`
+    const labfm_step_plan& k = c->step_key;  // field by field: the struct has padding
     const bool same = c->step_exec && c->step_stream == st && c->step_u == u && c->step_scratch == scratch &&
-                      memcmp(&c->step_key, p, sizeof(*p)) == 0;
+                      k.row_ptr == p->row_ptr && k.col == p->col && k.n == p->n && k.nnz == p->nnz &&
+                      k.dtype == p->dtype && k.w_lin == p->w_lin && k.w_bh == p->w_bh && k.gamma == p->gamma &&
+                      k.dt == p->dt;
     if (!same) {
         if (c->step_exec) LABFM_HIP_CHECK(hipStreamSynchronize(c->step_stream));
         release_step_graph(c);

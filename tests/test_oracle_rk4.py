@@ -84,3 +84,55 @@ def test_composed_hyperviscosity_is_dissipative():
     dy = (y[col[s_:e_]] - y[i] + 0.5) % 1.0 - 0.5
     f = dx ** 4 + dy ** 2 * dx ** 2
     assert (f * w[0][s_:e_]).sum() == pytest.approx(-(24.0 + 2 * 4.0), rel=1e-7)
+
+
+def _csr_matrix(rp, col, w):
+    """Dense matrix of L_i(u) = sum_j (u_j - u_i) w_ij (Sec. 3.1)."""
+    n = rp.size - 1
+    A = np.zeros((n, n))
+    for i in range(n):
+        for e in range(rp[i], rp[i + 1]):
+            A[i, col[e]] += w[e]
+            A[i, i] -= w[e]
+    return A
+
+
+@pytest.mark.parametrize("with_bh", [False, True])
+def test_rk4_is_degree4_taylor_polynomial_with_dirichlet_nodes(with_bh):
+    """On a linear system du/dt = D (A - gamma B B) u, where D zeroes the rows
+    of the Dirichlet nodes, one classical RK4 step is exactly the degree-4
+    Taylor polynomial of exp(dt D (A - gamma B B)); fixed nodes never move."""
+    import oracle as O
+
+    rng = np.random.default_rng(11)
+    n = 14
+    rp = [0]
+    cols = []
+    for i in range(n):
+        nb = rng.choice([j for j in range(n) if j != i], size=int(rng.integers(2, 6)), replace=False)
+        cols.extend(sorted(int(j) for j in nb))
+        rp.append(len(cols))
+    rp = np.array(rp, np.int64)
+    col = np.array(cols, np.int32)
+    w_lin = rng.normal(size=col.size)
+    w_bh = rng.normal(size=col.size) if with_bh else None
+    gamma = 0.3 if with_bh else 0.0
+    fixed = np.zeros(n, np.int8)
+    fixed[[0, 5, 13]] = 1
+    u0 = rng.normal(size=n)
+    dt, nsteps = 0.02, 7
+    M = _csr_matrix(rp, col, w_lin)
+    if with_bh:
+        B = _csr_matrix(rp, col, w_bh)
+        M = M - gamma * B @ B
+    M = np.diag(1.0 - fixed) @ M
+    Z = dt * M
+    P = np.eye(n) + Z + Z @ Z / 2 + Z @ Z @ Z / 6 + Z @ Z @ Z @ Z / 24
+    expect = np.linalg.matrix_power(P, nsteps) @ u0
+    got = O.rk4(rp, col, w_lin, w_bh, gamma, dt, nsteps, u0, fixed=fixed)
+    assert np.allclose(got, expect, rtol=0, atol=1e-12 * np.abs(expect).max())
+    assert np.array_equal(got[fixed == 1], u0[fixed == 1])
+    # no mask and an all-zero mask are the same integration
+    a = O.rk4(rp, col, w_lin, w_bh, gamma, dt, nsteps, u0)
+    b = O.rk4(rp, col, w_lin, w_bh, gamma, dt, nsteps, u0, fixed=np.zeros(n, np.int8))
+    assert np.array_equal(a, b)
