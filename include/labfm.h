@@ -7,7 +7,7 @@
  *   2. per-node weights (Sec. 3.1: M_i = sum_j X_ji (x) W_ji, M_i Psi^d = C^d,
  *      w^d_ji = W_ji . Psi^d),
  *   3. operator application (Sec. 2 eq. general_do: L^d_i(u) = sum_j (u_j - u_i) w^d_ji),
- *   4. explicit RK4 time stepping with those operators (Sec. 4.1).
+ *   4. explicit RK4 time stepping with those operators (Sec. 5.1).
  *
  * Conventions shared by every entry point:
  *   - Pointers named as device pointers must point to memory on the
@@ -43,9 +43,13 @@ typedef enum {
 /* ABF family.  HERMITE: W_m(d) = H_a(sigma d_x) H_b(sigma d_y) phi(|d|)
  * (physicists' Hermite polynomials times a radial function).  PAPER:
  * W_m = d^a_x d^b_y W0(|d|) (Sec. 3.2), keeping only the dW0/dr term for
- * elements of total order >= 4 (App. A).  (a, b) follow the element order of
- * the monomial vector X (Sec. 2 eq. 1). */
-typedef enum { LABFM_ABF_HERMITE = 0, LABFM_ABF_PAPER = 1 } labfm_abf;
+ * elements of total order >= 4 (App. A).  PAPER_D1: every element keeps only
+ * the dW0/dr term, W_m = dW0/dr(|d|) d^a_x d^b_y |d| (the App. A truncation
+ * applied to all elements; with this family the quadratic RBF shows the
+ * stability limits of Table noise_limits and the Dirichlet rates of Table
+ * heatss).  For the cone (dW0/dr constant) PAPER and PAPER_D1 coincide.
+ * (a, b) follow the element order of the monomial vector X (Sec. 2 eq. 1). */
+typedef enum { LABFM_ABF_HERMITE = 0, LABFM_ABF_PAPER = 1, LABFM_ABF_PAPER_D1 = 2 } labfm_abf;
 
 /* Fundamental RBF (App. A): cone, quadratic, Wendland C6, Gaussian, and the
  * 2-D Wendland C2 (1 - q/2)^4 (1 + 2q).  Constants do not change weights. */
@@ -58,7 +62,7 @@ typedef enum {
 } labfm_rbf;
 
 /* Operators (bits; weight sets are written in increasing bit order).
- * Targets C^d (Sec. 2, Sec. 3.3): DX e1, DY e2, LAP e3 + e5,
+ * Targets C^d (Sec. 2, Sec. 4.2): DX e1, DY e2, LAP e3 + e5,
  * BIHARM -(e10 + 2 e12 + e14) (i.e. -nabla^4, needs k >= 4),
  * TRIHARM e21 + 3 e23 + 3 e25 + e27 (nabla^6, needs k >= 6). */
 enum {
@@ -246,9 +250,13 @@ labfm_err labfm_apply_operator(void* ctx, const int64_t* row_ptr, const int32_t*
                                int64_t nnz, int nops, const void* w, int dtype, const void* u,
                                void* out, void* stream);
 
-/* Classical RK4 (Sec. 4.1) on du/dt = L_lin(u) - gamma B(B(u)), where L_lin
+/* Classical RK4 (Sec. 5.1) on du/dt = L_lin(u) - gamma B(B(u)), where L_lin
  * uses w_lin and B (optional) uses w_bh; with B the -nabla^4 stencil,
- * B o B approximates nabla^8 (composed hyperviscosity). */
+ * B o B approximates nabla^8 (composed hyperviscosity).  Dirichlet nodes
+ * (Sec. 5.1, heat equation with prescribed boundary values): where fixed[i]
+ * is non-zero every stage derivative of node i is zero, so u[i] keeps the
+ * value the caller put there; the other nodes still read it through their
+ * stencils. */
 typedef struct {
     const int64_t* row_ptr; /* device int64 [n+1]                   */
     const int32_t* col;     /* device int32 [nnz]                   */
@@ -258,6 +266,7 @@ typedef struct {
     const void* w_bh;       /* device [nnz] or NULL                 */
     double gamma;           /* coefficient of B(B(u))               */
     double dt;
+    const int8_t* fixed;    /* device int8 [n] or NULL (no Dirichlet nodes) */
 } labfm_step_plan;
 
 /* Advance u (device [n], dtype of the plan) by nsteps RK4 steps.

@@ -6,7 +6,7 @@ code with the HIP library, and the library never imports it.
 
 Method: King, Lind & Nasar, arXiv:1912.06441 -- Sec. 2 (operator, eq. general_do),
 Sec. 3.1 (moment system, eqs. w_abf / disc_form / lsys), Sec. 3.2 and App. A
-(ABFs), Sec. 3.3 (hyperviscosity targets), Sec. 4.1 (RK4).
+(ABFs), Sec. 4.2 (hyperviscosity targets), Sec. 5.1 (RK4).
 """
 import ctypes as C
 import os
@@ -15,7 +15,7 @@ import numpy as np
 
 from . import build as _build
 
-ABF_HERMITE, ABF_PAPER = 0, 1
+ABF_HERMITE, ABF_PAPER, ABF_PAPER_D1 = 0, 1, 2
 RBF_WENDLAND_C2, RBF_CONE, RBF_QUADRATIC, RBF_WENDLAND_C6, RBF_GAUSSIAN = 0, 1, 2, 3, 4
 OP_DX, OP_DY, OP_LAP, OP_BIHARM, OP_TRIHARM = 1, 2, 4, 8, 16
 ST_OK, ST_NOT_CONVERGED, ST_SINGULAR, ST_TOO_FEW, ST_DEGENERATE, ST_ORDER_TOO_LOW = range(6)
@@ -171,7 +171,7 @@ def node_weights(k, dxh, dyh, **kw):
 
 
 def targets(ops, k):
-    """Target vectors C^d (Sec. 2, Sec. 3.3) of the operators in `ops`, [nops, p]."""
+    """Target vectors C^d (Sec. 2, Sec. 4.2) of the operators in `ops`, [nops, p]."""
     C_ = np.zeros((nops(ops), p_of_k(k)))
     if lib().or_targets(int(ops), int(k), _p(C_, C.c_double)) != 0:
         raise ValueError("order %d cannot express the requested operators" % k)

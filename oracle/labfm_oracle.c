@@ -226,7 +226,10 @@ static void or_paper_low(int a, int b, double x, double y, double r, const doubl
 }
 
 /* ABF vector W(d) for offset d = (dx, dy) in units of h.  Returns nonzero if
- * the ABFs are undefined at this offset (PAPER family at d = 0). */
+ * the ABFs are undefined at this offset (PAPER families at d = 0).
+ * PAPER: full derivatives of W0 up to total order 3, then only the dW0/dr
+ * term (App. A).  PAPER_D1: only the dW0/dr term in every element (the App. A
+ * truncation applied from the first element on). */
 int or_abfs(int family, int rbf, double sigma, int k, double dx, double dy, double* W) {
     int ea[OR_MAXP], eb[OR_MAXP];
     or_index_table(k, ea, eb);
@@ -244,7 +247,7 @@ int or_abfs(int family, int rbf, double sigma, int k, double dx, double dy, doub
     if (q == 0.0) return 1;
     for (int m = 0; m < p; ++m) {
         int a = ea[m], b = eb[m], n = a + b;
-        if (n <= 3) {
+        if (family == OR_ABF_PAPER && n <= 3) {
             or_paper_low(a, b, dx, dy, q, f, &W[m]);
         } else {
             double den = 1.0;
@@ -432,7 +435,7 @@ int64_t or_neighbours_cells(int64_t n, const double* x, const double* y, const o
 }
 
 /* ------------------------------------------------------------------------ */
-/* Target vectors C^d (Sec. 2 and Sec. 3.3), in element order of X.          */
+/* Target vectors C^d (Sec. 2 and Sec. 4.2), in element order of X.          */
 /* x: e1; y: e2; Laplacian: e3 + e5; -nabla^4: -(e10 + 2 e12 + e14);        */
 /* nabla^6: e21 + 3 e23 + 3 e25 + e27 (1-based).  l = derivative order.      */
 static int or_target(unsigned op, int p, double* C, int* l) {
@@ -801,7 +804,7 @@ void or_combine(int64_t nnz, int nsets, const double* w, const double* coef, dou
     }
 }
 
-/* Classical RK4 (Sec. 4.1) on du/dt = L_lin(u) - gamma B(B(u)), where B is
+/* Classical RK4 (Sec. 5.1) on du/dt = L_lin(u) - gamma B(B(u)), where B is
  * the biharmonic stencil (B o B approximates nabla^8) or absent. */
 static void or_rhs(int64_t n, const int64_t* rp, const int32_t* col, const double* w_lin,
                    const double* w_bh, double gamma, const double* u, double* f, double* t1,
@@ -814,7 +817,7 @@ static void or_rhs(int64_t n, const int64_t* rp, const int32_t* col, const doubl
     }
 }
 
-/* Dirichlet nodes (fixed[i] != 0, Sec. 4.1): u is prescribed there, so its
+/* Dirichlet nodes (fixed[i] != 0, Sec. 5.1): u is prescribed there, so its
  * time derivative is zero and only the other nodes are advanced. */
 static void or_pin(int64_t n, const int8_t* fixed, double* k) {
     if (!fixed) return;

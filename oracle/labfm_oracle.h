@@ -11,8 +11,8 @@
  *   Sec. 2 eq. (general_do)      L_i(u) = sum_j (u_j - u_i) w_ji
  *   Sec. 3.1 eqs. (w_abf), (disc_form), (lsys)   w = W.Psi, M = sum X (x) W, M Psi = C
  *   Sec. 3.2 eq. (conic_abs) and App. A          ABFs from a fundamental RBF
- *   Sec. 3.3 (stability)         hyperviscosity target vectors
- *   Sec. 4.1                     classical RK4
+ *   Sec. 4.2 (stability)         hyperviscosity target vectors
+ *   Sec. 5.1                     classical RK4
  * Readings where the paper is silent are listed at each function.
  */
 #ifndef LABFM_ORACLE_H
@@ -24,7 +24,7 @@
 
 /* ABF families: HERMITE = H_a(s dx) H_b(s dy) phi(|d|); PAPER = D^(a,b) W0(|d|)
  * with the App. A truncation (only the dW0/dr term for total order >= 4). */
-enum { OR_ABF_HERMITE = 0, OR_ABF_PAPER = 1 };
+enum { OR_ABF_HERMITE = 0, OR_ABF_PAPER = 1, OR_ABF_PAPER_D1 = 2 };
 enum { OR_RBF_WENDLAND_C2 = 0, OR_RBF_CONE = 1, OR_RBF_QUADRATIC = 2,
        OR_RBF_WENDLAND_C6 = 3, OR_RBF_GAUSSIAN = 4 };
 /* operator bits, in output order */

@@ -7,7 +7,7 @@ or no GPU is present, calls raise.
 
 Method: King, Lind & Nasar, "High order difference schemes using the Local
 Anisotropic Basis Function Method", arXiv:1912.06441 (Sec. 2, 3.1, 3.2,
-App. A, Sec. 4.1).
+App. A, Sec. 4.2, Sec. 5.1).
 """
 import ctypes as C
 import os
@@ -15,7 +15,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblabfm.so")
 
-ABF_HERMITE, ABF_PAPER = 0, 1
+ABF_HERMITE, ABF_PAPER, ABF_PAPER_D1 = 0, 1, 2
 RBF_WENDLAND_C2, RBF_CONE, RBF_QUADRATIC, RBF_WENDLAND_C6, RBF_GAUSSIAN = 0, 1, 2, 3, 4
 OP_DX, OP_DY, OP_LAP, OP_BIHARM, OP_TRIHARM = 1, 2, 4, 8, 16
 PREC_FP64, PREC_MIXED, PREC_MLP = 0, 1, 2
@@ -67,7 +67,7 @@ class NodeSetDesc(C.Structure):
 class StepPlan(C.Structure):
     _fields_ = [("row_ptr", C.c_void_p), ("col", C.c_void_p), ("n", C.c_int64), ("nnz", C.c_int64),
                 ("dtype", C.c_int), ("w_lin", C.c_void_p), ("w_bh", C.c_void_p), ("gamma", C.c_double),
-                ("dt", C.c_double)]
+                ("dt", C.c_double), ("fixed", C.c_void_p)]
 
 
 _lib = None
@@ -315,15 +315,19 @@ class Context:
         return feat
 
     # ------------------------------------------------------------------ time stepping
-    def step(self, row_ptr, col, w_lin, w_bh, gamma, dt, u, nsteps, scratch=None, use_graph=True):
-        """Advance u in place by nsteps RK4 steps of du/dt = L_lin u - gamma B(B u)."""
+    def step(self, row_ptr, col, w_lin, w_bh, gamma, dt, u, nsteps, scratch=None, use_graph=True, fixed=None):
+        """Advance u in place by nsteps RK4 steps of du/dt = L_lin u - gamma B(B u);
+        nodes with fixed != 0 (int8 device tensor [n]) keep their value."""
         torch = self.torch
         n = u.numel()
         if scratch is None:
             scratch = torch.empty(5 * n, dtype=u.dtype, device=u.device)
         dtype = 1 if u.dtype == torch.float64 else 0
+        if fixed is not None and (fixed.dtype != torch.int8 or fixed.numel() != n or not fixed.is_contiguous()):
+            raise ValueError("fixed must be a contiguous int8 tensor of n entries")
         plan = StepPlan(row_ptr.data_ptr(), col.data_ptr(), n, col.numel(), dtype, w_lin.data_ptr(),
-                        w_bh.data_ptr() if w_bh is not None else None, float(gamma), float(dt))
+                        w_bh.data_ptr() if w_bh is not None else None, float(gamma), float(dt),
+                        fixed.data_ptr() if fixed is not None else None)
         _check(self.lib.labfm_step(self.h, C.byref(plan), _ptr(u), _ptr(scratch), int(nsteps), int(bool(use_graph)),
                                    _stream(torch)), "labfm_step")
         return u

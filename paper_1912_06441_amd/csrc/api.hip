@@ -201,7 +201,7 @@ labfm_err labfm_weights(void* ctx, const double* x, const double* y, int64_t n, 
     if (n < 0 || n > INT32_MAX || nnz < 0) return fail(LABFM_EINVAL, "labfm_weights: n or nnz out of range");
     if (!domain_ok(dom)) return fail(LABFM_EINVAL, "labfm_weights: bad domain");
     if (opt->ops == 0 || (opt->ops & ~31u)) return fail(LABFM_EINVAL, "labfm_weights: ops must be a nonzero set of LABFM_OP_* bits");
-    if (opt->abf != LABFM_ABF_HERMITE && opt->abf != LABFM_ABF_PAPER) return fail(LABFM_EINVAL, "labfm_weights: bad abf");
+    if (opt->abf < LABFM_ABF_HERMITE || opt->abf > LABFM_ABF_PAPER_D1) return fail(LABFM_EINVAL, "labfm_weights: bad abf");
     if (opt->rbf < 0 || opt->rbf > 4) return fail(LABFM_EINVAL, "labfm_weights: bad rbf");
     if (!(opt->sigma > 0.0) || !std::isfinite(opt->sigma)) return fail(LABFM_EINVAL, "labfm_weights: sigma must be > 0");
     if (opt->max_iters < 0 || opt->max_iters > 100) return fail(LABFM_EINVAL, "labfm_weights: max_iters out of range");
@@ -261,7 +261,7 @@ labfm_err labfm_weights_batched(void* ctx, int nsets, const labfm_node_set* sets
     if (!ctx || !opt) return fail(LABFM_EINVAL, "labfm_weights_batched: ctx or opt is NULL");
     if (nsets < 1 || !sets) return fail(LABFM_EINVAL, "labfm_weights_batched: need nsets >= 1 and a set table");
     if (opt->ops == 0 || (opt->ops & ~31u)) return fail(LABFM_EINVAL, "labfm_weights_batched: bad ops");
-    if (opt->abf != LABFM_ABF_HERMITE && opt->abf != LABFM_ABF_PAPER) return fail(LABFM_EINVAL, "labfm_weights_batched: bad abf");
+    if (opt->abf < LABFM_ABF_HERMITE || opt->abf > LABFM_ABF_PAPER_D1) return fail(LABFM_EINVAL, "labfm_weights_batched: bad abf");
     if (opt->rbf < 0 || opt->rbf > 4) return fail(LABFM_EINVAL, "labfm_weights_batched: bad rbf");
     if (!(opt->sigma > 0.0) || !std::isfinite(opt->sigma)) return fail(LABFM_EINVAL, "labfm_weights_batched: sigma must be > 0");
     if (opt->max_iters < 0 || opt->max_iters > 100) return fail(LABFM_EINVAL, "labfm_weights_batched: max_iters out of range");

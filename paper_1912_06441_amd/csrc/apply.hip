@@ -8,7 +8,8 @@
 // the G lanes with shuffles.  Several operators on the same neighbour
 // structure share the index stream.
 //
-// Time stepping: classical RK4 (Sec. 4.1) on du/dt = L_lin(u) - gamma B(B(u)).
+// Time stepping: classical RK4 (Sec. 5.1) on du/dt = L_lin(u) - gamma B(B(u)),
+// with optional Dirichlet nodes whose stage derivatives are zero.
 // With B present each stage is two passes: A computes L_lin(u_s) and B(u_s)
 // with one read of the index stream; B applies B to that result, forms the
 // stage derivative and the stage update.  Without B one pass per stage.
@@ -113,9 +114,10 @@ __global__ void k_combine(const double* __restrict__ w, int nsets, double c0, do
     if (out32) out32[s] = (float)acc;
 }
 
-// stage update: k is the stage derivative at node i
+// stage update: k is the stage derivative at node i (zero on Dirichlet nodes)
 template <typename T>
-__device__ inline void rk4_update(int stage, T k, T dt, int64_t i, T* u, T* acc, T* us_out) {
+__device__ inline void rk4_update(int stage, T k, T dt, int64_t i, const int8_t* fixed, T* u, T* acc, T* us_out) {
+    if (fixed && fixed[i]) k = T(0);
     const T ui = u[i];
     if (stage == 0) {
         acc[i] = k;
@@ -135,7 +137,8 @@ __device__ inline void rk4_update(int stage, T k, T dt, int64_t i, T* u, T* acc,
 template <typename T>
 __global__ __launch_bounds__(256) void k_step_single(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                                                      int64_t n, const T* __restrict__ wl, const T* us_in, T dt,
-                                                     int stage, T* u, T* acc, T* us_out) {
+                                                     int stage, const int8_t* __restrict__ fixed, T* u, T* acc,
+                                                     T* us_out) {
     constexpr int G = Shape<T>::G, U = Shape<T>::U;
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t row = gid / G;
@@ -145,7 +148,7 @@ __global__ __launch_bounds__(256) void k_step_single(const int64_t* __restrict__
     T a[1] = {T(0)};
     row_sums<T, G, U, 1>(col, rp[row], rp[row + 1], sub, wp, us_in, us_in[row], a);
     const T k = group_sum<T, G>(a[0]);
-    if (sub == 0) rk4_update<T>(stage, k, dt, row, u, acc, us_out);
+    if (sub == 0) rk4_update<T>(stage, k, dt, row, fixed, u, acc, us_out);
 }
 
 // pass A: ra = L_lin(us_in), b1 = B(us_in), one read of the index stream
@@ -173,8 +176,8 @@ __global__ __launch_bounds__(256) void k_step_a(const int64_t* __restrict__ rp, 
 template <typename T>
 __global__ __launch_bounds__(256) void k_step_b(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                                                 int64_t n, const T* __restrict__ wb, const T* __restrict__ b1,
-                                                const T* __restrict__ ra, T gamma, T dt, int stage, T* u, T* acc,
-                                                T* us_out) {
+                                                const T* __restrict__ ra, T gamma, T dt, int stage,
+                                                const int8_t* __restrict__ fixed, T* u, T* acc, T* us_out) {
     constexpr int G = Shape<T>::G, U = Shape<T>::U;
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t row = gid / G;
@@ -184,7 +187,7 @@ __global__ __launch_bounds__(256) void k_step_b(const int64_t* __restrict__ rp, 
     T c[1] = {T(0)};
     row_sums<T, G, U, 1>(col, rp[row], rp[row + 1], sub, wp, b1, b1[row], c);
     const T bb = group_sum<T, G>(c[0]);
-    if (sub == 0) rk4_update<T>(stage, ra[row] - gamma * bb, dt, row, u, acc, us_out);
+    if (sub == 0) rk4_update<T>(stage, ra[row] - gamma * bb, dt, row, fixed, u, acc, us_out);
 }
 
 template <typename T>
@@ -209,11 +212,11 @@ labfm_err enqueue_step(const labfm_step_plan* p, T* u, T* scratch, hipStream_t s
         if (p->w_bh) {
             k_step_a<T><<<nb, 256, 0, st>>>(p->row_ptr, p->col, n, (const T*)p->w_lin, (const T*)p->w_bh, in[stage],
                                             ra, b1);
-            k_step_b<T><<<nb, 256, 0, st>>>(p->row_ptr, p->col, n, (const T*)p->w_bh, b1, ra, gamma, dt, stage, u,
-                                            acc, outs[stage]);
+            k_step_b<T><<<nb, 256, 0, st>>>(p->row_ptr, p->col, n, (const T*)p->w_bh, b1, ra, gamma, dt, stage,
+                                            p->fixed, u, acc, outs[stage]);
         } else {
-            k_step_single<T><<<nb, 256, 0, st>>>(p->row_ptr, p->col, n, (const T*)p->w_lin, in[stage], dt, stage, u,
-                                                 acc, outs[stage]);
+            k_step_single<T><<<nb, 256, 0, st>>>(p->row_ptr, p->col, n, (const T*)p->w_lin, in[stage], dt, stage,
+                                                 p->fixed, u, acc, outs[stage]);
         }
     }
     LABFM_HIP_CHECK(hipGetLastError());
@@ -276,7 +279,7 @@ labfm_err step_launch(Context* c, const labfm_step_plan* p, void* u, void* scrat
     const bool same = c->step_exec && c->step_stream == st && c->step_u == u && c->step_scratch == scratch &&
                       k.row_ptr == p->row_ptr && k.col == p->col && k.n == p->n && k.nnz == p->nnz &&
                       k.dtype == p->dtype && k.w_lin == p->w_lin && k.w_bh == p->w_bh && k.gamma == p->gamma &&
-                      k.dt == p->dt;
+                      k.dt == p->dt && k.fixed == p->fixed;
     if (!same) {
         if (c->step_exec) LABFM_HIP_CHECK(hipStreamSynchronize(c->step_stream));
         release_step_graph(c);

@@ -9,6 +9,7 @@
 //   HERMITE: W_m = H_a(sigma x) H_b(sigma y) phi(|d|)      (physicists' Hermite)
 //   PAPER:   W_m = d^a_x d^b_y W0(|d|) for a + b <= 3, and dW0/dr * d^a_x d^b_y |d|
 //            for a + b >= 4 (App. A truncation).
+//   PAPER_D1: dW0/dr * d^a_x d^b_y |d| for every element.
 // The PAPER family is evaluated through s = r^2 / 2: for a radial function
 // F(r) = G(s),
 //   d^a_x d^b_y G(s) = sum_{i,l} c_{a,i} c_{b,l} x^(2i-a) y^(2l-b) G^(i+l)(s),
@@ -195,7 +196,7 @@ __device__ inline void basis_prepare(BasisState<K>& B, double dx, double dy, int
         B.G[1] = F[1] * ir;
         B.G[2] = (F[2] - F[1] * ir) * ir * ir;
         B.G[3] = (F[3] - 3.0 * F[2] * ir + 3.0 * F[1] * ir * ir) * ir * ir * ir;
-        B.phi = F[1];  // W0'(q) for the truncated elements (order >= 4)
+        B.phi = F[1];  // W0'(q) for the truncated elements
         B.ir = ir;
     }
 }
@@ -212,13 +213,14 @@ __device__ inline double abf(const BasisState<K>& B, int m) {
     if (FAM == LABFM_ABF_HERMITE) return B.hx[a] * B.hy[b] * B.phi;
     int n = a + b;
     double acc = 0.0;
-    if (n <= 3) {
+    if (FAM == LABFM_ABF_PAPER && n <= 3) {
         for (int t = 0; t < FDB.nt[m]; ++t) {
             const FdbTerm& T = FDB.t[m][t];
             acc += T.coef * B.px[T.ex] * B.py[T.ey] * B.G[T.m];
         }
         return acc;
     }
+    // dW0/dr * d^a_x d^b_y |d|: orders >= 4 of PAPER, every order of PAPER_D1
     double ir = B.ir;
     for (int t = 0; t < FDB.nt[m]; ++t) {
         const FdbTerm& T = FDB.t[m][t];

@@ -72,7 +72,7 @@ __global__ __launch_bounds__(64) void k_weights_fp64(WeightArgs a, OpList ops, c
                     dyr[js] = min_image(S.y[j] - yi, S.Ly, S.pery) / h;
                     sD[0][q] = dxr[js];
                     sD[1][q] = dyr[js];
-                    if (FAM == LABFM_ABF_PAPER && dxr[js] == 0.0 && dyr[js] == 0.0) bad = true;
+                    if (FAM != LABFM_ABF_HERMITE && dxr[js] == 0.0 && dyr[js] == 0.0) bad = true;
                 }
             }
             if (__any(bad)) status = LABFM_ST_DEGENERATE;
@@ -483,6 +483,7 @@ void launch_all(Context* c, const WeightArgs& a, const OpList& ops, const int32_
 void init_weight_grids() {
     launch_grids_all<LABFM_ABF_HERMITE>();
     launch_grids_all<LABFM_ABF_PAPER>();
+    launch_grids_all<LABFM_ABF_PAPER_D1>();
 }
 
 labfm_err fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st) {
@@ -530,8 +531,10 @@ labfm_err weights_fp64_lists(Context* c, const WeightArgs& a, const int32_t* lis
         if (a.ops & (1u << b)) ops.op[ops.nops++] = 1u << b;
     if (a.abf == LABFM_ABF_HERMITE)
         launch_all<LABFM_ABF_HERMITE>(c, a, ops, list, off, cnt, mask, st);
-    else
+    else if (a.abf == LABFM_ABF_PAPER)
         launch_all<LABFM_ABF_PAPER>(c, a, ops, list, off, cnt, mask, st);
+    else
+        launch_all<LABFM_ABF_PAPER_D1>(c, a, ops, list, off, cnt, mask, st);
     LABFM_HIP_CHECK(hipGetLastError());
     return LABFM_OK;
 }

@@ -81,7 +81,7 @@ __global__ __launch_bounds__(64) void k_weights_mixed(WeightArgs a, OpList ops, 
                     dyr[js] = min_image(S.y[j] - yi, S.Ly, S.pery) / h;
                     sD[0][q] = dxr[js];
                     sD[1][q] = dyr[js];
-                    if (FAM == LABFM_ABF_PAPER && dxr[js] == 0.0 && dyr[js] == 0.0) bad = true;
+                    if (FAM != LABFM_ABF_HERMITE && dxr[js] == 0.0 && dyr[js] == 0.0) bad = true;
                 }
             }
             if (__any(bad)) status = LABFM_ST_DEGENERATE;
@@ -443,6 +443,7 @@ void launch_mixed_all(Context* c, const WeightArgs& a, const OpList& ops, const 
 void init_mixed_grids() {
     mixed_grids_all<LABFM_ABF_HERMITE>();
     mixed_grids_all<LABFM_ABF_PAPER>();
+    mixed_grids_all<LABFM_ABF_PAPER_D1>();
 }
 
 // Mixed kernels of the orders in `mask` over given lists, then FP64 kernels on
@@ -459,8 +460,10 @@ labfm_err weights_mixed_lists(Context* c, const WeightArgs& a0, const int32_t* l
         if (a0.ops & (1u << b)) ops.op[ops.nops++] = 1u << b;
     if (a0.abf == LABFM_ABF_HERMITE)
         launch_mixed_all<LABFM_ABF_HERMITE>(c, a0, ops, list, off, cnt, rlist, rcnt, mask, st);
-    else
+    else if (a0.abf == LABFM_ABF_PAPER)
         launch_mixed_all<LABFM_ABF_PAPER>(c, a0, ops, list, off, cnt, rlist, rcnt, mask, st);
+    else
+        launch_mixed_all<LABFM_ABF_PAPER_D1>(c, a0, ops, list, off, cnt, rlist, rcnt, mask, st);
     LABFM_HIP_CHECK(hipGetLastError());
     // FP64 recomputation of the retry list; iters of those nodes are offset by 64
     WeightArgs a = a0;

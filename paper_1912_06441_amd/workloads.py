@@ -8,6 +8,12 @@ lattice of spacing s, every node perturbed by at most eps*s.  Here the
 lattice is cell-centred ((i + 1/2) s) and each coordinate is perturbed by
 U(-eps s, +eps s); nodes are stored in Morton order of their lattice cell
 so that neighbours are close in memory.
+
+The noise level eps/dr quoted with the paper's own experiments maps to a
+per-coordinate half-width of eps/2 (`paper_jitter`): Sec. 4.1 gives the
+separation and fill distances of its eps/dr = 0.5 sets as about 0.29 dr and
+0.86 dr, which per-coordinate U(-0.25 dr, 0.25 dr) reproduces (0.26-0.27 dr,
+0.89-0.92 dr), while U(-0.5 dr, 0.5 dr) does not (0.02-0.05 dr, 1.1 dr).
 """
 import math
 
@@ -76,6 +82,12 @@ def wall_conforming_lattice(n, eps=0.3, seed=0, morton=True):
     return np.ascontiguousarray(x), np.ascontiguousarray(y), s
 
 
+def paper_jitter(eps_over_dr):
+    """Per-coordinate jitter half-width (in units of s) of the paper's noise
+    level eps/dr (see the module docstring)."""
+    return 0.5 * float(eps_over_dr)
+
+
 def unit_domain(periodic=False):
     return {"lo": (0.0, 0.0), "hi": (1.0, 1.0), "periodic": (bool(periodic), bool(periodic))}
 
@@ -125,6 +137,13 @@ def config(name):
         "c5": dict(n_side=1024, eps=0.3, seed=5, k=6, k_boundary=6, R_s=4.0, periodic=True,
                    a=(1.0, 0.5), nu=1e-3, beta=1e-7, dt_s=0.1, nsteps=1000,
                    x0=(0.5, 0.5), width2=0.01),
+        # heat equation u_t = kappa lap u, kappa = 1 (Sec. 5.1): quadratic RBF, ABF family
+        # PAPER_D1 (= 2), h/dr = 2 (R = 4 dr, growth to the critical counts near walls),
+        # eps/dr = 0.5 (paper's measure), dt = 0.05 h^2.  Dirichlet: wall-conforming lattice on
+        # [0,1]^2, u = sin(pi x) on y = 0 and 0 on the other walls, steady state taken at
+        # t* = 8 pi^2 t = 100; periodic: sin(2 pi x) sin(2 pi y) decaying to t* = 1.
+        "heat": dict(abf=2, rbf=2, h_over_dr=2.0, eps_paper=0.5, dt_h2=0.05, tstar_ss=100.0,
+                     tstar_periodic=1.0, seed=7, hH=(0.2, 0.1, 0.05, 0.025, 0.0125)),
     }
     return dict(cfgs[name])
 
@@ -246,3 +265,38 @@ def advected_gaussian(x, y, t, a, nu, x0=(0.5, 0.5), width2=0.01, images=2):
             dy = y - cy - iy
             u += amp * np.exp(-(dx * dx + dy * dy) / s2)
     return u
+
+
+# ---------------------------------------------------------------------------
+# heat equation (Sec. 5.1)
+
+
+def heat_dirichlet_nodes(hH, eps_over_dr=0.5, seed=7):
+    """Wall-conforming lattice with h/H = hH at h/dr = 2 (dr = hH / 2), paper
+    noise level eps/dr.  Returns (x, y, s, wall) with wall a bool mask of the
+    boundary nodes."""
+    n = int(round(2.0 / hH)) + 1
+    x, y, s = wall_conforming_lattice(n, eps=paper_jitter(eps_over_dr), seed=seed)
+    wall = (x == 0.0) | (x == 1.0) | (y == 0.0) | (y == 1.0)
+    return x, y, s, wall
+
+
+def heat_periodic_nodes(hH, eps_over_dr=0.5, seed=3):
+    """Periodic cell-centred lattice with h/H = hH at h/dr = 2."""
+    n = int(round(2.0 / hH))
+    return jittered_lattice(n, eps=paper_jitter(eps_over_dr), seed=seed, periodic=True)
+
+
+def heat_boundary_values(x, y):
+    """Dirichlet data of the steady-state case: sin(pi x) on y = 0, else 0."""
+    return np.where(y == 0.0, np.sin(math.pi * x), 0.0)
+
+
+def heat_steady_state(x, y):
+    """u_ss = sinh(pi (1 - y)) sin(pi x) / sinh(pi) (Sec. 5.1, eq. heatss)."""
+    return np.sinh(math.pi * (1.0 - y)) * np.sin(math.pi * x) / math.sinh(math.pi)
+
+
+def heat_periodic_solution(x, y, t, kappa=1.0):
+    """sin(2 pi x) sin(2 pi y) exp(-8 kappa pi^2 t) on the unit torus (Sec. 5.1)."""
+    return np.sin(2 * math.pi * x) * np.sin(2 * math.pi * y) * math.exp(-8.0 * kappa * math.pi ** 2 * t)

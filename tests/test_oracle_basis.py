@@ -195,3 +195,45 @@ def test_paper_abfs_undefined_at_origin(O):
         O.abfs(4, 0.0, 0.0, family=O.ABF_PAPER, rbf=O.RBF_QUADRATIC)
     W = O.abfs(4, 0.0, 0.0, family=O.ABF_HERMITE)
     assert np.all(np.isfinite(W))
+
+
+@pytest.mark.parametrize("rbf", [2, 3])
+def test_paper_d1_family_is_dw0_times_derivatives_of_r(O, rbf):
+    """PAPER_D1 keeps only the dW0/dr term in every element (the App. A
+    truncation from the first element on): W_m = W0'(|d|) d^(a,b) |d|.
+    Checked symbolically, and against the cone family, whose ABFs are exactly
+    that shape with a constant W0' (eq. conic_abs)."""
+    qq = sp.symbols("qq", positive=True)
+    if rbf == 2:
+        W0q = sp.Rational(3, 16) / sp.pi * (qq - 2) ** 2
+    else:
+        W0q = sp.Rational(78, 28) / sp.pi * (1 - qq / 2) ** 8 * (4 * qq ** 3 + sp.Rational(25, 4) * qq ** 2 + 4 * qq + 1)
+    dW0 = sp.diff(W0q, qq)
+    k = 8
+    idx = O.index_table(k)
+    pts = list(zip(*_pts(4, 9)))
+    for m, (a, b) in enumerate(idx):
+        dr = rs
+        if a:
+            dr = sp.diff(dr, xs, a)
+        if b:
+            dr = sp.diff(dr, ys, b)
+        fn = sp.lambdify((xs, ys), dW0.subs(qq, rs) * dr, "mpmath")
+        for px, py in pts:
+            W = O.abfs(k, px, py, family=O.ABF_PAPER_D1, rbf=rbf)
+            ref = float(fn(px, py))
+            assert W[m] == pytest.approx(ref, rel=1e-11, abs=1e-11 * (1 + abs(ref))), (m, a, b)
+    # cone: W0' = -3/(8 pi) is constant, so PAPER_D1 = PAPER; quadratic: W0'(q) / W0'_cone = 2 - q
+    for px, py in zip(*_pts(6, 10)):
+        q = math.hypot(px, py)
+        cone = O.abfs(k, px, py, family=O.ABF_PAPER, rbf=O.RBF_CONE)
+        np.testing.assert_allclose(O.abfs(k, px, py, family=O.ABF_PAPER_D1, rbf=O.RBF_CONE), cone,
+                                   rtol=1e-13, atol=1e-14)
+        np.testing.assert_allclose(O.abfs(k, px, py, family=O.ABF_PAPER_D1, rbf=O.RBF_QUADRATIC), (2 - q) * cone,
+                                   rtol=1e-12, atol=1e-13)
+    # elements of order 1, and of order >= 4, are the same in both PAPER families
+    for px, py in zip(*_pts(3, 11)):
+        a_ = O.abfs(k, px, py, family=O.ABF_PAPER, rbf=rbf)
+        b_ = O.abfs(k, px, py, family=O.ABF_PAPER_D1, rbf=rbf)
+        keep = [m for m, (a, b) in enumerate(idx) if a + b == 1 or a + b >= 4]
+        np.testing.assert_allclose(b_[keep], a_[keep], rtol=1e-13, atol=1e-14)

@@ -1,4 +1,4 @@
-"""Pins of the oracle's time stepping (classical RK4, Sec. 4.1) against
+"""Pins of the oracle's time stepping (classical RK4, Sec. 5.1) against
 closed-form solutions of the heat and advection-diffusion equations."""
 import math
 
@@ -19,7 +19,7 @@ def _periodic_ops(O, side, k, Rs, eps, seed, ops=None):
 
 
 def test_heat_equation_decay():
-    """Sec. 4.1 heat equation, periodic: u = sin(2 pi x) sin(2 pi y) exp(-8 pi^2 kappa t),
+    """Sec. 5.1 heat equation, periodic: u = sin(2 pi x) sin(2 pi y) exp(-8 pi^2 kappa t),
     kappa = 1, dt = 0.05 h^2 / kappa, eps/dr = 0.5, h/dr = 2; error falls ~ h^k."""
     import oracle as O
 

@@ -350,9 +350,9 @@ def test_status_codes(O):
 
 
 def test_hyperviscosity_targets(O):
-    """Sec. 3.3 targets: -nabla^4 (elements 10, 12, 14) and nabla^6 (21, 23, 25, 27)
+    """Sec. 4.2 targets: -nabla^4 (elements 10, 12, 14) and nabla^6 (21, 23, 25, 27)
     reproduce the operators exactly on polynomials of degree <= k."""
-    lines = golden_lines("hyperviscosity_targets_sec33.txt")
+    lines = golden_lines("hyperviscosity_targets_sec42.txt")
     assert lines[0].split()[1:] == ["10:-1", "12:-2", "14:-1"]
     assert lines[1].split()[1:] == ["21:1", "23:3", "25:3", "27:1"]
     x, y, s, dom, order = _setup(40, 6, 4.0, periodic=True)
