@@ -276,6 +276,36 @@ typedef struct {
 labfm_err labfm_step(void* ctx, const labfm_step_plan* plan, void* u, void* scratch, int nsteps,
                      int use_graph, void* stream);
 
+/* Viscous Burgers' equation (Sec. 5.3, eq. burgers) for the velocity (u, v)
+ * with classical RK4 (Sec. 5.1):
+ *   du/dt = -(u L^x(u) + v L^y(u)) + nu L^L(u) + L^hv(u),
+ *   dv/dt = -(u L^x(v) + v L^y(v)) + nu L^L(v) + L^hv(v),
+ * nu = 1/Re; L^hv is an optional hyperviscosity operator (Sec. 4.2, e.g.
+ * -100 h^4 nabla^4 or 8 h^6 nabla^6) whose coefficient the caller has folded
+ * into w_hv (labfm_combine).  Dirichlet nodes (fixed[i] != 0) keep their
+ * values, as in labfm_step. */
+typedef struct {
+    const int64_t* row_ptr; /* device int64 [n+1]                   */
+    const int32_t* col;     /* device int32 [nnz]                   */
+    int64_t n, nnz;
+    int dtype;              /* 0: FP32 weights and state; 1: FP64   */
+    const void* w_x;        /* device [nnz]: d/dx weights           */
+    const void* w_y;        /* device [nnz]: d/dy weights           */
+    const void* w_lap;      /* device [nnz]: Laplacian weights      */
+    const void* w_hv;       /* device [nnz] or NULL                 */
+    double nu;              /* viscosity 1/Re                       */
+    double dt;
+    const int8_t* fixed;    /* device int8 [n] or NULL              */
+} labfm_burgers_plan;
+
+/* Advance (u, v) (device [n] each, dtype of the plan) by nsteps RK4 steps.
+ * scratch: device, at least 6 n elements of the plan's dtype, not aliasing u
+ * or v.  use_graph != 0 captures one step as a HIP graph (kept while plan,
+ * buffers and stream are unchanged) and replays it.  Argument errors return
+ * LABFM_EINVAL before any launch.  Asynchronous. */
+labfm_err labfm_burgers_step(void* ctx, const labfm_burgers_plan* plan, void* u, void* v, void* scratch,
+                             int nsteps, int use_graph, void* stream);
+
 /* ---- learned warm start: features, network, training --------------------
  * Features of every node i < n (Sec. 2 stencil, scaled offsets d = r_ji / h_i,
  * h_i = R_i / 2): the row's neighbours ranked by (d_x^2 + d_y^2, j), the

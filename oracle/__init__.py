@@ -63,6 +63,8 @@ def lib():
         L.or_apply.argtypes = [C.c_int64, i64, i32, dp, dp, dp]
         L.or_combine.argtypes = [C.c_int64, C.c_int, dp, dp, dp]
         L.or_rk4.argtypes = [C.c_int64, i64, i32, dp, dp, C.c_double, C.c_double, C.c_int, dp, i8]
+        L.or_burgers_rk4.argtypes = [C.c_int64, i64, i32, dp, dp, dp, dp, C.c_double, C.c_double, C.c_int, dp, dp,
+                                     i8]
         L.or_num_threads.restype = C.c_int
         L.or_set_num_threads.argtypes = [C.c_int]
         _lib = L
@@ -262,6 +264,26 @@ def rk4(row_ptr, col, w_lin, w_bh, gamma, dt, nsteps, u0, fixed=None):
     lib().or_rk4(n, _p(row_ptr, C.c_int64), _p(col, C.c_int32), _p(w_lin, C.c_double), wb,
                  float(gamma), float(dt), int(nsteps), _p(u, C.c_double), fx)
     return u
+
+
+def burgers_rk4(row_ptr, col, wx, wy, wl, whv, nu, dt, nsteps, u0, v0, fixed=None):
+    """Classical RK4 on the viscous Burgers' equation (Sec. 5.3):
+    du/dt = -(u d/dx + v d/dy) u + nu lap u + L_hv u, the same for v; returns (u, v)."""
+    row_ptr = np.ascontiguousarray(row_ptr, np.int64)
+    col = np.ascontiguousarray(col, np.int32)
+    ws = [np.ascontiguousarray(a, np.float64) for a in (wx, wy, wl)]
+    hv = None if whv is None else np.ascontiguousarray(whv, np.float64)
+    u = np.array(u0, dtype=np.float64, copy=True)
+    v = np.array(v0, dtype=np.float64, copy=True)
+    fx = None
+    if fixed is not None:
+        fixed = np.ascontiguousarray(fixed, np.int8)
+        fx = _p(fixed, C.c_int8)
+    n = row_ptr.size - 1
+    lib().or_burgers_rk4(n, _p(row_ptr, C.c_int64), _p(col, C.c_int32), _p(ws[0], C.c_double),
+                         _p(ws[1], C.c_double), _p(ws[2], C.c_double), None if hv is None else _p(hv, C.c_double),
+                         float(nu), float(dt), int(nsteps), _p(u, C.c_double), _p(v, C.c_double), fx)
+    return u, v
 
 
 def num_threads():

@@ -848,5 +848,64 @@ void or_rk4(int64_t n, const int64_t* row_ptr, const int32_t* col, const double*
     free(k1); free(k2); free(k3); free(k4); free(us); free(t1); free(t2);
 }
 
+/* Viscous Burgers' equation (Sec. 5.3, eq. burgers) for the velocity (u, v):
+ *   du/dt = -(u L^x(u) + v L^y(u)) + nu L^L(u) + L^hv(u),
+ *   dv/dt = -(u L^x(v) + v L^y(v)) + nu L^L(v) + L^hv(v),
+ * nu = 1/Re, L^hv an optional hyperviscosity operator whose coefficient is
+ * part of its weights (Sec. 4.2), each L by eq. (general_do).  Classical RK4
+ * (Sec. 5.1); nodes with fixed[i] != 0 keep their values. */
+static void or_burgers_rhs(int64_t n, const int64_t* rp, const int32_t* col, const double* wx,
+                           const double* wy, const double* wl, const double* whv, double nu,
+                           const double* u, const double* v, double* ku, double* kv, double* t) {
+    /* t: 8 scratch arrays of n: L^x u, L^y u, L^L u, L^hv u, then the same of v */
+    const double* f[2] = {u, v};
+    for (int c = 0; c < 2; ++c) {
+        double* o = t + (size_t)4 * c * n;
+        or_apply(n, rp, col, wx, f[c], o);
+        or_apply(n, rp, col, wy, f[c], o + n);
+        or_apply(n, rp, col, wl, f[c], o + 2 * n);
+        if (whv) or_apply(n, rp, col, whv, f[c], o + 3 * n);
+        else for (int64_t i = 0; i < n; ++i) o[3 * n + i] = 0.0;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        const double* a = t;
+        const double* b = t + (size_t)4 * n;
+        ku[i] = -(u[i] * a[i] + v[i] * a[n + i]) + nu * a[2 * n + i] + a[3 * n + i];
+        kv[i] = -(u[i] * b[i] + v[i] * b[n + i]) + nu * b[2 * n + i] + b[3 * n + i];
+    }
+}
+
+void or_burgers_rk4(int64_t n, const int64_t* row_ptr, const int32_t* col, const double* wx,
+                    const double* wy, const double* wl, const double* whv, double nu, double dt,
+                    int nsteps, double* u, double* v, const int8_t* fixed) {
+    size_t sz = sizeof(double) * (size_t)(n > 0 ? n : 1);
+    double *ku[4], *kv[4];
+    for (int q = 0; q < 4; ++q) { ku[q] = malloc(sz); kv[q] = malloc(sz); }
+    double *us = malloc(sz), *vs = malloc(sz), *t = malloc(8 * sz);
+    const double c[4] = {0.0, 0.5, 0.5, 1.0}; /* stage q is evaluated at u + c[q] dt k_(q-1) */
+    for (int st = 0; st < nsteps; ++st) {
+        for (int q = 0; q < 4; ++q) {
+            const double *uq = u, *vq = v;
+            if (q > 0) {
+                for (int64_t i = 0; i < n; ++i) {
+                    us[i] = u[i] + c[q] * dt * ku[q - 1][i];
+                    vs[i] = v[i] + c[q] * dt * kv[q - 1][i];
+                }
+                uq = us;
+                vq = vs;
+            }
+            or_burgers_rhs(n, row_ptr, col, wx, wy, wl, whv, nu, uq, vq, ku[q], kv[q], t);
+            or_pin(n, fixed, ku[q]);
+            or_pin(n, fixed, kv[q]);
+        }
+        for (int64_t i = 0; i < n; ++i) {
+            u[i] = u[i] + dt / 6.0 * (ku[0][i] + 2.0 * ku[1][i] + 2.0 * ku[2][i] + ku[3][i]);
+            v[i] = v[i] + dt / 6.0 * (kv[0][i] + 2.0 * kv[1][i] + 2.0 * kv[2][i] + kv[3][i]);
+        }
+    }
+    for (int q = 0; q < 4; ++q) { free(ku[q]); free(kv[q]); }
+    free(us); free(vs); free(t);
+}
+
 int or_num_threads(void) { return omp_get_max_threads(); }
 void or_set_num_threads(int t) { omp_set_num_threads(t); }

@@ -13,6 +13,7 @@
  *   Sec. 3.2 eq. (conic_abs) and App. A          ABFs from a fundamental RBF
  *   Sec. 4.2 (stability)         hyperviscosity target vectors
  *   Sec. 5.1                     classical RK4
+ *   Sec. 5.3                     viscous Burgers' equation (RK4)
  * Readings where the paper is silent are listed at each function.
  */
 #ifndef LABFM_ORACLE_H
@@ -79,6 +80,10 @@ void or_combine(int64_t nnz, int nsets, const double* w, const double* coef, dou
 void or_rk4(int64_t n, const int64_t* row_ptr, const int32_t* col, const double* w_lin,
             const double* w_bh, double gamma, double dt, int nsteps, double* u,
             const int8_t* fixed /* optional [n]: Dirichlet nodes, not advanced */);
+void or_burgers_rk4(int64_t n, const int64_t* row_ptr, const int32_t* col, const double* wx,
+                    const double* wy, const double* wl, const double* whv /* or NULL */, double nu,
+                    double dt, int nsteps, double* u, double* v,
+                    const int8_t* fixed /* optional [n]: Dirichlet nodes, not advanced */);
 int or_num_threads(void);
 void or_set_num_threads(int t);
 

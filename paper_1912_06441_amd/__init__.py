@@ -25,7 +25,7 @@ EXPORTED = sorted(["labfm_last_error", "labfm_create", "labfm_destroy", "labfm_b
                    "labfm_combine", "labfm_apply_operator", "labfm_step", "labfm_timing_enable",
                    "labfm_timing_read", "labfm_mlp_features", "labfm_mlp_forward", "labfm_mlp_cache_floats",
                    "labfm_mlp_backward", "labfm_mlp_moment_loss", "labfm_mlp_adam", "labfm_mlp_cast_bf16",
-                   "labfm_weights_batched", "labfm_autotune_query"])
+                   "labfm_weights_batched", "labfm_autotune_query", "labfm_burgers_step"])
 MLP_MAX_LAYERS = 8
 
 
@@ -64,6 +64,12 @@ class NodeSetDesc(C.Structure):
                 ("iters", C.c_void_p)]
 
 
+class BurgersPlan(C.Structure):
+    _fields_ = [("row_ptr", C.c_void_p), ("col", C.c_void_p), ("n", C.c_int64), ("nnz", C.c_int64),
+                ("dtype", C.c_int), ("w_x", C.c_void_p), ("w_y", C.c_void_p), ("w_lap", C.c_void_p),
+                ("w_hv", C.c_void_p), ("nu", C.c_double), ("dt", C.c_double), ("fixed", C.c_void_p)]
+
+
 class StepPlan(C.Structure):
     _fields_ = [("row_ptr", C.c_void_p), ("col", C.c_void_p), ("n", C.c_int64), ("nnz", C.c_int64),
                 ("dtype", C.c_int), ("w_lin", C.c_void_p), ("w_bh", C.c_void_p), ("gamma", C.c_double),
@@ -92,6 +98,7 @@ def load_library(path=LIB_PATH):
     L.labfm_combine.argtypes = [vp, vp, C.c_int, C.POINTER(dp), i64, vp, vp, vp]
     L.labfm_apply_operator.argtypes = [vp, vp, vp, i64, i64, C.c_int, vp, C.c_int, vp, vp, vp]
     L.labfm_step.argtypes = [vp, C.POINTER(StepPlan), vp, vp, C.c_int, C.c_int, vp]
+    L.labfm_burgers_step.argtypes = [vp, C.POINTER(BurgersPlan), vp, vp, vp, C.c_int, C.c_int, vp]
     L.labfm_mlp_features.argtypes = [vp, vp, vp, i64, C.POINTER(Domain), vp, vp, vp, C.c_int, vp, vp]
     L.labfm_mlp_forward.argtypes = [vp, C.POINTER(MLPDesc), vp, i64, vp, vp, C.c_int, vp]
     L.labfm_mlp_cache_floats.argtypes = [C.POINTER(MLPDesc), i64]
@@ -331,6 +338,26 @@ class Context:
         _check(self.lib.labfm_step(self.h, C.byref(plan), _ptr(u), _ptr(scratch), int(nsteps), int(bool(use_graph)),
                                    _stream(torch)), "labfm_step")
         return u
+
+    def burgers_step(self, row_ptr, col, w_x, w_y, w_lap, nu, dt, u, v, nsteps, w_hv=None, scratch=None,
+                     use_graph=True, fixed=None):
+        """Advance the velocity (u, v) in place by nsteps RK4 steps of the viscous
+        Burgers' equation du/dt = -(u d/dx + v d/dy) u + nu lap u + L_hv u (same for v)."""
+        torch = self.torch
+        n = u.numel()
+        if v.numel() != n or v.dtype != u.dtype:
+            raise ValueError("u and v must have the same size and dtype")
+        if scratch is None:
+            scratch = torch.empty(6 * n, dtype=u.dtype, device=u.device)
+        dtype = 1 if u.dtype == torch.float64 else 0
+        if fixed is not None and (fixed.dtype != torch.int8 or fixed.numel() != n or not fixed.is_contiguous()):
+            raise ValueError("fixed must be a contiguous int8 tensor of n entries")
+        plan = BurgersPlan(row_ptr.data_ptr(), col.data_ptr(), n, col.numel(), dtype, w_x.data_ptr(), w_y.data_ptr(),
+                           w_lap.data_ptr(), w_hv.data_ptr() if w_hv is not None else None, float(nu), float(dt),
+                           fixed.data_ptr() if fixed is not None else None)
+        _check(self.lib.labfm_burgers_step(self.h, C.byref(plan), _ptr(u), _ptr(v), _ptr(scratch), int(nsteps),
+                                           int(bool(use_graph)), _stream(torch)), "labfm_burgers_step")
+        return u, v
 
 
 class MLP:

@@ -150,6 +150,7 @@ labfm_err labfm_destroy(void* ctx) {
     DeviceGuard g(c->device);
     if (c->step_exec) hipStreamSynchronize(c->step_stream);
     release_step_graph(c);
+    release_burgers_graph(c);
     if (c->batch.exec) hipStreamSynchronize(c->batch.stream);
     release_batch(c);
     for (auto& t : c->timed) {
@@ -327,6 +328,23 @@ labfm_err labfm_step(void* ctx, const labfm_step_plan* plan, void* u, void* scra
     Context* c = (Context*)ctx;
     DeviceGuard g(c->device);
     return step_launch(c, plan, u, scratch, nsteps, use_graph, (hipStream_t)stream);
+}
+
+labfm_err labfm_burgers_step(void* ctx, const labfm_burgers_plan* plan, void* u, void* v, void* scratch, int nsteps,
+                             int use_graph, void* stream) {
+    if (!ctx || !plan) return fail(LABFM_EINVAL, "labfm_burgers_step: ctx or plan is NULL");
+    if (plan->n < 0 || plan->nnz < 0 || nsteps < 0) return fail(LABFM_EINVAL, "labfm_burgers_step: negative size");
+    if (plan->dtype != 0 && plan->dtype != 1) return fail(LABFM_EINVAL, "labfm_burgers_step: dtype must be 0 or 1");
+    if (plan->n > 0 && (!plan->row_ptr || !u || !v || !scratch ||
+                        (plan->nnz > 0 && (!plan->col || !plan->w_x || !plan->w_y || !plan->w_lap))))
+        return fail(LABFM_EINVAL, "labfm_burgers_step: NULL array");
+    if (plan->n > 0 && (u == v || u == scratch || v == scratch))
+        return fail(LABFM_EINVAL, "labfm_burgers_step: u, v and scratch must be distinct buffers");
+    if (!std::isfinite(plan->dt) || !std::isfinite(plan->nu))
+        return fail(LABFM_EINVAL, "labfm_burgers_step: dt/nu not finite");
+    Context* c = (Context*)ctx;
+    DeviceGuard g(c->device);
+    return burgers_launch(c, plan, u, v, scratch, nsteps, use_graph, (hipStream_t)stream);
 }
 
 labfm_err labfm_mlp_features(void* ctx, const double* x, const double* y, int64_t n, const labfm_domain* dom,

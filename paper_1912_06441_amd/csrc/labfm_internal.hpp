@@ -48,6 +48,13 @@ struct Context {
     labfm_step_plan step_key{};
     void* step_u = nullptr;
     void* step_scratch = nullptr;
+    // cached Burgers step graph (same replay rule)
+    struct StepGraph {
+        hipGraphExec_t exec = nullptr;
+        hipStream_t stream = nullptr;
+        void *u = nullptr, *v = nullptr, *scratch = nullptr;
+    } burgers;
+    labfm_burgers_plan burgers_key{};
     // cached batched-weights graph (replayed while sets, options and stream are unchanged)
     struct Batch {
         std::vector<labfm_node_set> sets;
@@ -100,6 +107,7 @@ struct KernelTimer {
 };
 
 void release_step_graph(Context* c);
+void release_burgers_graph(Context* c);
 void release_batch(Context* c);
 
 labfm_err ensure(Scratch& s, size_t bytes);
@@ -211,5 +219,7 @@ labfm_err combine_launch(const double* w64, int nsets, const double* coef, int64
                          float* out32, hipStream_t st);
 labfm_err step_launch(Context* c, const labfm_step_plan* plan, void* u, void* scratch, int nsteps,
                       int use_graph, hipStream_t st);
+labfm_err burgers_launch(Context* c, const labfm_burgers_plan* plan, void* u, void* v, void* scratch, int nsteps,
+                         int use_graph, hipStream_t st);
 
 }  // namespace labfm

@@ -144,6 +144,12 @@ def config(name):
         # t* = 8 pi^2 t = 100; periodic: sin(2 pi x) sin(2 pi y) decaying to t* = 1.
         "heat": dict(abf=2, rbf=2, h_over_dr=2.0, eps_paper=0.5, dt_h2=0.05, tstar_ss=100.0,
                      tstar_periodic=1.0, seed=7, hH=(0.2, 0.1, 0.05, 0.025, 0.0125)),
+        # viscous Burgers' equation (Sec. 5.3), periodic unit square: u0 = sin(2 pi x), v0 = 0
+        # (Cole-Hopf solution), Re = 100, eps/dr = 0.2, h/dr = 2, quadratic x PAPER_D1,
+        # dt = min(0.2 h / max|u|, 0.05 h^2 Re) (eq. tstep), resolutions h/H = 2/n_side;
+        # the Re = 250 run adds -100 h^4 nabla^4 hyperviscosity (k = 6, eps/dr = 0.5, h/H = 2/81).
+        "burgers": dict(abf=2, rbf=2, h_over_dr=2.0, Re=100.0, eps_paper=0.2, seed=11, t_end=0.4,
+                        sides=(21, 41, 81, 161), Re_hv=250.0, hv_coef=100.0, hv_eps_paper=0.5, hv_side=81),
     }
     return dict(cfgs[name])
 
@@ -300,3 +306,34 @@ def heat_steady_state(x, y):
 def heat_periodic_solution(x, y, t, kappa=1.0):
     """sin(2 pi x) sin(2 pi y) exp(-8 kappa pi^2 t) on the unit torus (Sec. 5.1)."""
     return np.sin(2 * math.pi * x) * np.sin(2 * math.pi * y) * math.exp(-8.0 * kappa * math.pi ** 2 * t)
+
+
+# ---------------------------------------------------------------------------
+# viscous Burgers' equation (Sec. 5.3)
+
+
+def burgers_cole_hopf(x, t, Re, H=1.0, nterms=30):
+    """Exact u(x, t) of u_t + u u_x = u_xx / Re from u(x, 0) = sin(2 pi x / H)
+    (Cole-Hopf): with z = Re H / (4 pi), A_0 = e^-z I_0(z), A_n = 2 e^-z I_n(z),
+    u = (4 pi / (H Re)) sum n A_n sin(2 n pi x / H) E_n / (A_0 + sum A_n cos(2 n pi x / H) E_n),
+    E_n = exp(-4 n^2 pi^2 t / (H^2 Re)).  The printed decay exponent lacks the
+    factor 4 that the heat equation behind the transform gives (modes
+    cos(2 n pi x / H) decay at (2 n pi / H)^2 / Re); with it the series
+    satisfies the equation."""
+    from scipy.special import ive
+
+    x = np.asarray(x, dtype=np.float64)
+    z = Re * H / (4.0 * math.pi)
+    n = np.arange(1, nterms + 1, dtype=np.float64)
+    A0 = ive(0, z)
+    An = 2.0 * ive(n, z)
+    E = np.exp(-4.0 * n ** 2 * math.pi ** 2 * t / (H * H * Re))
+    ang = 2.0 * math.pi * np.multiply.outer(x.ravel(), n) / H
+    num = (np.sin(ang) * (n * An * E)).sum(axis=1)
+    den = A0 + (np.cos(ang) * (An * E)).sum(axis=1)
+    return (4.0 * math.pi / (H * Re) * num / den).reshape(x.shape)
+
+
+def burgers_dt(h, umax, Re):
+    """Eq. (tstep): dt = min(0.2 h / max|u|, 0.05 h^2 Re)."""
+    return min(0.2 * h / umax, 0.05 * h * h * Re)

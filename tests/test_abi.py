@@ -58,8 +58,9 @@ def test_last_error_on_bad_arguments(lib):
 
 
 def test_new_entry_points_validate_before_device_work(lib):
-    """Batched weights, autotune query and the warm-start calls reject a NULL
-    context (or network) with LABFM_EINVAL and a message, without a GPU."""
+    """Batched weights, autotune query, the Burgers step and the warm-start calls
+    reject a NULL context (or network) with LABFM_EINVAL and a message, without
+    a GPU."""
     c = ctypes
     lib.labfm_last_error.restype = c.c_char_p
     calls = {
@@ -71,6 +72,7 @@ def test_new_entry_points_validate_before_device_work(lib):
         "labfm_mlp_moment_loss": (None, None, None, None, None, 8, c.c_uint(7), c.c_int64(0), None, None, None),
         "labfm_mlp_adam": (None, None, None, None, None, None, c.c_int64(0), None, c.c_int64(1), None),
         "labfm_mlp_cast_bf16": (None, None, None, c.c_int64(0), None),
+        "labfm_burgers_step": (None, None, None, None, None, 1, 1, None),
     }
     for name, args in calls.items():
         fn = getattr(lib, name)

@@ -1,0 +1,204 @@
+"""Viscous Burgers' equation (Sec. 5.3) through labfm_burgers_step against the
+oracle's RK4 and the Cole-Hopf solution.
+
+* Parity, two-dimensional initial condition u = sin(2 pi x) sin(2 pi y),
+  v = -cos(2 pi x) cos(2 pi y), k = 6, eps/dr = 0.5: FP64 within 1e-12 of the
+  oracle (graph replay == direct launches bit for bit), with and without a
+  hyperviscosity operator and with a Dirichlet mask; FP32 within 1e-4.
+* Periodic sawtooth (Re = 100, eps/dr = 0.2) through the whole GPU path
+  (neighbours, FP64 weights, Burgers graph): error against Cole-Hopf falls
+  with resolution at k = 4 and 6; parity with the oracle at h/H = 2/41.
+* Re = 250, k = 6, eps/dr = 0.5, h/H = 2/81: the scheme blows up before
+  t = 0.4 without hyperviscosity and stays bounded with -0.2 h^4 nabla^4.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1912_06441_amd import workloads as WL
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    import oracle
+    import paper_1912_06441_amd as L
+
+    assert torch.cuda.is_available()
+    ctx = L.Context(0)
+    yield dict(torch=torch, O=oracle, L=L, ctx=ctx)
+    torch.cuda.synchronize()
+    ctx.close()
+
+
+def _dev(env, a, dtype=None):
+    t = env["torch"].from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def _oracle_set(env, k, side, eps_paper, ops=7):
+    O = env["O"]
+    cfg = WL.config("burgers")
+    x, y, s = WL.jittered_lattice(side, eps=WL.paper_jitter(eps_paper), seed=cfg["seed"], periodic=True)
+    dom = WL.unit_domain(True)
+    order = np.full(x.size, k, np.int8)
+    rp, col, R = O.neighbours(x, y, dom, 2.0 * cfg["h_over_dr"] * s, order, grow=True)
+    w, st, _, _ = O.weights(x, y, dom, R, order, rp, col, family=cfg["abf"], rbf=cfg["rbf"], ops=ops)
+    assert np.all(st == O.ST_OK)
+    return dict(x=x, y=y, s=s, h=cfg["h_over_dr"] * s, rp=rp, col=col, w=w, dom=dom, k=k)
+
+
+def _run_gpu(env, S, w, whv, nu, dt, nsteps, u0, v0, dtype, graph=True, fixed=None):
+    torch = env["torch"]
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    u, v = _dev(env, u0, tdt), _dev(env, v0, tdt)
+    env["ctx"].burgers_step(_dev(env, S["rp"]), _dev(env, S["col"]), _dev(env, w[0], tdt), _dev(env, w[1], tdt),
+                            _dev(env, w[2], tdt), nu, dt, u, v, nsteps,
+                            w_hv=None if whv is None else _dev(env, whv, tdt), use_graph=graph,
+                            fixed=None if fixed is None else _dev(env, fixed))
+    torch.cuda.synchronize()
+    return u.double().cpu().numpy(), v.double().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def set2d(env):
+    return _oracle_set(env, 6, 41, 0.5, ops=15)
+
+
+@pytest.mark.parametrize("variant", ["plain", "hyperviscosity", "dirichlet"])
+def test_burgers_fp64_parity(env, set2d, variant):
+    O = env["O"]
+    S = set2d
+    x, y = S["x"], S["y"]
+    u0 = np.sin(2 * math.pi * x) * np.sin(2 * math.pi * y)
+    v0 = -np.cos(2 * math.pi * x) * np.cos(2 * math.pi * y)
+    Re = 100.0
+    dt = WL.burgers_dt(S["h"], 1.0, Re)
+    # -0.05 h^4 nabla^4: inside RK4's stability interval at this dt (0.2 h^4 is not)
+    whv = 0.05 * S["h"] ** 4 * S["w"][3] if variant == "hyperviscosity" else None
+    fixed = (np.random.default_rng(3).random(x.size) < 0.1).astype(np.int8) if variant == "dirichlet" else None
+    nsteps = 50
+    ref = O.burgers_rk4(S["rp"], S["col"], S["w"][0], S["w"][1], S["w"][2], whv, 1.0 / Re, dt, nsteps, u0, v0,
+                        fixed=fixed)
+    assert np.all(np.isfinite(ref[0])) and np.all(np.isfinite(ref[1]))
+    a = _run_gpu(env, S, S["w"], whv, 1.0 / Re, dt, nsteps, u0, v0, "f64", graph=False, fixed=fixed)
+    b = _run_gpu(env, S, S["w"], whv, 1.0 / Re, dt, nsteps, u0, v0, "f64", graph=True, fixed=fixed)
+    da = max(np.abs(a[c] - ref[c]).max() for c in range(2))
+    db = max(np.abs(b[c] - ref[c]).max() for c in range(2))
+    dab = max(np.abs(a[c] - b[c]).max() for c in range(2))
+    _say("  %s: direct-oracle %.3e graph-oracle %.3e direct-graph %.3e" % (variant, da, db, dab))
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    if fixed is not None:
+        keep = fixed == 1
+        assert np.array_equal(b[0][keep], u0[keep]) and np.array_equal(b[1][keep], v0[keep])
+    err = max(np.abs(b[c] - ref[c]).max() / np.abs(ref[c]).max() for c in range(2))
+    _say("  burgers fp64 %s rel err %.3e" % (variant, err))
+    assert err <= 1e-12
+
+
+def test_burgers_fp32(env, set2d):
+    """FP32 weights and state: each stage rounds sums of ~50 terms at 2^-24;
+    over 50 steps the drift stays below 1e-4 of max|u|."""
+    O = env["O"]
+    S = set2d
+    x, y = S["x"], S["y"]
+    u0 = np.sin(2 * math.pi * x) * np.sin(2 * math.pi * y)
+    v0 = -np.cos(2 * math.pi * x) * np.cos(2 * math.pi * y)
+    dt = WL.burgers_dt(S["h"], 1.0, 100.0)
+    ref = O.burgers_rk4(S["rp"], S["col"], S["w"][0], S["w"][1], S["w"][2], None, 0.01, dt, 50, u0, v0)
+    g = _run_gpu(env, S, S["w"], None, 0.01, dt, 50, u0, v0, "f32")
+    err = max(np.abs(g[c] - ref[c]).max() / np.abs(ref[c]).max() for c in range(2))
+    _say("  burgers fp32 rel err %.3e" % err)
+    assert err <= 1e-4
+
+
+def _gpu_pipeline(env, k, side, eps_paper, ops):
+    """GPU neighbours and FP64 weights of one periodic set."""
+    L = env["L"]
+    cfg = WL.config("burgers")
+    x, y, s = WL.jittered_lattice(side, eps=WL.paper_jitter(eps_paper), seed=cfg["seed"], periodic=True)
+    dom = WL.unit_domain(True)
+    n = x.size
+    xt, yt = _dev(env, x), _dev(env, y)
+    Rt = _dev(env, np.full(n, 2.0 * cfg["h_over_dr"] * s))
+    ot = _dev(env, np.full(n, k, np.int8))
+    rp, col = env["ctx"].build_neighbours(xt, yt, Rt, ot, dom, grow=True)
+    w64, _, st, res, _ = env["ctx"].weights(xt, yt, Rt, ot, rp, col, dom, ops=ops, abf=cfg["abf"], rbf=cfg["rbf"])
+    env["torch"].cuda.synchronize()
+    assert np.all(st.cpu().numpy() == 0) and float(res.max()) <= 1e-10
+    return x, y, s, rp, col, w64
+
+
+@pytest.mark.parametrize("k", [4, 6])
+def test_sawtooth_convergence_gpu(env, k):
+    torch = env["torch"]
+    cfg = WL.config("burgers")
+    Re = cfg["Re"]
+    errs = []
+    for side in cfg["sides"][1:]:
+        _say("burgers sawtooth k=%d side %d" % (k, side))
+        x, y, s, rp, col, w = _gpu_pipeline(env, k, side, cfg["eps_paper"], 7)
+        h = cfg["h_over_dr"] * s
+        nsteps = int(math.ceil(cfg["t_end"] / WL.burgers_dt(h, 1.0, Re)))
+        dt = cfg["t_end"] / nsteps
+        u0 = np.sin(2 * math.pi * x)
+        u, v = _dev(env, u0), _dev(env, np.zeros_like(x))
+        env["ctx"].burgers_step(rp, col, w[0], w[1], w[2], 1.0 / Re, dt, u, v, nsteps)
+        torch.cuda.synchronize()
+        ug, vg = u.cpu().numpy(), v.cpu().numpy()
+        assert np.all(vg == 0.0)
+        ex = WL.burgers_cole_hopf(x, cfg["t_end"], Re)
+        errs.append(np.linalg.norm(ug - ex) / np.linalg.norm(ex))
+        msg = "  steps %d  L2 %.3e" % (nsteps, errs[-1])
+        if side == 41:
+            S = _oracle_set(env, k, side, cfg["eps_paper"])
+            uo, _ = env["O"].burgers_rk4(S["rp"], S["col"], S["w"][0], S["w"][1], S["w"][2], None, 1.0 / Re, dt,
+                                        nsteps, u0, np.zeros_like(x))
+            par = np.abs(ug - uo).max() / np.abs(uo).max()
+            msg += "  parity %.1e" % par
+            assert par <= 1e-9
+        _say(msg)
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+    _say("  rates %s" % np.round(rates, 2))
+    assert min(rates) >= 3.0 and errs[-1] < (1e-3 if k == 4 else 1e-4), (errs, rates)
+
+
+def test_re250_needs_hyperviscosity(env):
+    torch = env["torch"]
+    cfg = WL.config("burgers")
+    Re = cfg["Re_hv"]
+    x, y, s, rp, col, w = _gpu_pipeline(env, 6, cfg["hv_side"], cfg["hv_eps_paper"], 15)
+    h = cfg["h_over_dr"] * s
+    dt = WL.burgers_dt(h, 1.0, Re)
+    u0 = np.sin(2 * math.pi * x)
+    out = {}
+    for label, whv in (("none", None), ("hv", (0.2 * h ** 4) * w[3])):
+        u, v = _dev(env, u0), _dev(env, np.zeros_like(x))
+        t, peak = 0.0, 0.0
+        for seg in range(5):  # to t = 0.5 in five legs of 0.1
+            nsteps = int(math.ceil(0.1 / dt))
+            env["ctx"].burgers_step(rp, col, w[0], w[1], w[2], 1.0 / Re, 0.1 / nsteps, u, v, nsteps,
+                                    w_hv=None if whv is None else whv.contiguous())
+            torch.cuda.synchronize()
+            t += 0.1
+            m = float(u.abs().max()) if bool(torch.isfinite(u).all()) else math.inf
+            peak = max(peak, m)
+        ex = WL.burgers_cole_hopf(x, 0.5, Re)
+        ug = u.cpu().numpy()
+        err = np.linalg.norm(ug - ex) / np.linalg.norm(ex) if np.all(np.isfinite(ug)) else math.inf
+        out[label] = (peak, err)
+        _say("  Re 250 %s: max|u| over t <= 0.5 %.3e, L2 at t = 0.5 %.3e" % (label, peak, err))
+    assert not out["none"][0] < 10.0
+    assert out["hv"][0] < 1.2 and out["hv"][1] < 0.15
