@@ -89,6 +89,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-rk4", action="store_true")
     ap.add_argument("--rk4-steps", type=int, default=200)
+    ap.add_argument("--no-burgers", action="store_true", help="skip the Burgers step measurement")
+    ap.add_argument("--burgers-steps", type=int, default=200)
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-set batched weights measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device to device 4 times (counter calibration) and exit")
@@ -218,6 +220,8 @@ def main():
 
     if not args.no_rk4:
         rec["rk4_c5"] = run_rk4(ctx, torch, np, L, WL, args.rk4_steps)
+    if not args.no_burgers:
+        rec["burgers_1024"] = run_burgers(ctx, torch, np, L, WL, args.burgers_steps)
     if not args.no_batch:
         rec["batch_c3"] = run_batch(ctx, torch, np, L, WL, reps=3)
     rec["mlp_bf16"] = run_mlp(ctx, torch, L, WL)
@@ -305,6 +309,46 @@ def run_rk4(ctx, torch, np, L, WL, nsteps):
             "operator_apps_nodes_per_s": 12 * n / (ms_step / 1e3),
             "GB_per_s": bytes_step / (ms_step / 1e3) / 1e9, "hbm_frac": bytes_step / (ms_step / 1e3) / PEAK_HBM,
             "weights_all_ok": bool((st == 0).all().item()), "u_max": float(u.abs().max().item())}
+
+
+def run_burgers(ctx, torch, np, L, WL, nsteps):
+    """Viscous Burgers' equation (FP32, Re = 100) on the 1024x1024 periodic
+    order-6 node set: ms per RK4 step of the one-pass two-field stage kernel."""
+    dev = torch.device("cuda:0")
+    cfg = WL.config("c5")
+    nd = WL.make_nodes(cfg)
+    n = nd["x"].size
+    x = torch.from_numpy(nd["x"]).to(dev)
+    y = torch.from_numpy(nd["y"]).to(dev)
+    R = torch.from_numpy(nd["R"]).to(dev)
+    order = torch.from_numpy(nd["order"]).to(dev)
+    rp, col = ctx.build_neighbours(x, y, R, order, nd["domain"])
+    w64, _, st, _, _ = ctx.weights(x, y, R, order, rp, col, nd["domain"], ops=L.OP_DX | L.OP_DY | L.OP_LAP)
+    w = w64.to(torch.float32)
+    h = 0.5 * cfg["R_s"] * nd["s"]
+    Re = 100.0
+    dt = WL.burgers_dt(h, 1.0, Re)
+    xs, ys = nd["x"], nd["y"]
+    u = torch.from_numpy(np.sin(2 * np.pi * xs) * np.sin(2 * np.pi * ys)).to(dev).to(torch.float32)
+    v = torch.from_numpy(-np.cos(2 * np.pi * xs) * np.cos(2 * np.pi * ys)).to(dev).to(torch.float32)
+    scratch = torch.empty(6 * n, dtype=torch.float32, device=dev)
+    ctx.burgers_step(rp, col, w[0], w[1], w[2], 1.0 / Re, dt, u, v, 5, scratch=scratch)  # warm-up + capture
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    ctx.burgers_step(rp, col, w[0], w[1], w[2], 1.0 / Re, dt, u, v, nsteps, scratch=scratch)
+    torch.cuda.synchronize()
+    ctx.timing(False)
+    kg = ctx.timing_read("burgers")
+    ctx.timing_read(None)
+    nnz = col.numel()
+    ms_step = kg[1] / nsteps
+    # per step: 4 stages x (col + 3 FP32 weight streams per entry) + per node the row bounds
+    # (8 B per stage) and the stage states of both fields (24 + 40 + 40 + 32 B over the stages)
+    bytes_step = 4 * nnz * (4 + 3 * 4) + n * (4 * 8 + 136)
+    return {"nodes": n, "nnz": nnz, "steps": nsteps, "Re": Re, "dt": dt, "ms_per_rk4_step": ms_step,
+            "GB_per_s": bytes_step / (ms_step / 1e3) / 1e9, "hbm_frac": bytes_step / (ms_step / 1e3) / PEAK_HBM,
+            "bytes_per_step": bytes_step, "weights_all_ok": bool((st == 0).all().item()),
+            "finite": bool(torch.isfinite(u).all().item() and torch.isfinite(v).all().item())}
 
 
 def run_mlp(ctx, torch, L, WL, B=1 << 20, reps=5):

@@ -7,7 +7,8 @@
  *   2. per-node weights (Sec. 3.1: M_i = sum_j X_ji (x) W_ji, M_i Psi^d = C^d,
  *      w^d_ji = W_ji . Psi^d),
  *   3. operator application (Sec. 2 eq. general_do: L^d_i(u) = sum_j (u_j - u_i) w^d_ji),
- *   4. explicit RK4 time stepping with those operators (Sec. 5.1).
+ *   4. explicit RK4 time stepping with those operators (Sec. 5.1), and the
+ *      viscous Burgers' equation on a velocity field (Sec. 5.3).
  *
  * Conventions shared by every entry point:
  *   - Pointers named as device pointers must point to memory on the
@@ -354,7 +355,8 @@ labfm_err labfm_mlp_cast_bf16(void* ctx, const float* src, void* dst, int64_t co
  * contains `filter` (NULL: all), returns their count and summed duration in
  * milliseconds, and forgets them.  Kernel names: neigh_count, neigh_fill,
  * weights64_k1..k8, weights32_k1..k8, apply_f32, apply_f64, step_graph,
- * step_direct, mlp_features, mlp_forward, mlp_backward, mlp_loss, mlp_adam,
+ * step_direct, burgers_graph, burgers_direct, mlp_features, mlp_forward,
+ * mlp_backward, mlp_loss, mlp_adam,
  * weights_batch_graph. */
 labfm_err labfm_timing_enable(void* ctx, int enable);
 labfm_err labfm_timing_read(void* ctx, const char* filter, int64_t* launches, double* total_ms);
