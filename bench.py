@@ -324,7 +324,7 @@ def run_burgers(ctx, torch, np, L, WL, nsteps):
     order = torch.from_numpy(nd["order"]).to(dev)
     rp, col = ctx.build_neighbours(x, y, R, order, nd["domain"])
     w64, _, st, _, _ = ctx.weights(x, y, R, order, rp, col, nd["domain"], ops=L.OP_DX | L.OP_DY | L.OP_LAP)
-    w = w64.to(torch.float32)
+    w = [w64[d].to(torch.float32) for d in range(3)]  # one allocation each: 16-byte aligned streams
     h = 0.5 * cfg["R_s"] * nd["s"]
     Re = 100.0
     dt = WL.burgers_dt(h, 1.0, Re)

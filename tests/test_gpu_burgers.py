@@ -108,9 +108,11 @@ def test_burgers_fp64_parity(env, set2d, variant):
     assert err <= 1e-12
 
 
-def test_burgers_fp32(env, set2d):
+@pytest.mark.parametrize("offset", [0, 1])
+def test_burgers_fp32(env, set2d, offset):
     """FP32 weights and state: each stage rounds sums of ~50 terms at 2^-24;
-    over 50 steps the drift stays below 1e-4 of max|u|."""
+    over 50 steps the drift stays below 1e-4 of max|u|; weight streams at
+    offset 0 and at an odd element offset."""
     O = env["O"]
     S = set2d
     x, y = S["x"], S["y"]
@@ -118,9 +120,18 @@ def test_burgers_fp32(env, set2d):
     v0 = -np.cos(2 * math.pi * x) * np.cos(2 * math.pi * y)
     dt = WL.burgers_dt(S["h"], 1.0, 100.0)
     ref = O.burgers_rk4(S["rp"], S["col"], S["w"][0], S["w"][1], S["w"][2], None, 0.01, dt, 50, u0, v0)
-    g = _run_gpu(env, S, S["w"], None, 0.01, dt, 50, u0, v0, "f32")
+    torch = env["torch"]
+    u, v = _dev(env, u0, torch.float32), _dev(env, v0, torch.float32)
+    ws = []
+    for d in range(3):
+        buf = torch.zeros(S["w"][d].size + offset, dtype=torch.float32, device="cuda")
+        buf[offset:].copy_(torch.from_numpy(S["w"][d].astype(np.float32)).cuda())
+        ws.append(buf[offset:])
+    env["ctx"].burgers_step(_dev(env, S["rp"]), _dev(env, S["col"]), ws[0], ws[1], ws[2], 0.01, dt, u, v, 50)
+    torch.cuda.synchronize()
+    g = (u.double().cpu().numpy(), v.double().cpu().numpy())
     err = max(np.abs(g[c] - ref[c]).max() / np.abs(ref[c]).max() for c in range(2))
-    _say("  burgers fp32 rel err %.3e" % err)
+    _say("  burgers fp32 (stream offset %d) rel err %.3e" % (offset, err))
     assert err <= 1e-4
 
 

@@ -298,6 +298,44 @@ def test_apply_empty_rows_and_large_rows(env):
     assert np.all(out[:, :10] == 0)
 
 
+def _offset_copy(torch, a, offset):
+    """Device copy of a float32 array starting `offset` elements into a fresh
+    buffer (offset 1: not on a 16-byte boundary)."""
+    flat = torch.from_numpy(np.ascontiguousarray(a, np.float32)).reshape(-1)
+    buf = torch.zeros(flat.numel() + offset, dtype=torch.float32, device="cuda")
+    view = buf[offset:offset + flat.numel()]
+    view.copy_(flat.cuda())
+    return view.view(*a.shape)
+
+
+@pytest.mark.parametrize("nops,nnz_mod4,offset", [(1, 3, 0), (3, 0, 0), (3, 2, 0), (3, 0, 1), (1, 1, 1)])
+def test_apply_f32_stream_alignment(env, nops, nnz_mod4, offset):
+    """FP32 application with weight streams on and off 16-byte boundaries, nnz
+    of every residue mod 4, empty rows and rows of up to 131 entries: each
+    within the FP32 rounding bound of the oracle."""
+    torch = env["torch"]
+    O = env["O"]
+    rng = np.random.default_rng(7 + nops + nnz_mod4 + offset)
+    n = 517
+    lens = rng.integers(0, 129, n)
+    lens[:7] = 0
+    lens[-1] += (nnz_mod4 - lens.sum()) % 4
+    rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    nnz = int(rp[-1])
+    assert nnz % 4 == nnz_mod4
+    col = rng.integers(0, n, nnz).astype(np.int32)
+    w = rng.standard_normal((nops, nnz)).astype(np.float32)
+    u = rng.standard_normal(n).astype(np.float32)
+    wt = _offset_copy(torch, w, offset)
+    out = env["ctx"].apply_operator(_dev(env, rp), _dev(env, col), wt, _dev(env, u)).double().cpu().numpy()
+    for d in range(nops):
+        ref = O.apply(rp, col, w[d].astype(np.float64), u.astype(np.float64))
+        scale = np.array([np.abs(w[d][rp[i]:rp[i + 1]].astype(np.float64) * (u[col[rp[i]:rp[i + 1]]] - u[i])).sum()
+                          for i in range(n)])
+        assert np.all(np.abs(out[d] - ref) <= 2e-6 * scale + 1e-30), d
+    assert np.all(out[:, :7] == 0)
+
+
 # --------------------------------------------------------------------------- time stepping
 @pytest.fixture(scope="module")
 def adv_ops(env):
@@ -336,7 +374,8 @@ def test_step_fp64_parity(env, adv_ops, hv):
     assert err <= 1e-12
 
 
-def test_step_fp32_vs_fp64_oracle(env, adv_ops):
+@pytest.mark.parametrize("offset", [0, 1])
+def test_step_fp32_vs_fp64_oracle(env, adv_ops, offset):
     """FP32 application and state against the FP64 oracle.  Each stage rounds
     the sum of ~50 terms |w (u_j - u_i)| (amplification A = sum|w||du| / |L u|)
     at 2^-24; over S steps of RK4 the error grows at most linearly: bound
@@ -348,11 +387,12 @@ def test_step_fp32_vs_fp64_oracle(env, adv_ops):
     nsteps = 200
     ref = O.rk4(a["rp"], a["col"], a["wlin"], a["wbh"], a["gamma"], a["dt"], nsteps, a["u0"])
     u = _dev(env, a["u0"], torch.float32)
-    env["ctx"].step(_dev(env, a["rp"]), _dev(env, a["col"]), _dev(env, a["wlin"], torch.float32),
-                    _dev(env, a["wbh"], torch.float32), a["gamma"], a["dt"], u, nsteps)
+    # weight streams at offset 0 and at an odd element offset
+    env["ctx"].step(_dev(env, a["rp"]), _dev(env, a["col"]), _offset_copy(torch, a["wlin"], offset),
+                    _offset_copy(torch, a["wbh"], offset), a["gamma"], a["dt"], u, nsteps)
     torch.cuda.synchronize()
     err = np.abs(u.double().cpu().numpy() - ref).max() / np.abs(ref).max()
-    _say("  rk4 fp32 rel err %.3e" % err)
+    _say("  rk4 fp32 (stream offset %d) rel err %.3e" % (offset, err))
     assert err <= 1e-4
 
 
