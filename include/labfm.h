@@ -307,6 +307,34 @@ typedef struct {
 labfm_err labfm_burgers_step(void* ctx, const labfm_burgers_plan* plan, void* u, void* v, void* scratch,
                              int nsteps, int use_graph, void* stream);
 
+/* Global Laplacian solve (Sec. 5.2, eq. poisson_system): A^L Phi = F, where
+ * row i of A^L applies node i's Laplacian weights in difference form
+ * (A_ij = w_ij for j in row i, A_ii = -sum_j w_ij) and a node with
+ * fixed[i] != 0 has an identity row (A_ii = 1, Phi_i = F_i: Dirichlet data).
+ * Solver: BiCGStab with a Jacobi preconditioner applied on the right, FP64,
+ * started from the Phi passed in; it stops when ||F - A Phi||_2 <= tol ||F||_2,
+ * when the recurrence breaks down, or after max_iters iterations. */
+typedef struct {
+    const int64_t* row_ptr; /* device int64 [n+1]                            */
+    const int32_t* col;     /* device int32 [nnz]                            */
+    int64_t n, nnz;
+    const double* w_lap;    /* device FP64 [nnz]: Laplacian weights          */
+    const int8_t* fixed;    /* device int8 [n] or NULL: Dirichlet rows       */
+    double tol;             /* relative residual target, > 0                 */
+    int max_iters;          /* >= 0                                          */
+    int check_every;        /* iterations between host reads of the residual */
+} labfm_poisson_plan;
+
+/* Solve in place: phi (device FP64 [n]) holds the initial guess on entry and
+ * the solution on exit; F (device FP64 [n]) is not modified.  scratch: device,
+ * at least 8 n doubles.  On return (the call synchronises `stream`) *iters,
+ * *rel_resid (||F - A Phi|| / ||F|| of the returned Phi) and *converged (1 if
+ * the tolerance was met) are set (host pointers, each may be NULL).  A
+ * non-converged solve still returns LABFM_OK; argument errors return
+ * LABFM_EINVAL before any launch. */
+labfm_err labfm_poisson_solve(void* ctx, const labfm_poisson_plan* plan, const double* F, double* phi,
+                              void* scratch, int* iters, double* rel_resid, int* converged, void* stream);
+
 /* ---- learned warm start: features, network, training --------------------
  * Features of every node i < n (Sec. 2 stencil, scaled offsets d = r_ji / h_i,
  * h_i = R_i / 2): the row's neighbours ranked by (d_x^2 + d_y^2, j), the
@@ -355,7 +383,8 @@ labfm_err labfm_mlp_cast_bf16(void* ctx, const float* src, void* dst, int64_t co
  * contains `filter` (NULL: all), returns their count and summed duration in
  * milliseconds, and forgets them.  Kernel names: neigh_count, neigh_fill,
  * weights64_k1..k8, weights32_k1..k8, apply_f32, apply_f64, step_graph,
- * step_direct, burgers_graph, burgers_direct, mlp_features, mlp_forward,
+ * step_direct, burgers_graph, burgers_direct, poisson_setup,
+ * poisson_iterations, mlp_features, mlp_forward,
  * mlp_backward, mlp_loss, mlp_adam,
  * weights_batch_graph. */
 labfm_err labfm_timing_enable(void* ctx, int enable);

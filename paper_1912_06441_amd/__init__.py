@@ -25,7 +25,8 @@ EXPORTED = sorted(["labfm_last_error", "labfm_create", "labfm_destroy", "labfm_b
                    "labfm_combine", "labfm_apply_operator", "labfm_step", "labfm_timing_enable",
                    "labfm_timing_read", "labfm_mlp_features", "labfm_mlp_forward", "labfm_mlp_cache_floats",
                    "labfm_mlp_backward", "labfm_mlp_moment_loss", "labfm_mlp_adam", "labfm_mlp_cast_bf16",
-                   "labfm_weights_batched", "labfm_autotune_query", "labfm_burgers_step"])
+                   "labfm_weights_batched", "labfm_autotune_query", "labfm_burgers_step",
+                   "labfm_poisson_solve"])
 MLP_MAX_LAYERS = 8
 
 
@@ -70,6 +71,12 @@ class BurgersPlan(C.Structure):
                 ("w_hv", C.c_void_p), ("nu", C.c_double), ("dt", C.c_double), ("fixed", C.c_void_p)]
 
 
+class PoissonPlan(C.Structure):
+    _fields_ = [("row_ptr", C.c_void_p), ("col", C.c_void_p), ("n", C.c_int64), ("nnz", C.c_int64),
+                ("w_lap", C.c_void_p), ("fixed", C.c_void_p), ("tol", C.c_double), ("max_iters", C.c_int),
+                ("check_every", C.c_int)]
+
+
 class StepPlan(C.Structure):
     _fields_ = [("row_ptr", C.c_void_p), ("col", C.c_void_p), ("n", C.c_int64), ("nnz", C.c_int64),
                 ("dtype", C.c_int), ("w_lin", C.c_void_p), ("w_bh", C.c_void_p), ("gamma", C.c_double),
@@ -99,6 +106,8 @@ def load_library(path=LIB_PATH):
     L.labfm_apply_operator.argtypes = [vp, vp, vp, i64, i64, C.c_int, vp, C.c_int, vp, vp, vp]
     L.labfm_step.argtypes = [vp, C.POINTER(StepPlan), vp, vp, C.c_int, C.c_int, vp]
     L.labfm_burgers_step.argtypes = [vp, C.POINTER(BurgersPlan), vp, vp, vp, C.c_int, C.c_int, vp]
+    L.labfm_poisson_solve.argtypes = [vp, C.POINTER(PoissonPlan), vp, vp, vp, C.POINTER(C.c_int),
+                                      C.POINTER(C.c_double), C.POINTER(C.c_int), vp]
     L.labfm_mlp_features.argtypes = [vp, vp, vp, i64, C.POINTER(Domain), vp, vp, vp, C.c_int, vp, vp]
     L.labfm_mlp_forward.argtypes = [vp, C.POINTER(MLPDesc), vp, i64, vp, vp, C.c_int, vp]
     L.labfm_mlp_cache_floats.argtypes = [C.POINTER(MLPDesc), i64]
@@ -358,6 +367,29 @@ class Context:
         _check(self.lib.labfm_burgers_step(self.h, C.byref(plan), _ptr(u), _ptr(v), _ptr(scratch), int(nsteps),
                                            int(bool(use_graph)), _stream(torch)), "labfm_burgers_step")
         return u, v
+
+    def poisson_solve(self, row_ptr, col, w_lap, F, phi=None, fixed=None, tol=1e-10, max_iters=10000,
+                      check_every=16, scratch=None):
+        """Solve A^L phi = F (FP64, Jacobi-BiCGStab on the GPU); rows with
+        fixed != 0 are identity rows.  Returns (phi, iterations, relative
+        residual, converged)."""
+        torch = self.torch
+        n = F.numel()
+        if F.dtype != torch.float64 or w_lap.dtype != torch.float64:
+            raise ValueError("the Poisson solve is FP64: F and w_lap must be float64")
+        if phi is None:
+            phi = torch.zeros_like(F)
+        if scratch is None:
+            scratch = torch.empty(8 * n, dtype=torch.float64, device=F.device)
+        if fixed is not None and (fixed.dtype != torch.int8 or fixed.numel() != n or not fixed.is_contiguous()):
+            raise ValueError("fixed must be a contiguous int8 tensor of n entries")
+        plan = PoissonPlan(row_ptr.data_ptr(), col.data_ptr(), n, col.numel(), w_lap.data_ptr(),
+                           fixed.data_ptr() if fixed is not None else None, float(tol), int(max_iters),
+                           int(check_every))
+        it, res, conv = C.c_int(0), C.c_double(0.0), C.c_int(0)
+        _check(self.lib.labfm_poisson_solve(self.h, C.byref(plan), _ptr(F), _ptr(phi), _ptr(scratch), C.byref(it),
+                                            C.byref(res), C.byref(conv), _stream(torch)), "labfm_poisson_solve")
+        return phi, it.value, res.value, bool(conv.value)
 
 
 class MLP:

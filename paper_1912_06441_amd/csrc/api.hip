@@ -150,6 +150,7 @@ labfm_err labfm_destroy(void* ctx) {
     DeviceGuard g(c->device);
     if (c->step_exec) hipStreamSynchronize(c->step_stream);
     release_step_graph(c);
+    if (c->burgers.exec) hipStreamSynchronize(c->burgers.stream);
     release_burgers_graph(c);
     if (c->batch.exec) hipStreamSynchronize(c->batch.stream);
     release_batch(c);
@@ -158,7 +159,7 @@ labfm_err labfm_destroy(void* ctx) {
         hipEventDestroy(t.b);
     }
     Scratch* all[] = {&c->grid_count, &c->grid_idx, &c->node_cell, &c->counts, &c->scan_tmp, &c->worklist,
-                      &c->mixed,      &c->mlp_act,  &c->mlp_feat,  &c->mlp_psi, &c->mlp_part,
+                      &c->mixed,      &c->mlp_act,  &c->mlp_feat,  &c->mlp_psi, &c->mlp_part, &c->poisson,
                       &c->batch.d_sets, &c->batch.d_off, &c->batch.wl, &c->batch.rl};
     for (Scratch* s : all)
         if (s->p) hipFree(s->p);
@@ -345,6 +346,24 @@ labfm_err labfm_burgers_step(void* ctx, const labfm_burgers_plan* plan, void* u,
     Context* c = (Context*)ctx;
     DeviceGuard g(c->device);
     return burgers_launch(c, plan, u, v, scratch, nsteps, use_graph, (hipStream_t)stream);
+}
+
+labfm_err labfm_poisson_solve(void* ctx, const labfm_poisson_plan* plan, const double* F, double* phi, void* scratch,
+                              int* iters, double* rel_resid, int* converged, void* stream) {
+    if (!ctx || !plan) return fail(LABFM_EINVAL, "labfm_poisson_solve: ctx or plan is NULL");
+    if (plan->n < 0 || plan->nnz < 0) return fail(LABFM_EINVAL, "labfm_poisson_solve: negative size");
+    if (!(plan->tol > 0.0) || !std::isfinite(plan->tol)) return fail(LABFM_EINVAL, "labfm_poisson_solve: tol must be > 0");
+    if (plan->max_iters < 0 || plan->check_every < 1)
+        return fail(LABFM_EINVAL, "labfm_poisson_solve: max_iters >= 0 and check_every >= 1 required");
+    if (plan->n > 0 && (!plan->row_ptr || !F || !phi || !scratch || (plan->nnz > 0 && (!plan->col || !plan->w_lap))))
+        return fail(LABFM_EINVAL, "labfm_poisson_solve: NULL array");
+    if (iters) *iters = 0;
+    if (rel_resid) *rel_resid = 0.0;
+    if (converged) *converged = 1;
+    if (plan->n == 0) return LABFM_OK;
+    Context* c = (Context*)ctx;
+    DeviceGuard g(c->device);
+    return poisson_solve(c, plan, F, phi, (double*)scratch, iters, rel_resid, converged, (hipStream_t)stream);
 }
 
 labfm_err labfm_mlp_features(void* ctx, const double* x, const double* y, int64_t n, const labfm_domain* dom,

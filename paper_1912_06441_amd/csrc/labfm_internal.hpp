@@ -42,6 +42,7 @@ struct Context {
     Scratch mlp_feat;     // stencil features of one chunk of nodes
     Scratch mlp_psi;      // network output Psi0 of every node [n][outputs]
     Scratch mlp_part;     // column-sum partials of the bias gradients
+    Scratch poisson;      // reduction partials and scalars of the Krylov solve
     // cached RK4 step graph (replayed while plan, buffers and stream are unchanged)
     hipGraphExec_t step_exec = nullptr;
     hipStream_t step_stream = nullptr;
@@ -221,5 +222,7 @@ labfm_err step_launch(Context* c, const labfm_step_plan* plan, void* u, void* sc
                       int use_graph, hipStream_t st);
 labfm_err burgers_launch(Context* c, const labfm_burgers_plan* plan, void* u, void* v, void* scratch, int nsteps,
                          int use_graph, hipStream_t st);
+labfm_err poisson_solve(Context* c, const labfm_poisson_plan* plan, const double* F, double* phi, double* scratch,
+                        int* iters, double* rel_resid, int* converged, hipStream_t st);
 
 }  // namespace labfm

@@ -148,6 +148,12 @@ def config(name):
         # (Cole-Hopf solution), Re = 100, eps/dr = 0.2, h/dr = 2, quadratic x PAPER_D1,
         # dt = min(0.2 h / max|u|, 0.05 h^2 Re) (eq. tstep), resolutions h/H = 2/n_side;
         # the Re = 250 run adds -100 h^4 nabla^4 hyperviscosity (k = 6, eps/dr = 0.5, h/H = 2/81).
+        # Poisson's equation lap phi = f (Sec. 5.2), phi = sin(2 pi x) sin(2 pi y): periodic unit
+        # square with node 0 held at the exact value (the periodic problem fixes phi up to a
+        # constant), and the unit square with phi = 0 on the walls; quadratic x PAPER_D1,
+        # h/dr = 2 (3 for k = 7, 8), eps/dr = 0.5, BiCGStab to ||r|| <= 1e-10 ||F||.
+        "poisson": dict(abf=2, rbf=2, eps_paper=0.5, seed=13, tol=1e-10, sides=(20, 40, 80, 160),
+                        h_over_dr={2: 2.0, 3: 2.0, 4: 2.0, 5: 2.0, 6: 2.0, 7: 3.0, 8: 3.0}),
         "burgers": dict(abf=2, rbf=2, h_over_dr=2.0, Re=100.0, eps_paper=0.2, seed=11, t_end=0.4,
                         sides=(21, 41, 81, 161), Re_hv=250.0, hv_coef=100.0, hv_eps_paper=0.5, hv_side=81),
     }
@@ -337,3 +343,27 @@ def burgers_cole_hopf(x, t, Re, H=1.0, nterms=30):
 def burgers_dt(h, umax, Re):
     """Eq. (tstep): dt = min(0.2 h / max|u|, 0.05 h^2 Re)."""
     return min(0.2 * h / umax, 0.05 * h * h * Re)
+
+
+# ---------------------------------------------------------------------------
+# Poisson's equation (Sec. 5.2)
+
+
+def poisson_solution(x, y):
+    """phi = sin(2 pi x) sin(2 pi y); lap phi = -8 pi^2 phi."""
+    return np.sin(2 * math.pi * x) * np.sin(2 * math.pi * y)
+
+
+def poisson_source(x, y):
+    return -8.0 * math.pi ** 2 * poisson_solution(x, y)
+
+
+def poisson_system(x, y, fixed):
+    """Right-hand side F of eq. (poisson_system): f on free rows, the exact
+    value on Dirichlet rows; and the initial guess (exact value on Dirichlet
+    rows, 0 elsewhere)."""
+    phi = poisson_solution(x, y)
+    fx = np.asarray(fixed) != 0
+    F = np.where(fx, phi, poisson_source(x, y))
+    x0 = np.where(fx, phi, 0.0)
+    return F, x0
