@@ -90,6 +90,7 @@ def main():
     ap.add_argument("--no-rk4", action="store_true")
     ap.add_argument("--rk4-steps", type=int, default=200)
     ap.add_argument("--no-burgers", action="store_true", help="skip the Burgers step measurement")
+    ap.add_argument("--no-poisson", action="store_true", help="skip the Poisson solve measurement")
     ap.add_argument("--burgers-steps", type=int, default=200)
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-set batched weights measurement")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -222,6 +223,8 @@ def main():
         rec["rk4_c5"] = run_rk4(ctx, torch, np, L, WL, args.rk4_steps)
     if not args.no_burgers:
         rec["burgers_1024"] = run_burgers(ctx, torch, np, L, WL, args.burgers_steps)
+    if not args.no_poisson:
+        rec["poisson_1024"] = run_poisson(ctx, torch, np, L, WL)
     if not args.no_batch:
         rec["batch_c3"] = run_batch(ctx, torch, np, L, WL, reps=3)
     rec["mlp_bf16"] = run_mlp(ctx, torch, L, WL)
@@ -349,6 +352,52 @@ def run_burgers(ctx, torch, np, L, WL, nsteps):
             "GB_per_s": bytes_step / (ms_step / 1e3) / 1e9, "hbm_frac": bytes_step / (ms_step / 1e3) / PEAK_HBM,
             "bytes_per_step": bytes_step, "weights_all_ok": bool((st == 0).all().item()),
             "finite": bool(torch.isfinite(u).all().item() and torch.isfinite(v).all().item())}
+
+
+def run_poisson(ctx, torch, np, L, WL, tol=1e-10):
+    """Periodic Poisson solve (Jacobi-BiCGStab, FP64) with the order-6
+    Laplacian of the 1024x1024 node set, node 0 pinned to the exact value."""
+    dev = torch.device("cuda:0")
+    cfg = WL.config("c5")
+    nd = WL.make_nodes(cfg)
+    n = nd["x"].size
+    x = torch.from_numpy(nd["x"]).to(dev)
+    y = torch.from_numpy(nd["y"]).to(dev)
+    R = torch.from_numpy(nd["R"]).to(dev)
+    order = torch.from_numpy(nd["order"]).to(dev)
+    rp, col = ctx.build_neighbours(x, y, R, order, nd["domain"])
+    w64, _, st, _, _ = ctx.weights(x, y, R, order, rp, col, nd["domain"], ops=L.OP_LAP)
+    w = w64[0].contiguous()
+    fixed_np = np.zeros(n, np.int8)
+    fixed_np[0] = 1
+    F_np, x0_np = WL.poisson_system(nd["x"], nd["y"], fixed_np)
+    F = torch.from_numpy(F_np).to(dev)
+    fixed = torch.from_numpy(fixed_np).to(dev)
+    scratch = torch.empty(8 * n, dtype=torch.float64, device=dev)
+    phi = torch.from_numpy(x0_np).to(dev)
+    ctx.poisson_solve(rp, col, w, F, phi=phi, fixed=fixed, tol=tol, max_iters=20, scratch=scratch)  # warm-up
+    phi = torch.from_numpy(x0_np).to(dev)
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    t0 = time.perf_counter()
+    phi, it, res, ok = ctx.poisson_solve(rp, col, w, F, phi=phi, fixed=fixed, tol=tol, max_iters=20000,
+                                         check_every=32, scratch=scratch)
+    t1 = time.perf_counter()
+    ctx.timing(False)
+    ki = ctx.timing_read("poisson_iterations")
+    ctx.timing_read(None)
+    nnz = col.numel()
+    ex = WL.poisson_solution(nd["x"], nd["y"])
+    err = float(np.linalg.norm(phi.cpu().numpy() - ex) / np.linalg.norm(ex))
+    ms_it = ki[1] / max(it, 1)
+    # per iteration: two products (col 4 B + w 8 B per entry; row bounds, x_i, y_i and the
+    # Dirichlet flag per row) and the vector updates and reductions (25 FP64 vectors of n:
+    # p-update 6, (r0, v) 2, s-update 8, (t, s) and (t, t) 2, r-update with its two sums 7)
+    bytes_it = 2 * (nnz * 12 + n * 25) + 25 * 8 * n
+    return {"nodes": n, "nnz": nnz, "iterations": it, "converged": ok, "rel_resid": res, "L2_error": err,
+            "solve_ms": (t1 - t0) * 1e3, "ms_per_iteration": ms_it,
+            "GB_per_s": bytes_it / (ms_it / 1e3) / 1e9, "hbm_frac": bytes_it / (ms_it / 1e3) / PEAK_HBM,
+            "weights_all_ok": bool((st == 0).all().item())}
 
 
 def run_mlp(ctx, torch, L, WL, B=1 << 20, reps=5):
