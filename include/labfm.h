@@ -335,6 +335,38 @@ typedef struct {
 labfm_err labfm_poisson_solve(void* ctx, const labfm_poisson_plan* plan, const double* F, double* phi,
                               void* scratch, int* iters, double* rel_resid, int* converged, void* stream);
 
+/* Incompressible Navier-Stokes in vorticity-streamfunction form (Sec. 5.4):
+ *   d omega/dt = -(u L^x(omega) + v L^y(omega)) + nu L^L(omega),
+ *   L^L psi = -omega,  u = L^y(psi),  v = -L^x(psi),
+ * classical RK4 (Sec. 5.1) in FP64; at every stage psi is re-solved with
+ * labfm_poisson_solve's method (warm-started from the previous psi) with the
+ * rows marked in psi_fixed held at psi = 0 (on a periodic domain one pinned
+ * node fixes the free constant). */
+typedef struct {
+    const int64_t* row_ptr; /* device int64 [n+1]                                 */
+    const int32_t* col;     /* device int32 [nnz]                                 */
+    int64_t n, nnz;
+    const double* w_x;      /* device FP64 [nnz]: d/dx weights                    */
+    const double* w_y;      /* device FP64 [nnz]: d/dy weights                    */
+    const double* w_lap;    /* device FP64 [nnz]: Laplacian weights               */
+    const int8_t* psi_fixed;/* device int8 [n] or NULL: rows with psi = 0         */
+    double nu;              /* 1 / Re                                             */
+    double dt;
+    double tol;             /* relative residual of every stream-function solve   */
+    int max_iters;          /* per solve                                          */
+    int check_every;        /* per solve, as in labfm_poisson_plan                */
+} labfm_ns_plan;
+
+/* Advance omega (device FP64 [n]) by nsteps RK4 steps; psi (device FP64 [n])
+ * holds the initial guess of the first solve on entry and the stream function
+ * of the last step's first stage on exit.  scratch: device, at least 14 n
+ * doubles, aliasing neither omega nor psi.  Synchronises `stream` at every
+ * solve.  *solver_iters receives the BiCGStab iterations summed over all
+ * solves and *all_converged 1 if every solve met tol (host pointers, each may
+ * be NULL).  Argument errors return LABFM_EINVAL before any launch. */
+labfm_err labfm_ns_step(void* ctx, const labfm_ns_plan* plan, double* omega, double* psi, void* scratch, int nsteps,
+                        int* solver_iters, int* all_converged, void* stream);
+
 /* ---- learned warm start: features, network, training --------------------
  * Features of every node i < n (Sec. 2 stencil, scaled offsets d = r_ji / h_i,
  * h_i = R_i / 2): the row's neighbours ranked by (d_x^2 + d_y^2, j), the

@@ -26,7 +26,7 @@ EXPORTED = sorted(["labfm_last_error", "labfm_create", "labfm_destroy", "labfm_b
                    "labfm_timing_read", "labfm_mlp_features", "labfm_mlp_forward", "labfm_mlp_cache_floats",
                    "labfm_mlp_backward", "labfm_mlp_moment_loss", "labfm_mlp_adam", "labfm_mlp_cast_bf16",
                    "labfm_weights_batched", "labfm_autotune_query", "labfm_burgers_step",
-                   "labfm_poisson_solve"])
+                   "labfm_poisson_solve", "labfm_ns_step"])
 MLP_MAX_LAYERS = 8
 
 
@@ -77,6 +77,13 @@ class PoissonPlan(C.Structure):
                 ("check_every", C.c_int)]
 
 
+class NSPlan(C.Structure):
+    _fields_ = [("row_ptr", C.c_void_p), ("col", C.c_void_p), ("n", C.c_int64), ("nnz", C.c_int64),
+                ("w_x", C.c_void_p), ("w_y", C.c_void_p), ("w_lap", C.c_void_p), ("psi_fixed", C.c_void_p),
+                ("nu", C.c_double), ("dt", C.c_double), ("tol", C.c_double), ("max_iters", C.c_int),
+                ("check_every", C.c_int)]
+
+
 class StepPlan(C.Structure):
     _fields_ = [("row_ptr", C.c_void_p), ("col", C.c_void_p), ("n", C.c_int64), ("nnz", C.c_int64),
                 ("dtype", C.c_int), ("w_lin", C.c_void_p), ("w_bh", C.c_void_p), ("gamma", C.c_double),
@@ -106,6 +113,8 @@ def load_library(path=LIB_PATH):
     L.labfm_apply_operator.argtypes = [vp, vp, vp, i64, i64, C.c_int, vp, C.c_int, vp, vp, vp]
     L.labfm_step.argtypes = [vp, C.POINTER(StepPlan), vp, vp, C.c_int, C.c_int, vp]
     L.labfm_burgers_step.argtypes = [vp, C.POINTER(BurgersPlan), vp, vp, vp, C.c_int, C.c_int, vp]
+    L.labfm_ns_step.argtypes = [vp, C.POINTER(NSPlan), vp, vp, vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                vp]
     L.labfm_poisson_solve.argtypes = [vp, C.POINTER(PoissonPlan), vp, vp, vp, C.POINTER(C.c_int),
                                       C.POINTER(C.c_double), C.POINTER(C.c_int), vp]
     L.labfm_mlp_features.argtypes = [vp, vp, vp, i64, C.POINTER(Domain), vp, vp, vp, C.c_int, vp, vp]
@@ -390,6 +399,30 @@ class Context:
         _check(self.lib.labfm_poisson_solve(self.h, C.byref(plan), _ptr(F), _ptr(phi), _ptr(scratch), C.byref(it),
                                             C.byref(res), C.byref(conv), _stream(torch)), "labfm_poisson_solve")
         return phi, it.value, res.value, bool(conv.value)
+
+    def ns_step(self, row_ptr, col, w_x, w_y, w_lap, nu, dt, omega, nsteps, psi=None, psi_fixed=None, tol=1e-10,
+                max_iters=10000, check_every=8, scratch=None):
+        """Advance the vorticity in place by nsteps RK4 steps of the vorticity-
+        streamfunction Navier-Stokes equations (FP64).  Returns (omega, psi,
+        BiCGStab iterations over all solves, all solves converged)."""
+        torch = self.torch
+        n = omega.numel()
+        for t in (w_x, w_y, w_lap, omega):
+            if t.dtype != torch.float64:
+                raise ValueError("the vorticity-streamfunction step is FP64")
+        if psi is None:
+            psi = torch.zeros_like(omega)
+        if scratch is None:
+            scratch = torch.empty(14 * n, dtype=torch.float64, device=omega.device)
+        if psi_fixed is not None and (psi_fixed.dtype != torch.int8 or psi_fixed.numel() != n):
+            raise ValueError("psi_fixed must be an int8 tensor of n entries")
+        plan = NSPlan(row_ptr.data_ptr(), col.data_ptr(), n, col.numel(), w_x.data_ptr(), w_y.data_ptr(),
+                      w_lap.data_ptr(), psi_fixed.data_ptr() if psi_fixed is not None else None, float(nu), float(dt),
+                      float(tol), int(max_iters), int(check_every))
+        it, conv = C.c_int(0), C.c_int(0)
+        _check(self.lib.labfm_ns_step(self.h, C.byref(plan), _ptr(omega), _ptr(psi), _ptr(scratch), int(nsteps),
+                                      C.byref(it), C.byref(conv), _stream(torch)), "labfm_ns_step")
+        return omega, psi, it.value, bool(conv.value)
 
 
 class MLP:

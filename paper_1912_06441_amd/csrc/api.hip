@@ -366,6 +366,26 @@ labfm_err labfm_poisson_solve(void* ctx, const labfm_poisson_plan* plan, const d
     return poisson_solve(c, plan, F, phi, (double*)scratch, iters, rel_resid, converged, (hipStream_t)stream);
 }
 
+labfm_err labfm_ns_step(void* ctx, const labfm_ns_plan* plan, double* omega, double* psi, void* scratch, int nsteps,
+                        int* solver_iters, int* all_converged, void* stream) {
+    if (!ctx || !plan) return fail(LABFM_EINVAL, "labfm_ns_step: ctx or plan is NULL");
+    if (plan->n < 0 || plan->nnz < 0 || nsteps < 0) return fail(LABFM_EINVAL, "labfm_ns_step: negative size");
+    if (!(plan->tol > 0.0) || !std::isfinite(plan->tol) || plan->max_iters < 0 || plan->check_every < 1)
+        return fail(LABFM_EINVAL, "labfm_ns_step: tol > 0, max_iters >= 0 and check_every >= 1 required");
+    if (!std::isfinite(plan->dt) || !std::isfinite(plan->nu)) return fail(LABFM_EINVAL, "labfm_ns_step: dt/nu not finite");
+    if (plan->n > 0 && (!plan->row_ptr || !omega || !psi || !scratch ||
+                        (plan->nnz > 0 && (!plan->col || !plan->w_x || !plan->w_y || !plan->w_lap))))
+        return fail(LABFM_EINVAL, "labfm_ns_step: NULL array");
+    if (plan->n > 0 && (omega == psi || (void*)omega == scratch || (void*)psi == scratch))
+        return fail(LABFM_EINVAL, "labfm_ns_step: omega, psi and scratch must be distinct buffers");
+    if (solver_iters) *solver_iters = 0;
+    if (all_converged) *all_converged = 1;
+    if (plan->n == 0 || nsteps == 0) return LABFM_OK;
+    Context* c = (Context*)ctx;
+    DeviceGuard g(c->device);
+    return ns_step(c, plan, omega, psi, (double*)scratch, nsteps, solver_iters, all_converged, (hipStream_t)stream);
+}
+
 labfm_err labfm_mlp_features(void* ctx, const double* x, const double* y, int64_t n, const labfm_domain* dom,
                              const double* R, const int64_t* row_ptr, const int32_t* col, int kmax, float* feat,
                              void* stream) {

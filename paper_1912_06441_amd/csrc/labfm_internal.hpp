@@ -224,5 +224,7 @@ labfm_err burgers_launch(Context* c, const labfm_burgers_plan* plan, void* u, vo
                          int use_graph, hipStream_t st);
 labfm_err poisson_solve(Context* c, const labfm_poisson_plan* plan, const double* F, double* phi, double* scratch,
                         int* iters, double* rel_resid, int* converged, hipStream_t st);
+labfm_err ns_step(Context* c, const labfm_ns_plan* plan, double* omega, double* psi, double* scratch, int nsteps,
+                  int* solver_iters, int* all_converged, hipStream_t st);
 
 }  // namespace labfm

@@ -154,6 +154,12 @@ def config(name):
         # h/dr = 2 (3 for k = 7, 8), eps/dr = 0.5, BiCGStab to ||r|| <= 1e-10 ||F||.
         "poisson": dict(abf=2, rbf=2, eps_paper=0.5, seed=13, tol=1e-10, sides=(20, 40, 80, 160),
                         h_over_dr={2: 2.0, 3: 2.0, 4: 2.0, 5: 2.0, 6: 2.0, 7: 3.0, 8: 3.0}),
+        # Taylor-Green vortices (Sec. 5.4), vorticity-streamfunction form on the periodic unit
+        # square: omega = 4 pi sin(2 pi x) sin(2 pi y) exp(-8 pi^2 t / Re), Re = 100, quadratic x
+        # PAPER_D1, h/dr = 2 and eps/dr = 0.5 (k = 2, 4, 6), dt by eq. (tstep) with max|u| = 1,
+        # stream function pinned to 0 at node 0, Poisson tolerance 1e-10.
+        "taylor_green": dict(abf=2, rbf=2, Re=100.0, h_over_dr=2.0, eps_paper=0.5, seed=17, tol=1e-10,
+                             t_end=0.5, sides=(10, 20, 40, 80)),
         "burgers": dict(abf=2, rbf=2, h_over_dr=2.0, Re=100.0, eps_paper=0.2, seed=11, t_end=0.4,
                         sides=(21, 41, 81, 161), Re_hv=250.0, hv_coef=100.0, hv_eps_paper=0.5, hv_side=81),
     }
@@ -367,3 +373,13 @@ def poisson_system(x, y, fixed):
     F = np.where(fx, phi, poisson_source(x, y))
     x0 = np.where(fx, phi, 0.0)
     return F, x0
+
+
+# ---------------------------------------------------------------------------
+# Taylor-Green vortices (Sec. 5.4)
+
+
+def taylor_green_vorticity(x, y, t, Re, H=1.0):
+    """omega = (4 pi / H) sin(2 pi x / H) sin(2 pi y / H) exp(-8 pi^2 t / (Re H^2))."""
+    return (4.0 * math.pi / H) * np.sin(2 * math.pi * x / H) * np.sin(2 * math.pi * y / H) * \
+        math.exp(-8.0 * math.pi ** 2 * t / (Re * H * H))

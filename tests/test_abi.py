@@ -74,6 +74,7 @@ def test_new_entry_points_validate_before_device_work(lib):
         "labfm_mlp_cast_bf16": (None, None, None, c.c_int64(0), None),
         "labfm_burgers_step": (None, None, None, None, None, 1, 1, None),
         "labfm_poisson_solve": (None, None, None, None, None, None, None, None, None),
+        "labfm_ns_step": (None, None, None, None, None, 1, None, None, None),
     }
     for name, args in calls.items():
         fn = getattr(lib, name)
