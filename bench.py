@@ -91,6 +91,7 @@ def main():
     ap.add_argument("--rk4-steps", type=int, default=200)
     ap.add_argument("--no-burgers", action="store_true", help="skip the Burgers step measurement")
     ap.add_argument("--no-poisson", action="store_true", help="skip the Poisson solve measurement")
+    ap.add_argument("--no-ns", action="store_true", help="skip the Taylor-Green Navier-Stokes measurement")
     ap.add_argument("--burgers-steps", type=int, default=200)
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-set batched weights measurement")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -211,7 +212,8 @@ def main():
                      "kernel": "weights64_k8", "flops_per_launch": flops8},
         "roofline_apply": {"bound": "hbm", "achieved": apply_bytes / (ka_ms / 1e3) / 1e9, "peak": PEAK_HBM / 1e9,
                            "unit": "GB/s", "frac": apply_bytes / (ka_ms / 1e3) / PEAK_HBM,
-                           "traffic": measured_traffic("apply_f64", ["apply.hip"]), "kernel": "apply_f64",
+                           "traffic": measured_traffic("apply_f64", ["apply.hip", "stencil_rows.hpp"]),
+                           "kernel": "apply_f64",
                            "bytes_per_launch": apply_bytes},
     }
 
@@ -225,6 +227,8 @@ def main():
         rec["burgers_1024"] = run_burgers(ctx, torch, np, L, WL, args.burgers_steps)
     if not args.no_poisson:
         rec["poisson_1024"] = run_poisson(ctx, torch, np, L, WL)
+    if not args.no_ns:
+        rec["taylor_green_256"] = run_ns(ctx, torch, np, L, WL)
     if not args.no_batch:
         rec["batch_c3"] = run_batch(ctx, torch, np, L, WL, reps=3)
     rec["mlp_bf16"] = run_mlp(ctx, torch, L, WL)
@@ -397,6 +401,44 @@ def run_poisson(ctx, torch, np, L, WL, tol=1e-10):
     return {"nodes": n, "nnz": nnz, "iterations": it, "converged": ok, "rel_resid": res, "L2_error": err,
             "solve_ms": (t1 - t0) * 1e3, "ms_per_iteration": ms_it,
             "GB_per_s": bytes_it / (ms_it / 1e3) / 1e9, "hbm_frac": bytes_it / (ms_it / 1e3) / PEAK_HBM,
+            "weights_all_ok": bool((st == 0).all().item())}
+
+
+def run_ns(ctx, torch, np, L, WL, side=256, k=6, nsteps=10):
+    """Taylor-Green vortices (vorticity-streamfunction, FP64, Re = 100) on a
+    256x256 periodic order-6 set: ms per RK4 step (four stream-function
+    solves to 1e-10, warm-started) and the error against the exact decay."""
+    dev = torch.device("cuda:0")
+    cfg = WL.config("taylor_green")
+    x_np, y_np, s = WL.jittered_lattice(side, eps=WL.paper_jitter(cfg["eps_paper"]), seed=cfg["seed"], periodic=True)
+    n = x_np.size
+    x = torch.from_numpy(x_np).to(dev)
+    y = torch.from_numpy(y_np).to(dev)
+    R = torch.full((n,), 2.0 * cfg["h_over_dr"] * s, dtype=torch.float64, device=dev)
+    order = torch.full((n,), k, dtype=torch.int8, device=dev)
+    dom = WL.unit_domain(True)
+    rp, col = ctx.build_neighbours(x, y, R, order, dom)
+    w, _, st, _, _ = ctx.weights(x, y, R, order, rp, col, dom, ops=7, abf=cfg["abf"], rbf=cfg["rbf"])
+    wx, wy, wl = (w[d].contiguous() for d in range(3))
+    fixed = torch.zeros(n, dtype=torch.int8, device=dev)
+    fixed[0] = 1
+    Re = cfg["Re"]
+    h = cfg["h_over_dr"] * s
+    dt = WL.burgers_dt(h, 1.0, Re)
+    om = torch.from_numpy(WL.taylor_green_vorticity(x_np, y_np, 0.0, Re)).to(dev)
+    psi = torch.zeros(n, dtype=torch.float64, device=dev)
+    scratch = torch.empty(14 * n, dtype=torch.float64, device=dev)
+    ctx.ns_step(rp, col, wx, wy, wl, 1.0 / Re, dt, om, 1, psi=psi, psi_fixed=fixed, tol=cfg["tol"], scratch=scratch)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    om, psi, it, ok = ctx.ns_step(rp, col, wx, wy, wl, 1.0 / Re, dt, om, nsteps, psi=psi, psi_fixed=fixed,
+                                  tol=cfg["tol"], scratch=scratch)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ex = WL.taylor_green_vorticity(x_np, y_np, (nsteps + 1) * dt, Re)
+    err = float(np.linalg.norm(om.cpu().numpy() - ex) / np.linalg.norm(ex))
+    return {"nodes": n, "nnz": col.numel(), "order": k, "steps": nsteps, "ms_per_rk4_step": (t1 - t0) * 1e3 / nsteps,
+            "bicgstab_iterations_per_solve": it / (4.0 * nsteps), "all_solves_converged": ok, "L2_error": err,
             "weights_all_ok": bool((st == 0).all().item())}
 
 
