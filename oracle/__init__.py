@@ -18,12 +18,17 @@ from . import build as _build
 ABF_HERMITE, ABF_PAPER, ABF_PAPER_D1 = 0, 1, 2
 RBF_WENDLAND_C2, RBF_CONE, RBF_QUADRATIC, RBF_WENDLAND_C6, RBF_GAUSSIAN = 0, 1, 2, 3, 4
 OP_DX, OP_DY, OP_LAP, OP_BIHARM, OP_TRIHARM = 1, 2, 4, 8, 16
+OP_DZ = 32  # three dimensions only
 ST_OK, ST_NOT_CONVERGED, ST_SINGULAR, ST_TOO_FEW, ST_DEGENERATE, ST_ORDER_TOO_LOW = range(6)
 MAXK = 8
 
 
 class _Domain(C.Structure):
     _fields_ = [("lo", C.c_double * 2), ("hi", C.c_double * 2), ("periodic", C.c_int * 2)]
+
+
+class _Domain3(C.Structure):
+    _fields_ = [("lo", C.c_double * 3), ("hi", C.c_double * 3), ("periodic", C.c_int * 3)]
 
 
 class _WOpts(C.Structure):
@@ -58,6 +63,14 @@ def lib():
         L.or_weights.argtypes = [C.c_int64, dp, dp, C.POINTER(_Domain), dp, i8, i64, i32,
                                  C.POINTER(_WOpts), dp, i8, dp, i8]
         L.or_targets.argtypes = [C.c_uint, C.c_int, dp]
+        L.or_p3_of_k.argtypes = [C.c_int]
+        L.or_index_table3.argtypes = [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.or_monomials3.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, dp]
+        L.or_abfs3.argtypes = [C.c_int, C.c_double, C.c_int, C.c_double, C.c_double, C.c_double, dp]
+        L.or_neighbours3_brute.argtypes = [C.c_int64, dp, dp, dp, C.POINTER(_Domain3), dp, i64, i32]
+        L.or_neighbours3_brute.restype = C.c_int64
+        L.or_weights3.argtypes = [C.c_int64, dp, dp, dp, C.POINTER(_Domain3), dp, C.c_int, i64, i32,
+                                  C.POINTER(_WOpts), dp, i8, dp, i8]
         L.or_stencils_psi.argtypes = [C.c_int64, C.c_int, C.c_int, i32, dp, dp, C.POINTER(_WOpts), dp, i8, dp, dp]
         L.or_stencils_psi.restype = None
         L.or_apply.argtypes = [C.c_int64, i64, i32, dp, dp, dp]
@@ -292,3 +305,75 @@ def num_threads():
 
 def set_num_threads(t):
     lib().or_set_num_threads(int(t))
+
+
+# ---------------------------------------------------------------------------
+# three dimensions (HERMITE family)
+
+
+def p3_of_k(k):
+    return lib().or_p3_of_k(int(k))
+
+
+def index_table3(k):
+    p = p3_of_k(k)
+    ea, eb, ec = (C.c_int * p)(), (C.c_int * p)(), (C.c_int * p)()
+    lib().or_index_table3(int(k), ea, eb, ec)
+    return list(zip(list(ea), list(eb), list(ec)))
+
+
+def monomials3(k, dx, dy, dz):
+    X = np.zeros(p3_of_k(k))
+    lib().or_monomials3(int(k), float(dx), float(dy), float(dz), _p(X, C.c_double))
+    return X
+
+
+def abfs3(k, dx, dy, dz, rbf=RBF_WENDLAND_C2, sigma=1.0):
+    W = np.zeros(p3_of_k(k))
+    lib().or_abfs3(int(rbf), float(sigma), int(k), float(dx), float(dy), float(dz), _p(W, C.c_double))
+    return W
+
+
+def _dom3(domain):
+    d = _Domain3()
+    for a in range(3):
+        d.lo[a] = float(domain["lo"][a])
+        d.hi[a] = float(domain["hi"][a])
+        d.periodic[a] = int(bool(domain["periodic"][a]))
+    return d
+
+
+def neighbours3(x, y, z, domain, R):
+    """3-D neighbour lists by brute force (CSR, ascending j): (row_ptr, col)."""
+    xs = [np.ascontiguousarray(a, np.float64) for a in (x, y, z)]
+    n = xs[0].size
+    R = np.ascontiguousarray(np.broadcast_to(np.asarray(R, np.float64), (n,)), np.float64)
+    d = _dom3(domain)
+    rp = np.zeros(n + 1, np.int64)
+    ptrs = [_p(a, C.c_double) for a in xs]
+    lib().or_neighbours3_brute(n, *ptrs, C.byref(d), _p(R, C.c_double), _p(rp, C.c_int64), None)
+    col = np.zeros(max(int(rp[-1]), 1), np.int32)
+    lib().or_neighbours3_brute(n, *ptrs, C.byref(d), _p(R, C.c_double), _p(rp, C.c_int64), _p(col, C.c_int32))
+    return rp, col[:int(rp[-1])]
+
+
+def weights3(x, y, z, domain, R, k, row_ptr, col, ops=OP_DX | OP_DY | OP_DZ | OP_LAP, rbf=RBF_WENDLAND_C2,
+             sigma=1.0, tol_stop=1e-13, max_iters=5):
+    """3-D weights [nops, nnz] (operators in bit order: dx, dy, lap, dz), status, resid, iters."""
+    o = _WOpts(ABF_HERMITE, int(rbf), float(sigma), int(ops), float(tol_stop), int(max_iters))
+    xs = [np.ascontiguousarray(a, np.float64) for a in (x, y, z)]
+    n = xs[0].size
+    R = np.ascontiguousarray(np.broadcast_to(np.asarray(R, np.float64), (n,)), np.float64)
+    row_ptr = np.ascontiguousarray(row_ptr, np.int64)
+    col = np.ascontiguousarray(col, np.int32)
+    nnz = int(row_ptr[-1])
+    nop = bin(int(ops) & 63).count("1")
+    w = np.zeros((nop, max(nnz, 1)))
+    st = np.zeros(n, np.int8)
+    res = np.zeros(n)
+    its = np.zeros(n, np.int8)
+    d = _dom3(domain)
+    lib().or_weights3(n, *[_p(a, C.c_double) for a in xs], C.byref(d), _p(R, C.c_double), int(k),
+                      _p(row_ptr, C.c_int64), _p(col, C.c_int32), C.byref(o), _p(w, C.c_double),
+                      _p(st, C.c_int8), _p(res, C.c_double), _p(its, C.c_int8))
+    return w[:, :nnz], st, res, its

@@ -907,5 +907,234 @@ void or_burgers_rk4(int64_t n, const int64_t* row_ptr, const int32_t* col, const
     free(us); free(vs); free(t);
 }
 
+/* ======================================================================== */
+/* Three dimensions.  Sec. 3.1: in 3-D, p is the sum of the triangular       */
+/* numbers 2..k+1 (3, 9, 19, 34 for k = 1..4).  Element order (a reading):    */
+/* total order n = 1..k; within n, a = n..0, then b = n-a..0, c = n-a-b.      */
+/* X_m = x^a y^b z^c / (a! b! c!) (the Taylor coefficients, as eq. (1));      */
+/* ABFs of the HERMITE family H_a(s x) H_b(s y) H_c(s z) phi(|d|).            */
+
+int or_p3_of_k(int k) {
+    int p = 0;
+    for (int m = 2; m <= k + 1; ++m) p += m * (m + 1) / 2;
+    return p;
+}
+
+void or_index_table3(int k, int* ea, int* eb, int* ec) {
+    int m = 0;
+    for (int n = 1; n <= k; ++n)
+        for (int a = n; a >= 0; --a)
+            for (int b = n - a; b >= 0; --b) {
+                ea[m] = a;
+                eb[m] = b;
+                ec[m] = n - a - b;
+                ++m;
+            }
+}
+
+void or_monomials3(int k, double dx, double dy, double dz, double* X) {
+    int ea[OR_MAXP], eb[OR_MAXP], ec[OR_MAXP];
+    or_index_table3(k, ea, eb, ec);
+    int p = or_p3_of_k(k);
+    for (int m = 0; m < p; ++m) {
+        double v = 1.0;
+        for (int e = 0; e < ea[m]; ++e) v *= dx;
+        for (int e = 0; e < eb[m]; ++e) v *= dy;
+        for (int e = 0; e < ec[m]; ++e) v *= dz;
+        X[m] = v / (or_factorial(ea[m]) * or_factorial(eb[m]) * or_factorial(ec[m]));
+    }
+}
+
+int or_abfs3(int rbf, double sigma, int k, double dx, double dy, double dz, double* W) {
+    int ea[OR_MAXP], eb[OR_MAXP], ec[OR_MAXP];
+    or_index_table3(k, ea, eb, ec);
+    int p = or_p3_of_k(k);
+    double q = sqrt(dx * dx + dy * dy + dz * dz);
+    double f[4];
+    if (or_rbf_derivs(rbf, q, f) != 0) return -1;
+    double Hx[OR_MAXK + 1], Hy[OR_MAXK + 1], Hz[OR_MAXK + 1];
+    or_hermite(k, sigma * dx, Hx);
+    or_hermite(k, sigma * dy, Hy);
+    or_hermite(k, sigma * dz, Hz);
+    for (int m = 0; m < p; ++m) W[m] = Hx[ea[m]] * Hy[eb[m]] * Hz[ec[m]] * f[0];
+    return 0;
+}
+
+/* 3-D targets: d/dx e(1,0,0), d/dy e(0,1,0), d/dz e(0,0,1) (elements 1, 2, 3),
+ * Laplacian e(2,0,0) + e(0,2,0) + e(0,0,2) (elements 4, 7, 9; 1-based). */
+static int or_target3(unsigned op, int p, double* C, int* l) {
+    for (int m = 0; m < p; ++m) C[m] = 0.0;
+    switch (op) {
+        case OR_OP_DX: C[0] = 1.0; *l = 1; return 0;
+        case OR_OP_DY: C[1] = 1.0; *l = 1; return 0;
+        case OR_OP_DZ: C[2] = 1.0; *l = 1; return 0;
+        case OR_OP_LAP:
+            if (p < 9) return -1;
+            C[3] = 1.0; C[6] = 1.0; C[8] = 1.0; *l = 2; return 0;
+    }
+    return -1;
+}
+
+/* operators of a 3-D request, in increasing bit order (DX, DY, LAP, DZ) */
+static int or_ops3(unsigned ops, unsigned* list) {
+    int c = 0;
+    for (int b = 0; b < 6; ++b)
+        if ((ops >> b) & 1u) list[c++] = 1u << b;
+    return c;
+}
+
+/* Neighbours in 3-D by brute force: j != i, squared distance (summed x, y, z
+ * in that order) < R_i^2, minimum image on periodic axes, ascending j.  col
+ * NULL: row_ptr only. */
+int64_t or_neighbours3_brute(int64_t n, const double* x, const double* y, const double* z,
+                             const or_domain3* dom, const double* R, int64_t* row_ptr, int32_t* col) {
+    double L[3] = {dom->hi[0] - dom->lo[0], dom->hi[1] - dom->lo[1], dom->hi[2] - dom->lo[2]};
+    int64_t* cnt = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i) {
+        double R2 = R[i] * R[i];
+        int64_t c = 0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double dx = or_wrap(x[j] - x[i], L[0], dom->periodic[0]);
+            double dy = or_wrap(y[j] - y[i], L[1], dom->periodic[1]);
+            double dz = or_wrap(z[j] - z[i], L[2], dom->periodic[2]);
+            double d2 = dx * dx + dy * dy + dz * dz;
+            if (d2 < R2) {
+                if (col) col[row_ptr[i] + c] = (int32_t)j;
+                ++c;
+            }
+        }
+        cnt[i] = c;
+    }
+    if (!col) {
+        row_ptr[0] = 0;
+        for (int64_t i = 0; i < n; ++i) row_ptr[i + 1] = row_ptr[i] + cnt[i];
+    }
+    free(cnt);
+    return row_ptr[n];
+}
+
+/* One 3-D node system: the steps of node_weights_impl with the 3-D basis. */
+static int node_weights3(int k, int N, const double* dxh, const double* dyh, const double* dzh,
+                         const or_wopts* o, double* what, double* resid, int* iters) {
+    int p = or_p3_of_k(k);
+    unsigned list[6];
+    int nops = or_ops3(o->ops, list);
+    *resid = INFINITY;
+    *iters = 0;
+    for (int i = 0; i < nops * N; ++i) what[i] = 0.0;
+    if (k < 1 || p > OR_MAXP) return OR_ST_ORDER_TOO_LOW;
+    for (int d = 0; d < nops; ++d) {
+        double Ct[OR_MAXP];
+        int l;
+        if (or_target3(list[d], p, Ct, &l) != 0) return OR_ST_ORDER_TOO_LOW;
+    }
+    if (N < p) return OR_ST_TOO_FEW;
+    double* X = (double*)malloc(sizeof(double) * (size_t)N * p);
+    double* W = (double*)malloc(sizeof(double) * (size_t)N * p);
+    for (int j = 0; j < N; ++j) {
+        or_monomials3(k, dxh[j], dyh[j], dzh[j], X + (size_t)j * p);
+        or_abfs3(o->rbf, o->sigma, k, dxh[j], dyh[j], dzh[j], W + (size_t)j * p);
+    }
+    double M[OR_MAXP * OR_MAXP];
+    for (int m = 0; m < p; ++m)
+        for (int nn = 0; nn < p; ++nn) {
+            double acc = 0.0;
+            for (int j = 0; j < N; ++j) acc += X[(size_t)j * p + m] * W[(size_t)j * p + nn];
+            M[m * p + nn] = acc;
+        }
+    or_lu F;
+    if (or_lu_factor(&F, M, p) != 0) {
+        free(X);
+        free(W);
+        return OR_ST_SINGULAR;
+    }
+    double worst = 0.0;
+    int maxit = 0;
+    for (int d = 0; d < nops; ++d) {
+        double C[OR_MAXP], Psi[OR_MAXP], r[OR_MAXP];
+        int l;
+        or_target3(list[d], p, C, &l);
+        double* w = what + (size_t)d * N;
+        or_lu_solve(&F, C, Psi);
+        for (int j = 0; j < N; ++j) {
+            double acc = 0.0;
+            for (int nn = 0; nn < p; ++nn) acc += W[(size_t)j * p + nn] * Psi[nn];
+            w[j] = acc;
+        }
+        int it = 0;
+        double res = 0.0;
+        for (;;) {
+            res = 0.0;
+            for (int m = 0; m < p; ++m) {
+                double acc = 0.0;
+                for (int j = 0; j < N; ++j) acc += X[(size_t)j * p + m] * w[j];
+                r[m] = C[m] - acc;
+                res = fmax(res, fabs(r[m]));
+            }
+            if (!(res > o->tol_stop) || it >= o->max_iters) break;
+            double dPsi[OR_MAXP];
+            or_lu_solve(&F, r, dPsi);
+            for (int j = 0; j < N; ++j) {
+                double acc = 0.0;
+                for (int nn = 0; nn < p; ++nn) acc += W[(size_t)j * p + nn] * dPsi[nn];
+                w[j] += acc;
+            }
+            ++it;
+        }
+        if (!isfinite(res)) res = INFINITY;
+        worst = fmax(worst, res);
+        if (it > maxit) maxit = it;
+    }
+    free(X);
+    free(W);
+    *resid = worst;
+    *iters = maxit;
+    return (worst <= 1e-10) ? OR_ST_OK : OR_ST_NOT_CONVERGED;
+}
+
+int or_weights3(int64_t n, const double* x, const double* y, const double* z, const or_domain3* dom,
+                const double* R, int k, const int64_t* row_ptr, const int32_t* col, const or_wopts* o,
+                double* w, int8_t* status, double* resid, int8_t* iters) {
+    unsigned list[6];
+    int nops = or_ops3(o->ops, list);
+    int64_t nnz = row_ptr[n];
+    double L[3] = {dom->hi[0] - dom->lo[0], dom->hi[1] - dom->lo[1], dom->hi[2] - dom->lo[2]};
+    int nbad = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : nbad)
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t s = row_ptr[i];
+        int N = (int)(row_ptr[i + 1] - s);
+        double h = 0.5 * R[i];
+        size_t sz = sizeof(double) * (size_t)(N > 0 ? N : 1);
+        double *dxh = malloc(sz), *dyh = malloc(sz), *dzh = malloc(sz), *wh = malloc(sz * (size_t)nops);
+        for (int j = 0; j < N; ++j) {
+            int32_t c = col[s + j];
+            dxh[j] = or_wrap(x[c] - x[i], L[0], dom->periodic[0]) / h;
+            dyh[j] = or_wrap(y[c] - y[i], L[1], dom->periodic[1]) / h;
+            dzh[j] = or_wrap(z[c] - z[i], L[2], dom->periodic[2]) / h;
+        }
+        double res;
+        int it;
+        int st = node_weights3(k, N, dxh, dyh, dzh, o, wh, &res, &it);
+        for (int d = 0; d < nops; ++d) {
+            double hl = (list[d] == OR_OP_LAP) ? h * h : h;
+            for (int j = 0; j < N; ++j)
+                w[(size_t)d * nnz + s + j] =
+                    (st == OR_ST_OK || st == OR_ST_NOT_CONVERGED) ? wh[(size_t)d * N + j] / hl : 0.0;
+        }
+        status[i] = (int8_t)st;
+        resid[i] = res;
+        iters[i] = (int8_t)it;
+        if (st != OR_ST_OK) nbad++;
+        free(dxh);
+        free(dyh);
+        free(dzh);
+        free(wh);
+    }
+    return nbad;
+}
+
 int or_num_threads(void) { return omp_get_max_threads(); }
 void or_set_num_threads(int t) { omp_set_num_threads(t); }

@@ -14,6 +14,7 @@
  *   Sec. 4.2 (stability)         hyperviscosity target vectors
  *   Sec. 5.1                     classical RK4
  *   Sec. 5.3                     viscous Burgers' equation (RK4)
+ *   Sec. 3.1 (3-D p)             three-dimensional monomials, Hermite ABFs, weights
  * Readings where the paper is silent are listed at each function.
  */
 #ifndef LABFM_ORACLE_H
@@ -29,7 +30,8 @@ enum { OR_ABF_HERMITE = 0, OR_ABF_PAPER = 1, OR_ABF_PAPER_D1 = 2 };
 enum { OR_RBF_WENDLAND_C2 = 0, OR_RBF_CONE = 1, OR_RBF_QUADRATIC = 2,
        OR_RBF_WENDLAND_C6 = 3, OR_RBF_GAUSSIAN = 4 };
 /* operator bits, in output order */
-enum { OR_OP_DX = 1, OR_OP_DY = 2, OR_OP_LAP = 4, OR_OP_BIHARM = 8, OR_OP_TRIHARM = 16 };
+enum { OR_OP_DX = 1, OR_OP_DY = 2, OR_OP_LAP = 4, OR_OP_BIHARM = 8, OR_OP_TRIHARM = 16,
+       OR_OP_DZ = 32 /* 3-D only */ };
 /* per-node status */
 enum { OR_ST_OK = 0, OR_ST_NOT_CONVERGED = 1, OR_ST_SINGULAR = 2, OR_ST_TOO_FEW = 3,
        OR_ST_DEGENERATE = 4, OR_ST_ORDER_TOO_LOW = 5 };
@@ -38,6 +40,11 @@ typedef struct {
     double lo[2], hi[2];
     int periodic[2];
 } or_domain;
+
+typedef struct {
+    double lo[3], hi[3];
+    int periodic[3];
+} or_domain3;
 
 typedef struct {
     int family;        /* OR_ABF_* */
@@ -84,6 +91,17 @@ void or_burgers_rk4(int64_t n, const int64_t* row_ptr, const int32_t* col, const
                     const double* wy, const double* wl, const double* whv /* or NULL */, double nu,
                     double dt, int nsteps, double* u, double* v,
                     const int8_t* fixed /* optional [n]: Dirichlet nodes, not advanced */);
+/* three dimensions (HERMITE family; k <= 4) */
+int or_p3_of_k(int k);
+void or_index_table3(int k, int* ea, int* eb, int* ec);
+void or_monomials3(int k, double dx, double dy, double dz, double* X);
+int or_abfs3(int rbf, double sigma, int k, double dx, double dy, double dz, double* W);
+int64_t or_neighbours3_brute(int64_t n, const double* x, const double* y, const double* z,
+                             const or_domain3* dom, const double* R, int64_t* row_ptr, int32_t* col);
+int or_weights3(int64_t n, const double* x, const double* y, const double* z, const or_domain3* dom,
+                const double* R, int k, const int64_t* row_ptr, const int32_t* col, const or_wopts* o,
+                double* w /* [nops][nnz], operators in bit order */, int8_t* status, double* resid,
+                int8_t* iters);
 int or_num_threads(void);
 void or_set_num_threads(int t);
 

@@ -160,6 +160,10 @@ def config(name):
         # stream function pinned to 0 at node 0, Poisson tolerance 1e-10.
         "taylor_green": dict(abf=2, rbf=2, Re=100.0, h_over_dr=2.0, eps_paper=0.5, seed=17, tol=1e-10,
                              t_end=0.5, sides=(10, 20, 40, 80)),
+        # three dimensions: periodic n^3 lattices, eps 0.3, Hermite (sigma 1.5) x Wendland C2, one
+        # order per set, R0 by order for mean N about 14, 29, 51, 82 (k = 1..4; p = 3, 9, 19, 34),
+        # no growth
+        "c3d": dict(eps=0.3, seed=21, sigma=1.5, R_s={1: 1.5, 2: 1.9, 3: 2.3, 4: 2.7}, bench_side=64, bench_k=4),
         "burgers": dict(abf=2, rbf=2, h_over_dr=2.0, Re=100.0, eps_paper=0.2, seed=11, t_end=0.4,
                         sides=(21, 41, 81, 161), Re_hv=250.0, hv_coef=100.0, hv_eps_paper=0.5, hv_side=81),
     }
@@ -383,3 +387,43 @@ def taylor_green_vorticity(x, y, t, Re, H=1.0):
     """omega = (4 pi / H) sin(2 pi x / H) sin(2 pi y / H) exp(-8 pi^2 t / (Re H^2))."""
     return (4.0 * math.pi / H) * np.sin(2 * math.pi * x / H) * np.sin(2 * math.pi * y / H) * \
         math.exp(-8.0 * math.pi ** 2 * t / (Re * H * H))
+
+
+# ---------------------------------------------------------------------------
+# three dimensions
+
+
+def jittered_lattice3(n, eps=0.3, seed=0, periodic=True, morton=True):
+    """Cell-centred n^3 lattice on [0,1]^3, per-coordinate jitter U(-eps s, eps s),
+    nodes in Morton order of their cell.  Returns (x, y, z, s)."""
+    s = 1.0 / n
+    rng = np.random.default_rng(seed)
+    kk, jj, ii = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    ii, jj, kk = ii.ravel(), jj.ravel(), kk.ravel()
+    x = (ii + 0.5 + rng.uniform(-eps, eps, ii.size)) * s
+    y = (jj + 0.5 + rng.uniform(-eps, eps, ii.size)) * s
+    z = (kk + 0.5 + rng.uniform(-eps, eps, ii.size)) * s
+    if periodic:
+        x, y, z = np.mod(x, 1.0), np.mod(y, 1.0), np.mod(z, 1.0)
+    if morton:
+        key = np.zeros(ii.size, dtype=np.uint64)
+        for b in range(21):
+            for a, sh in ((ii, 0), (jj, 1), (kk, 2)):
+                key |= ((a.astype(np.uint64) >> np.uint64(b)) & np.uint64(1)) << np.uint64(3 * b + sh)
+        perm = np.argsort(key, kind="stable")
+        x, y, z = x[perm], y[perm], z[perm]
+    return np.ascontiguousarray(x), np.ascontiguousarray(y), np.ascontiguousarray(z), s
+
+
+def unit_domain3(periodic=True):
+    return {"lo": (0.0, 0.0, 0.0), "hi": (1.0, 1.0, 1.0), "periodic": (bool(periodic),) * 3}
+
+
+def trig_field3(x, y, z):
+    """f = sin(2 pi x) cos(2 pi y) sin(2 pi z + 1) and its x, y, z derivatives and Laplacian."""
+    tp = 2 * math.pi
+    sx, cx = np.sin(tp * x), np.cos(tp * x)
+    sy, cy = np.sin(tp * y), np.cos(tp * y)
+    sz, cz = np.sin(tp * z + 1.0), np.cos(tp * z + 1.0)
+    f = sx * cy * sz
+    return f, tp * cx * cy * sz, -tp * sx * sy * sz, tp * sx * cy * cz, -3 * tp * tp * f

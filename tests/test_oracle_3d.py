@@ -1,0 +1,129 @@
+"""Pins of the oracle's three-dimensional LABFM (Sec. 3.1 gives p in 3-D).
+
+* p(k) as printed; every (a, b, c) with 1 <= a + b + c <= k exactly once, by
+  total order.
+* X(d) are Taylor coefficients: P(d) - P(0) = sum_m X_m(d) D^m P(0) for a
+  random polynomial of degree k (sympy), which fixes the 1/(a! b! c!) factors.
+* Hermite ABFs against numpy's hermval product times the Wendland C2 factor.
+* Neighbour lists against scipy's periodic k-d tree.
+* Weights reproduce d/dx, d/dy, d/dz and the Laplacian of random polynomials
+  of degree <= k exactly, and converge at rates ~k (gradients), ~k-1
+  (Laplacian) on a smooth field.
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+import sympy as sp
+from scipy.spatial import cKDTree
+
+from conftest import golden_lines
+from paper_1912_06441_amd import workloads as WL
+
+
+def test_p3_matches_sec31(O):
+    for ln in golden_lines("p3_of_k_sec31.txt"):
+        k, p = map(int, ln.split())
+        assert O.p3_of_k(k) == p
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
+def test_index_table3(O, k):
+    idx = O.index_table3(k)
+    want = {t for t in itertools.product(range(k + 1), repeat=3) if 1 <= sum(t) <= k}
+    assert len(idx) == len(want) == O.p3_of_k(k) and set(idx) == want
+    assert [sum(t) for t in idx] == sorted(sum(t) for t in idx)
+
+
+def test_monomials3_are_taylor_coefficients(O):
+    k = 4
+    xs, ys, zs = sp.symbols("x y z")
+    rng = np.random.default_rng(2)
+    P = sum(sp.Rational(int(rng.integers(-9, 10)), int(rng.integers(1, 5))) * xs ** a * ys ** b * zs ** c
+            for a, b, c in itertools.product(range(k + 1), repeat=3) if a + b + c <= k)
+    idx = O.index_table3(k)
+    D = [float(sp.diff(P, xs, a, ys, b, zs, c).subs({xs: 0, ys: 0, zs: 0})) for a, b, c in idx]
+    for d in rng.uniform(-1.5, 1.5, (6, 3)):
+        X = O.monomials3(k, *d)
+        lhs = float(P.subs({xs: d[0], ys: d[1], zs: d[2]}) - P.subs({xs: 0, ys: 0, zs: 0}))
+        assert np.dot(X, D) == pytest.approx(lhs, rel=1e-12, abs=1e-12)
+
+
+def test_hermite_abfs3(O):
+    from numpy.polynomial import hermite as H
+
+    k = 4
+    idx = O.index_table3(k)
+    for d in np.random.default_rng(3).uniform(-1.2, 1.2, (5, 3)):
+        for sigma in (1.0, 1.5):
+            W = O.abfs3(k, *d, sigma=sigma)
+            q = np.linalg.norm(d)
+            phi = (1 - q / 2) ** 4 * (1 + 2 * q) if q < 2 else 0.0
+            for m, (a, b, c) in enumerate(idx):
+                hv = [H.hermval(sigma * t, np.eye(e + 1)[e]) for t, e in zip(d, (a, b, c))]
+                assert W[m] == pytest.approx(hv[0] * hv[1] * hv[2] * phi, rel=1e-12, abs=1e-12)
+
+
+@pytest.mark.parametrize("periodic", [True, False])
+def test_neighbours3_against_kdtree(O, periodic):
+    x, y, z, s = WL.jittered_lattice3(10, eps=0.3, seed=4, periodic=periodic)
+    R = 2.1 * s
+    rp, col = O.neighbours3(x, y, z, WL.unit_domain3(periodic), R)
+    pts = np.c_[x, y, z]
+    tree = cKDTree(pts, boxsize=1.0 if periodic else None)
+    for i in range(x.size):
+        got = col[rp[i]:rp[i + 1]]
+        assert np.all(np.diff(got) > 0)
+        want = sorted(j for j in tree.query_ball_point(pts[i], R * (1 - 1e-12)) if j != i)
+        near = sorted(j for j in tree.query_ball_point(pts[i], R * (1 + 1e-12)) if j != i)
+        assert set(want) <= set(got.tolist()) <= set(near)
+
+
+@pytest.mark.parametrize("k", [2, 3, 4])
+def test_weights3_reproduce_polynomials(O, k):
+    cfg = WL.config("c3d")
+    x, y, z, s = WL.jittered_lattice3(8, eps=0.3, seed=5, periodic=False)
+    dom = WL.unit_domain3(False)
+    R = cfg["R_s"][k] * s
+    rp, col = O.neighbours3(x, y, z, dom, R)
+    w, st, res, _ = O.weights3(x, y, z, dom, R, k, rp, col, sigma=cfg["sigma"])
+    ok = st == O.ST_OK
+    assert ok.mean() > 0.5 and res[ok].max() <= 1e-10  # walls: some one-sided stencils have N < p
+    rng = np.random.default_rng(k)
+    terms = [(a, b, c, rng.normal()) for a, b, c in itertools.product(range(k + 1), repeat=3) if a + b + c <= k]
+
+    def P(x, y, z, da=0, db=0, dc=0):
+        out = np.zeros_like(x)
+        for a, b, c, co in terms:
+            if a < da or b < db or c < dc:
+                continue
+            f = co * math.perm(a, da) * math.perm(b, db) * math.perm(c, dc)
+            out += f * x ** (a - da) * y ** (b - db) * z ** (c - dc)
+        return out
+
+    f = P(x, y, z)
+    exact = [P(x, y, z, 1, 0, 0), P(x, y, z, 0, 1, 0),
+             P(x, y, z, 2, 0, 0) + P(x, y, z, 0, 2, 0) + P(x, y, z, 0, 0, 2), P(x, y, z, 0, 0, 1)]
+    for d in range(4):
+        got = O.apply(rp, col, w[d], f)
+        scale = np.abs(exact[d]).max() + 1.0
+        assert np.abs(got - exact[d])[ok].max() <= 1e-8 * scale * (1 / s) ** (2 if d == 2 else 1), d
+
+
+@pytest.mark.parametrize("k,rg,rl", [(2, 1.7, 0.9), (3, 2.6, 1.6), (4, 3.5, 2.4)])
+def test_weights3_convergence(O, k, rg, rl):
+    cfg = WL.config("c3d")
+    errs = []
+    for n in (12, 24):
+        x, y, z, s = WL.jittered_lattice3(n, eps=cfg["eps"], seed=cfg["seed"], periodic=True)
+        dom = WL.unit_domain3(True)
+        R = cfg["R_s"][k] * s
+        rp, col = O.neighbours3(x, y, z, dom, R)
+        w, st, _, _ = O.weights3(x, y, z, dom, R, k, rp, col, sigma=cfg["sigma"])
+        assert np.all(st == O.ST_OK)
+        f, fx, fy, fz, lap = WL.trig_field3(x, y, z)
+        errs.append([np.linalg.norm(O.apply(rp, col, w[d], f) - ref) / np.linalg.norm(ref)
+                     for d, ref in enumerate((fx, fy, lap, fz))])
+    r = np.log2(np.array(errs[0]) / np.array(errs[1]))
+    assert min(r[0], r[1], r[3]) >= rg and r[2] >= rl, r
