@@ -71,7 +71,8 @@ enum {
     LABFM_OP_DY = 2,
     LABFM_OP_LAP = 4,
     LABFM_OP_BIHARM = 8,
-    LABFM_OP_TRIHARM = 16
+    LABFM_OP_TRIHARM = 16,
+    LABFM_OP_DZ = 32 /* three-dimensional calls only */
 };
 
 /* Precision of the weight computation.
@@ -366,6 +367,38 @@ typedef struct {
  * be NULL).  Argument errors return LABFM_EINVAL before any launch. */
 labfm_err labfm_ns_step(void* ctx, const labfm_ns_plan* plan, double* omega, double* psi, void* scratch, int nsteps,
                         int* solver_iters, int* all_converged, void* stream);
+
+/* ---- three dimensions ----------------------------------------------------
+ * Sec. 3.1 gives p in 3-D (3, 9, 19, 34 for k = 1..4).  Element m is (a, b, c)
+ * over total order n = 1..k with a = n..0, then b = n-a..0, c = n-a-b;
+ * X_m = x^a y^b z^c / (a! b! c!); ABFs of the HERMITE family only,
+ * H_a(s x) H_b(s y) H_c(s z) phi(|d|).  Operators: LABFM_OP_DX, _DY, _DZ
+ * (target e1, e2, e3) and _LAP (e4 + e7 + e9, needs k >= 2); weight sets are
+ * written in increasing bit order (dx, dy, lap, dz). */
+typedef struct {
+    double lo[3], hi[3];
+    int periodic[3];
+} labfm_domain3;
+
+/* 3-D neighbour sets: j != i with |r_j - r_i| < R[i] (squared distance summed
+ * x, y, z in that order, explicitly rounded), minimum image on periodic axes,
+ * ascending j; no radius growth.  Two passes as labfm_build_neighbours: col
+ * NULL fills row_ptr [n+1] and *nnz_host (synchronises stream); then the
+ * caller allocates col [nnz] and calls again to fill it.  x, y, z, R: device
+ * FP64 [n], nodes inside [lo, hi). */
+labfm_err labfm_build_neighbours3(void* ctx, const double* x, const double* y, const double* z, int64_t n,
+                                  const labfm_domain3* dom, const double* R, int64_t* row_ptr, int32_t* col,
+                                  int64_t* nnz_host, void* stream);
+
+/* 3-D weights of order k (1..4) for every node, FP64 (opt->prec must be
+ * LABFM_PREC_FP64 and opt->abf LABFM_ABF_HERMITE, else LABFM_EUNSUPPORTED);
+ * the refinement, status, residual and iteration outputs are those of
+ * labfm_weights.  w64: device [nops][nnz]; status int8 [n]; resid FP32 [n]
+ * and iters int8 [n] may be NULL.  Asynchronous. */
+labfm_err labfm_weights3(void* ctx, const double* x, const double* y, const double* z, int64_t n,
+                         const labfm_domain3* dom, const double* R, int k, const int64_t* row_ptr,
+                         const int32_t* col, int64_t nnz, const labfm_wopts* opt, double* w64, int8_t* status,
+                         float* resid, int8_t* iters, void* stream);
 
 /* ---- learned warm start: features, network, training --------------------
  * Features of every node i < n (Sec. 2 stencil, scaled offsets d = r_ji / h_i,

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "liblabfm.so")
 ABF_HERMITE, ABF_PAPER, ABF_PAPER_D1 = 0, 1, 2
 RBF_WENDLAND_C2, RBF_CONE, RBF_QUADRATIC, RBF_WENDLAND_C6, RBF_GAUSSIAN = 0, 1, 2, 3, 4
 OP_DX, OP_DY, OP_LAP, OP_BIHARM, OP_TRIHARM = 1, 2, 4, 8, 16
+OP_DZ = 32  # three-dimensional calls only
 PREC_FP64, PREC_MIXED, PREC_MLP = 0, 1, 2
 ST_OK, ST_NOT_CONVERGED, ST_SINGULAR, ST_TOO_FEW, ST_DEGENERATE, ST_ORDER_TOO_LOW, ST_TOO_MANY = range(7)
 MAX_NEIGHBOURS = 128
@@ -26,7 +27,7 @@ EXPORTED = sorted(["labfm_last_error", "labfm_create", "labfm_destroy", "labfm_b
                    "labfm_timing_read", "labfm_mlp_features", "labfm_mlp_forward", "labfm_mlp_cache_floats",
                    "labfm_mlp_backward", "labfm_mlp_moment_loss", "labfm_mlp_adam", "labfm_mlp_cast_bf16",
                    "labfm_weights_batched", "labfm_autotune_query", "labfm_burgers_step",
-                   "labfm_poisson_solve", "labfm_ns_step"])
+                   "labfm_poisson_solve", "labfm_ns_step", "labfm_build_neighbours3", "labfm_weights3"])
 MLP_MAX_LAYERS = 8
 
 
@@ -110,6 +111,9 @@ def load_library(path=LIB_PATH):
     L.labfm_weights.argtypes = [vp, vp, vp, i64, C.POINTER(Domain), vp, vp, vp, vp, i64, C.POINTER(WOpts), vp, vp,
                                 vp, vp, vp, vp]
     L.labfm_combine.argtypes = [vp, vp, C.c_int, C.POINTER(dp), i64, vp, vp, vp]
+    L.labfm_build_neighbours3.argtypes = [vp, vp, vp, vp, i64, C.POINTER(Domain3), vp, vp, vp, C.POINTER(i64), vp]
+    L.labfm_weights3.argtypes = [vp, vp, vp, vp, i64, C.POINTER(Domain3), vp, C.c_int, vp, vp, i64,
+                                 C.POINTER(WOpts), vp, vp, vp, vp, vp]
     L.labfm_apply_operator.argtypes = [vp, vp, vp, i64, i64, C.c_int, vp, C.c_int, vp, vp, vp]
     L.labfm_step.argtypes = [vp, C.POINTER(StepPlan), vp, vp, C.c_int, C.c_int, vp]
     L.labfm_burgers_step.argtypes = [vp, C.POINTER(BurgersPlan), vp, vp, vp, C.c_int, C.c_int, vp]
@@ -157,6 +161,19 @@ def _ptr(t):
 
 def _stream(torch):
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Domain3(C.Structure):
+    _fields_ = [("lo", C.c_double * 3), ("hi", C.c_double * 3), ("periodic", C.c_int * 3)]
+
+
+def make_domain3(domain):
+    d = Domain3()
+    for a in range(3):
+        d.lo[a] = float(domain["lo"][a])
+        d.hi[a] = float(domain["hi"][a])
+        d.periodic[a] = int(bool(domain["periodic"][a]))
+    return d
 
 
 def make_domain(domain):
@@ -222,6 +239,43 @@ class Context:
                                                0, 0, _ptr(row_ptr), _ptr(col), None, st),
                "labfm_build_neighbours(fill)")
         return row_ptr, col[:nnz.value]
+
+    # ------------------------------------------------------------------ three dimensions
+    def build_neighbours3(self, x, y, z, R, domain):
+        """3-D CSR neighbour lists (no growth).  Returns (row_ptr, col)."""
+        torch = self.torch
+        n = x.numel()
+        dom = make_domain3(domain)
+        row_ptr = torch.empty(n + 1, dtype=torch.int64, device=x.device)
+        nnz = C.c_int64(0)
+        st = _stream(torch)
+        _check(self.lib.labfm_build_neighbours3(self.h, _ptr(x), _ptr(y), _ptr(z), n, C.byref(dom), _ptr(R),
+                                                _ptr(row_ptr), None, C.byref(nnz), st), "labfm_build_neighbours3(count)")
+        col = torch.empty(max(nnz.value, 1), dtype=torch.int32, device=x.device)
+        _check(self.lib.labfm_build_neighbours3(self.h, _ptr(x), _ptr(y), _ptr(z), n, C.byref(dom), _ptr(R),
+                                                _ptr(row_ptr), _ptr(col), None, st), "labfm_build_neighbours3(fill)")
+        return row_ptr, col[:nnz.value]
+
+    def weights3(self, x, y, z, R, k, row_ptr, col, domain, ops=OP_DX | OP_DY | OP_LAP | OP_DZ,
+                 rbf=RBF_WENDLAND_C2, sigma=1.5, tol_stop=1e-13, tol_pass=1e-10, max_iters=5):
+        """3-D FP64 weights [nops, nnz] (operators in bit order: dx, dy, lap, dz),
+        status[n] int8, resid[n] f32, iters[n] int8."""
+        torch = self.torch
+        n = x.numel()
+        nnz = col.numel()
+        nop = bin(int(ops) & 63).count("1")
+        dev = x.device
+        w64 = torch.empty((nop, nnz), dtype=torch.float64, device=dev)
+        status = torch.empty(n, dtype=torch.int8, device=dev)
+        resid = torch.empty(n, dtype=torch.float32, device=dev)
+        iters = torch.empty(n, dtype=torch.int8, device=dev)
+        o = WOpts(ABF_HERMITE, int(rbf), float(sigma), int(ops), PREC_FP64, float(tol_stop), float(tol_pass),
+                  int(max_iters), None)
+        dom = make_domain3(domain)
+        _check(self.lib.labfm_weights3(self.h, _ptr(x), _ptr(y), _ptr(z), n, C.byref(dom), _ptr(R), int(k),
+                                       _ptr(row_ptr), _ptr(col), nnz, C.byref(o), _ptr(w64), _ptr(status),
+                                       _ptr(resid), _ptr(iters), _stream(torch)), "labfm_weights3")
+        return w64, status, resid, iters
 
     # ------------------------------------------------------------------ weights
     def weights(self, x, y, R, order, row_ptr, col, domain, ops=OP_DX | OP_DY | OP_LAP, abf=ABF_HERMITE,

@@ -53,6 +53,34 @@ GridSpec make_grid(const labfm_domain* d, int64_t n) {
     return g;
 }
 
+bool domain3_ok(const labfm_domain3* d) {
+    if (!d) return false;
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(d->lo[a]) || !std::isfinite(d->hi[a]) || !(d->hi[a] > d->lo[a])) return false;
+    return true;
+}
+
+Grid3 make_grid3(const labfm_domain3* d, int64_t n) {
+    // about four nodes per bucket; the search visits ceil(R/w) cells each way
+    Grid3 g{};
+    double vol = 1.0;
+    for (int a = 0; a < 3; ++a) {
+        g.L[a] = d->hi[a] - d->lo[a];
+        vol *= g.L[a];
+    }
+    const double per_len = std::cbrt((double)(n > 0 ? n : 1) / 4.0 / vol);
+    for (int a = 0; a < 3; ++a) {
+        long nc = lround(g.L[a] * per_len);
+        if (nc < 1) nc = 1;
+        if (nc > 256) nc = 256;
+        g.nc[a] = (int)nc;
+        g.lo[a] = d->lo[a];
+        g.w[a] = g.L[a] / g.nc[a];
+        g.per[a] = d->periodic[a] != 0;
+    }
+    return g;
+}
+
 int popcount5(unsigned ops) {
     int k = 0;
     for (int b = 0; b < 5; ++b) k += (ops >> b) & 1u;
@@ -192,6 +220,58 @@ labfm_err labfm_build_neighbours(void* ctx, const double* x, const double* y, in
     }
     if (n == 0) return LABFM_OK;
     return neighbours_fill(c, x, y, n, grid, R, row_ptr, col, st);
+}
+
+labfm_err labfm_build_neighbours3(void* ctx, const double* x, const double* y, const double* z, int64_t n,
+                                  const labfm_domain3* dom, const double* R, int64_t* row_ptr, int32_t* col,
+                                  int64_t* nnz_host, void* stream) {
+    if (!ctx) return fail(LABFM_EINVAL, "labfm_build_neighbours3: ctx is NULL");
+    if (n < 0 || n > INT32_MAX) return fail(LABFM_EINVAL, "labfm_build_neighbours3: n out of range [0, 2^31)");
+    if (!domain3_ok(dom)) return fail(LABFM_EINVAL, "labfm_build_neighbours3: bad domain");
+    if (n > 0 && (!x || !y || !z || !R || !row_ptr)) return fail(LABFM_EINVAL, "labfm_build_neighbours3: NULL array");
+    if (!col && !nnz_host) return fail(LABFM_EINVAL, "labfm_build_neighbours3: nnz_host is NULL on the count pass");
+    Context* c = (Context*)ctx;
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(LABFM_EHIP, "labfm_build_neighbours3: hipSetDevice failed");
+    hipStream_t st = (hipStream_t)stream;
+    Grid3 grid = make_grid3(dom, n);
+    if (!col) {
+        labfm_err e = n > 0 ? neighbours3_count(c, x, y, z, n, grid, R, row_ptr, st)
+                            : exclusive_scan_i64(c, nullptr, row_ptr, 0, st);
+        if (e != LABFM_OK) return e;
+        LABFM_HIP_CHECK(hipMemcpyAsync(nnz_host, row_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        LABFM_HIP_CHECK(hipStreamSynchronize(st));
+        return LABFM_OK;
+    }
+    if (n == 0) return LABFM_OK;
+    return neighbours3_fill(c, x, y, z, n, grid, R, row_ptr, col, st);
+}
+
+labfm_err labfm_weights3(void* ctx, const double* x, const double* y, const double* z, int64_t n,
+                         const labfm_domain3* dom, const double* R, int k, const int64_t* row_ptr,
+                         const int32_t* col, int64_t nnz, const labfm_wopts* opt, double* w64, int8_t* status,
+                         float* resid, int8_t* iters, void* stream) {
+    if (!ctx) return fail(LABFM_EINVAL, "labfm_weights3: ctx is NULL");
+    if (!opt) return fail(LABFM_EINVAL, "labfm_weights3: opt is NULL");
+    if (n < 0 || n > INT32_MAX || nnz < 0) return fail(LABFM_EINVAL, "labfm_weights3: n or nnz out of range");
+    if (!domain3_ok(dom)) return fail(LABFM_EINVAL, "labfm_weights3: bad domain");
+    if (k < 1 || k > 4) return fail(LABFM_EINVAL, "labfm_weights3: k must be 1..4");
+    const unsigned allowed = LABFM_OP_DX | LABFM_OP_DY | LABFM_OP_LAP | LABFM_OP_DZ;
+    if (opt->ops == 0 || (opt->ops & ~allowed))
+        return fail(LABFM_EINVAL, "labfm_weights3: ops must be a nonzero set of DX, DY, DZ, LAP");
+    if (opt->abf != LABFM_ABF_HERMITE) return fail(LABFM_EUNSUPPORTED, "labfm_weights3: only the HERMITE family");
+    if (opt->prec != LABFM_PREC_FP64) return fail(LABFM_EUNSUPPORTED, "labfm_weights3: only LABFM_PREC_FP64");
+    if (opt->rbf < 0 || opt->rbf > 4) return fail(LABFM_EINVAL, "labfm_weights3: bad rbf");
+    if (!(opt->sigma > 0.0) || !std::isfinite(opt->sigma)) return fail(LABFM_EINVAL, "labfm_weights3: sigma must be > 0");
+    if (opt->max_iters < 0 || opt->max_iters > 100) return fail(LABFM_EINVAL, "labfm_weights3: max_iters out of range");
+    if (!(opt->tol_stop >= 0.0) || !(opt->tol_pass >= 0.0)) return fail(LABFM_EINVAL, "labfm_weights3: bad tolerances");
+    if (n > 0 && (!x || !y || !z || !R || !row_ptr || !status || !w64 || (nnz > 0 && !col)))
+        return fail(LABFM_EINVAL, "labfm_weights3: NULL array");
+    Context* c = (Context*)ctx;
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(LABFM_EHIP, "labfm_weights3: hipSetDevice failed");
+    return weights3(c, x, y, z, n, make_grid3(dom, n), R, k, row_ptr, col, nnz, opt, w64, status, resid, iters,
+                    (hipStream_t)stream);
 }
 
 labfm_err labfm_weights(void* ctx, const double* x, const double* y, int64_t n, const labfm_domain* dom,

@@ -126,6 +126,22 @@ struct GridSpec {
 labfm_err neighbours_count(Context* c, const double* x, const double* y, int64_t n, const GridSpec& g,
                            double* R, const int8_t* order, int grow, int max_grow, int64_t* row_ptr,
                            hipStream_t st);
+// rows of a CSR structure sorted ascending in place (entries distinct)
+labfm_err sort_rows(const int64_t* row_ptr, int32_t* col, int64_t n, hipStream_t st);
+// three dimensions
+struct Grid3 {
+    int nc[3];
+    double lo[3], w[3], L[3];
+    int per[3];
+};
+labfm_err neighbours3_count(Context* c, const double* x, const double* y, const double* z, int64_t n,
+                            const Grid3& g, const double* R, int64_t* row_ptr, hipStream_t st);
+labfm_err neighbours3_fill(Context* c, const double* x, const double* y, const double* z, int64_t n,
+                           const Grid3& g, const double* R, const int64_t* row_ptr, int32_t* col, hipStream_t st);
+labfm_err weights3(Context* c, const double* x, const double* y, const double* z, int64_t n, const Grid3& g,
+                   const double* R, int k, const int64_t* row_ptr, const int32_t* col, int64_t nnz,
+                   const labfm_wopts* opt, double* w64, int8_t* status, float* resid, int8_t* iters,
+                   hipStream_t st);
 labfm_err neighbours_fill(Context* c, const double* x, const double* y, int64_t n, const GridSpec& g,
                           const double* R, const int64_t* row_ptr, int32_t* col, hipStream_t st);
 

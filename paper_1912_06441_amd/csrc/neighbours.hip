@@ -280,6 +280,14 @@ labfm_err exclusive_scan_i32(Context* c, const int32_t* in, int32_t* out, int64_
     return scan_impl<int32_t>(c, in, out, n, st);
 }
 
+labfm_err sort_rows(const int64_t* row_ptr, int32_t* col, int64_t n, hipStream_t st) {
+    if (n <= 0) return LABFM_OK;
+    unsigned ns = (unsigned)((n + SORT_WAVES - 1) / SORT_WAVES);
+    k_sort_rows<<<ns, 64 * SORT_WAVES, 0, st>>>(row_ptr, col, n);
+    LABFM_HIP_CHECK(hipGetLastError());
+    return LABFM_OK;
+}
+
 labfm_err neighbours_count(Context* c, const double* x, const double* y, int64_t n, const GridSpec& g,
                            double* R, const int8_t* order, int grow, int max_grow, int64_t* row_ptr,
                            hipStream_t st) {

@@ -1,0 +1,487 @@
+// weights3.hip -- per-node LABFM weights in three dimensions, FP64 (Sec. 3.1
+// of King, Lind & Nasar with the third coordinate: p = 3, 9, 19, 34 for
+// k = 1..4).  Element m is (a, b, c) over total order n = 1..k with a = n..0,
+// then b = n-a..0, c = n-a-b; X_m = x^a y^b z^c / (a! b! c!), ABFs of the
+// Hermite family H_a(s x) H_b(s y) H_c(s z) phi(|d|).  The node system is
+// built and solved as in the two-dimensional FP64 kernel: one wavefront per
+// node, M accumulated in registers from basis chunks in LDS, row/column
+// equilibration, partial-pivot LU in LDS, FP64 refinement on the moment
+// residual, unscaling by h^l.
+#include "weights_common.hpp"
+
+namespace labfm {
+
+namespace {
+
+using namespace wk;
+
+constexpr int K3MAX = 4;
+constexpr int p3_of_k(int k) {
+    int p = 0;
+    for (int m = 2; m <= k + 1; ++m) p += m * (m + 1) / 2;
+    return p;
+}
+constexpr int P3MAX = p3_of_k(K3MAX);  // 34
+
+struct Elem3Table {
+    int a[P3MAX], b[P3MAX], c[P3MAX];
+};
+constexpr Elem3Table make_elems3() {
+    Elem3Table t{};
+    int m = 0;
+    for (int n = 1; n <= K3MAX; ++n)
+        for (int a = n; a >= 0; --a)
+            for (int b = n - a; b >= 0; --b) {
+                t.a[m] = a;
+                t.b[m] = b;
+                t.c[m] = n - a - b;
+                ++m;
+            }
+    return t;
+}
+constexpr Elem3Table ELEM3 = make_elems3();
+
+template <int K>
+struct Basis3 {
+    double px[K + 1], py[K + 1], pz[K + 1];
+    double hx[K + 1], hy[K + 1], hz[K + 1];
+    double phi;
+};
+
+template <int K>
+__device__ inline void hermite_row(double t, double (&h)[K + 1]) {
+    h[0] = 1.0;
+    if (K >= 1) h[1] = 2.0 * t;
+#pragma unroll
+    for (int e = 1; e < K; ++e) h[e + 1] = 2.0 * t * h[e] - 2.0 * e * h[e - 1];
+}
+
+template <int K>
+__device__ inline void basis3_prepare(Basis3<K>& B, double dx, double dy, double dz, int rbf, double sigma) {
+    B.px[0] = B.py[0] = B.pz[0] = 1.0;
+#pragma unroll
+    for (int e = 1; e <= K; ++e) {
+        B.px[e] = B.px[e - 1] * dx;
+        B.py[e] = B.py[e - 1] * dy;
+        B.pz[e] = B.pz[e - 1] * dz;
+    }
+    hermite_row<K>(sigma * dx, B.hx);
+    hermite_row<K>(sigma * dy, B.hy);
+    hermite_row<K>(sigma * dz, B.hz);
+    double F[4];
+    rbf_eval(rbf, sqrt(dx * dx + dy * dy + dz * dz), F);
+    B.phi = F[0];
+}
+
+template <int K>
+__device__ inline double monomial3(const Basis3<K>& B, int m) {
+    const int a = ELEM3.a[m], b = ELEM3.b[m], c = ELEM3.c[m];
+    return B.px[a] * B.py[b] * B.pz[c] * (inv_fact(a) * inv_fact(b) * inv_fact(c));
+}
+
+template <int K>
+__device__ inline double abf3(const Basis3<K>& B, int m) {
+    return B.hx[ELEM3.a[m]] * B.hy[ELEM3.b[m]] * B.hz[ELEM3.c[m]] * B.phi;
+}
+
+// 3-D targets: d/dx e1, d/dy e2, d/dz e3, Laplacian e4 + e7 + e9 (1-based)
+__device__ inline double target3(unsigned op, int m) {
+    switch (op) {
+        case LABFM_OP_DX: return m == 0 ? 1.0 : 0.0;
+        case LABFM_OP_DY: return m == 1 ? 1.0 : 0.0;
+        case LABFM_OP_DZ: return m == 2 ? 1.0 : 0.0;
+        case LABFM_OP_LAP: return (m == 3 || m == 6 || m == 8) ? 1.0 : 0.0;
+    }
+    return 0.0;
+}
+
+struct W3Args {
+    const double *x, *y, *z, *R;
+    const int64_t* row_ptr;
+    const int32_t* col;
+    int64_t n, nnz;
+    double L[3];
+    int per[3];
+    int rbf;
+    double sigma, tol_stop, tol_pass;
+    int max_iters;
+    double* w64;
+    int8_t* status;
+    float* resid;
+    int8_t* iters;
+};
+
+template <int K>
+__global__ __launch_bounds__(64) void k_weights3(W3Args a, OpList ops) {
+    constexpr int P = p3_of_k(K);
+    constexpr int BS = (P + 7) / 8;
+    constexpr int PP = 8 * BS;
+    constexpr int LD = P + 1;
+    constexpr int JS = NMAX / 64;
+
+    __shared__ double sM[P * LD];
+    __shared__ double sChunk[2 * CH * PP];
+    __shared__ double sD[3][NMAX];
+    __shared__ double sWl[MAXOPS][NMAX];
+    __shared__ double sPsi[MAXOPS][PP];
+    __shared__ double sRs[P], sCs[P];
+    __shared__ int sPerm[P];
+
+    const int lane = threadIdx.x;
+    const int nops = ops.nops;
+
+    for (int64_t i = blockIdx.x; i < a.n; i += gridDim.x) {
+        const int64_t s0 = a.row_ptr[i];
+        const int N = (int)(a.row_ptr[i + 1] - s0);
+        const double h = 0.5 * a.R[i];
+        int status = LABFM_ST_OK;
+        double res = INFINITY;
+        int iters = 0;
+        for (int d = 0; d < nops; ++d)
+            if (ops.op[d] == LABFM_OP_LAP && K < 2) status = LABFM_ST_ORDER_TOO_LOW;
+        if (status == LABFM_ST_OK && N < P) status = LABFM_ST_TOO_FEW;
+        if (status == LABFM_ST_OK && N > NMAX) status = LABFM_ST_TOO_MANY;
+
+        double dxr[JS], dyr[JS], dzr[JS];
+        if (status == LABFM_ST_OK) {
+            const double xi = a.x[i], yi = a.y[i], zi = a.z[i];
+#pragma unroll
+            for (int js = 0; js < JS; ++js) {
+                const int q = lane + 64 * js;
+                dxr[js] = dyr[js] = dzr[js] = 0.0;
+                if (q < N) {
+                    const int32_t j = a.col[s0 + q];
+                    dxr[js] = min_image(a.x[j] - xi, a.L[0], a.per[0]) / h;
+                    dyr[js] = min_image(a.y[j] - yi, a.L[1], a.per[1]) / h;
+                    dzr[js] = min_image(a.z[j] - zi, a.L[2], a.per[2]) / h;
+                    sD[0][q] = dxr[js];
+                    sD[1][q] = dyr[js];
+                    sD[2][q] = dzr[js];
+                }
+            }
+        }
+        __syncthreads();
+
+        if (status == LABFM_ST_OK) {
+            // ---- assembly: M = sum_j X(d_j) W(d_j)^T, register-blocked
+            const int lr = lane / 8, lc = lane % 8;
+            double acc[BS][BS];
+#pragma unroll
+            for (int r = 0; r < BS; ++r)
+#pragma unroll
+                for (int c = 0; c < BS; ++c) acc[r][c] = 0.0;
+            double* sX = sChunk;
+            double* sW = sChunk + CH * PP;
+            for (int j0 = 0; j0 < N; j0 += CH) {
+                if (lane < 2 * CH) {
+                    const int jj = lane % CH;
+                    const int j = j0 + jj;
+                    double* dst = (lane < CH ? sX : sW) + jj * PP;
+                    if (j < N) {
+                        Basis3<K> B;
+                        basis3_prepare<K>(B, sD[0][j], sD[1][j], sD[2][j], a.rbf, a.sigma);
+                        if (lane < CH) {
+#pragma unroll
+                            for (int m = 0; m < P; ++m) dst[m] = monomial3<K>(B, m);
+                        } else {
+#pragma unroll
+                            for (int m = 0; m < P; ++m) dst[m] = abf3<K>(B, m);
+                        }
+                    } else {
+#pragma unroll
+                        for (int m = 0; m < P; ++m) dst[m] = 0.0;
+                    }
+#pragma unroll
+                    for (int m = P; m < PP; ++m) dst[m] = 0.0;
+                }
+                __syncthreads();
+                const int jmax = min(CH, N - j0);
+                for (int jj = 0; jj < jmax; ++jj) {
+                    double xv[BS], wv[BS];
+#pragma unroll
+                    for (int r = 0; r < BS; ++r) xv[r] = sX[jj * PP + lr * BS + r];
+#pragma unroll
+                    for (int c = 0; c < BS; ++c) wv[c] = sW[jj * PP + lc * BS + c];
+#pragma unroll
+                    for (int r = 0; r < BS; ++r)
+#pragma unroll
+                        for (int c = 0; c < BS; ++c) acc[r][c] = fma(xv[r], wv[c], acc[r][c]);
+                }
+                __syncthreads();
+            }
+#pragma unroll
+            for (int r = 0; r < BS; ++r)
+#pragma unroll
+                for (int c = 0; c < BS; ++c) {
+                    const int m = lr * BS + r, nn = lc * BS + c;
+                    if (m < P && nn < P) sM[m * LD + nn] = acc[r][c];
+                }
+            __syncthreads();
+
+            // ---- equilibration: rows, then columns
+            bool sing = false;
+            if (lane < P) {
+                double mx = 0.0;
+                for (int c = 0; c < P; ++c) mx = fmax(mx, fabs(sM[lane * LD + c]));
+                if (!(mx > 0.0) || !isfinite(mx)) sing = true;
+                const double rs = 1.0 / mx;
+                sRs[lane] = rs;
+                for (int c = 0; c < P; ++c) sM[lane * LD + c] *= rs;
+            }
+            __syncthreads();
+            if (lane < P) {
+                double mx = 0.0;
+                for (int r = 0; r < P; ++r) mx = fmax(mx, fabs(sM[r * LD + lane]));
+                if (!(mx > 0.0) || !isfinite(mx)) sing = true;
+                const double cs = 1.0 / mx;
+                sCs[lane] = cs;
+                for (int r = 0; r < P; ++r) sM[r * LD + lane] *= cs;
+            }
+            __syncthreads();
+            if (__any(sing)) status = LABFM_ST_SINGULAR;
+
+            // ---- LU with partial pivoting (ties: lowest row)
+            int perm = lane;
+            if (status == LABFM_ST_OK) {
+                for (int kk = 0; kk < P; ++kk) {
+                    const double v = (lane >= kk && lane < P) ? fabs(sM[lane * LD + kk]) : -1.0;
+                    const double vmax = wave_max_double(v);
+                    const unsigned long long hit = __ballot(v == vmax);
+                    if (!(vmax > 0.0) || !isfinite(vmax) || hit == 0ull) {
+                        status = LABFM_ST_SINGULAR;
+                        break;
+                    }
+                    const int pr = __ffsll((long long)hit) - 1;
+                    if (pr != kk) {
+                        if (lane < P) {
+                            const double u = sM[kk * LD + lane];
+                            sM[kk * LD + lane] = sM[pr * LD + lane];
+                            sM[pr * LD + lane] = u;
+                        }
+                        const int pk = __builtin_amdgcn_readlane(perm, kk), pp = __builtin_amdgcn_readlane(perm, pr);
+                        if (lane == kk) perm = pp;
+                        if (lane == pr) perm = pk;
+                    }
+                    __syncthreads();
+                    if (lane >= kk && lane < P) {
+                        const double inv = 1.0 / sM[kk * LD + kk];
+                        const double u = sM[kk * LD + lane];
+                        const bool own = lane == kk;
+                        for (int r = kk + 1; r < P; ++r) {
+                            const double m = sM[r * LD + kk] * inv;
+                            const double a0 = sM[r * LD + lane];
+                            sM[r * LD + lane] = own ? m : fma(-m, u, a0);
+                        }
+                    }
+                    __syncthreads();
+                }
+            }
+            if (lane < P) sPerm[lane] = perm;
+            __syncthreads();
+
+            if (status == LABFM_ST_OK) {
+                // ---- initial solve: lane m holds C^d[m]
+                double b[MAXOPS];
+#pragma unroll
+                for (int d = 0; d < MAXOPS; ++d) b[d] = (d < nops) ? target3(ops.op[d], lane) : 0.0;
+                lu_solve<P, LD>(sM, sRs, sCs, sPerm, b, nops);
+                if (lane < P)
+#pragma unroll
+                    for (int d = 0; d < MAXOPS; ++d)
+                        if (d < nops) sPsi[d][lane] = b[d];
+                __syncthreads();
+
+                // ---- w_j = W(d_j) . Psi
+                double wreg[JS][MAXOPS];
+#pragma unroll
+                for (int js = 0; js < JS; ++js) {
+                    const int q = lane + 64 * js;
+#pragma unroll
+                    for (int d = 0; d < MAXOPS; ++d) wreg[js][d] = 0.0;
+                    if (q < N) {
+                        Basis3<K> B;
+                        basis3_prepare<K>(B, dxr[js], dyr[js], dzr[js], a.rbf, a.sigma);
+#pragma unroll
+                        for (int m = 0; m < P; ++m) {
+                            const double wm = abf3<K>(B, m);
+#pragma unroll
+                            for (int d = 0; d < MAXOPS; ++d)
+                                if (d < nops) wreg[js][d] = fma(wm, sPsi[d][m], wreg[js][d]);
+                        }
+#pragma unroll
+                        for (int d = 0; d < MAXOPS; ++d)
+                            if (d < nops) sWl[d][q] = wreg[js][d];
+                    }
+                }
+                __syncthreads();
+
+                // ---- refinement on the moment residual (FP64)
+                const int ma = lane < P ? ELEM3.a[lane] : 0;
+                const int mb = lane < P ? ELEM3.b[lane] : 0;
+                const int mc = lane < P ? ELEM3.c[lane] : 0;
+                const double mf = lane < P ? inv_fact(ma) * inv_fact(mb) * inv_fact(mc) : 0.0;
+                for (;;) {
+                    double r[MAXOPS];
+#pragma unroll
+                    for (int d = 0; d < MAXOPS; ++d) r[d] = 0.0;
+                    if (lane < P) {
+                        double accr[MAXOPS];
+#pragma unroll
+                        for (int d = 0; d < MAXOPS; ++d) accr[d] = 0.0;
+                        for (int q = 0; q < N; ++q) {
+                            const double dx = sD[0][q], dy = sD[1][q], dz = sD[2][q];
+                            double xm = mf;
+#pragma unroll
+                            for (int e = 0; e < K; ++e) {
+                                xm *= (e < ma) ? dx : 1.0;
+                                xm *= (e < mb) ? dy : 1.0;
+                                xm *= (e < mc) ? dz : 1.0;
+                            }
+#pragma unroll
+                            for (int d = 0; d < MAXOPS; ++d)
+                                if (d < nops) accr[d] = fma(xm, sWl[d][q], accr[d]);
+                        }
+#pragma unroll
+                        for (int d = 0; d < MAXOPS; ++d)
+                            if (d < nops) r[d] = target3(ops.op[d], lane) - accr[d];
+                    }
+                    double rm = 0.0;
+#pragma unroll
+                    for (int d = 0; d < MAXOPS; ++d) {
+                        const double ar = fabs(r[d]);
+                        rm = (ar > rm || ar != ar) ? ar : rm;
+                    }
+                    if (!isfinite(rm)) rm = INFINITY;
+                    res = wave_max(rm);
+                    if (!(res > a.tol_stop) || iters >= a.max_iters) break;
+                    lu_solve<P, LD>(sM, sRs, sCs, sPerm, r, nops);
+                    __syncthreads();
+                    if (lane < P)
+#pragma unroll
+                        for (int d = 0; d < MAXOPS; ++d)
+                            if (d < nops) sPsi[d][lane] = r[d];
+                    __syncthreads();
+#pragma unroll
+                    for (int js = 0; js < JS; ++js) {
+                        const int q = lane + 64 * js;
+                        if (q < N) {
+                            Basis3<K> B;
+                            basis3_prepare<K>(B, dxr[js], dyr[js], dzr[js], a.rbf, a.sigma);
+                            double dw[MAXOPS];
+#pragma unroll
+                            for (int d = 0; d < MAXOPS; ++d) dw[d] = 0.0;
+#pragma unroll
+                            for (int m = 0; m < P; ++m) {
+                                const double wm = abf3<K>(B, m);
+#pragma unroll
+                                for (int d = 0; d < MAXOPS; ++d)
+                                    if (d < nops) dw[d] = fma(wm, sPsi[d][m], dw[d]);
+                            }
+#pragma unroll
+                            for (int d = 0; d < MAXOPS; ++d)
+                                if (d < nops) {
+                                    wreg[js][d] += dw[d];
+                                    sWl[d][q] = wreg[js][d];
+                                }
+                        }
+                    }
+                    __syncthreads();
+                    ++iters;
+                }
+                if (!(res <= a.tol_pass)) status = LABFM_ST_NOT_CONVERGED;
+
+                // ---- unscale and store
+#pragma unroll
+                for (int d = 0; d < MAXOPS; ++d) {
+                    if (d >= nops) continue;
+                    const double hl = ops.op[d] == LABFM_OP_LAP ? h * h : h;
+#pragma unroll
+                    for (int js = 0; js < JS; ++js) {
+                        const int q = lane + 64 * js;
+                        if (q < N) a.w64[(int64_t)d * a.nnz + s0 + q] = wreg[js][d] / hl;
+                    }
+                }
+            }
+        }
+        const bool failed = !(status == LABFM_ST_OK || status == LABFM_ST_NOT_CONVERGED);
+        if (failed) {
+            for (int d = 0; d < nops; ++d)
+                for (int q = lane; q < N; q += 64) a.w64[(int64_t)d * a.nnz + s0 + q] = 0.0;
+            res = INFINITY;
+            iters = 0;
+        }
+        if (lane == 0) {
+            a.status[i] = (int8_t)status;
+            if (a.resid) a.resid[i] = (float)res;
+            if (a.iters) a.iters[i] = (int8_t)iters;
+        }
+        __syncthreads();
+    }
+}
+
+template <int K>
+int grid3_for() {
+    static int g = 0;
+    if (g == 0) {
+        int dev = 0, ncu = 0, per = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_weights3<K>, 64, 0);
+        if (ncu <= 0) ncu = 256;
+        if (per <= 0) per = 1;
+        g = ncu * per;
+    }
+    return g;
+}
+
+template <int K>
+void launch3(const W3Args& a, const OpList& ops, hipStream_t st) {
+    k_weights3<K><<<grid3_for<K>(), 64, 0, st>>>(a, ops);
+}
+
+}  // namespace
+
+labfm_err weights3(Context* c, const double* x, const double* y, const double* z, int64_t n, const Grid3& g,
+                   const double* R, int k, const int64_t* row_ptr, const int32_t* col, int64_t nnz,
+                   const labfm_wopts* opt, double* w64, int8_t* status, float* resid, int8_t* iters,
+                   hipStream_t st) {
+    if (n == 0) return LABFM_OK;
+    W3Args a{};
+    a.x = x;
+    a.y = y;
+    a.z = z;
+    a.R = R;
+    a.row_ptr = row_ptr;
+    a.col = col;
+    a.n = n;
+    a.nnz = nnz;
+    for (int d = 0; d < 3; ++d) {
+        a.L[d] = g.L[d];
+        a.per[d] = g.per[d];
+    }
+    a.rbf = opt->rbf;
+    a.sigma = opt->sigma;
+    a.tol_stop = opt->tol_stop;
+    a.tol_pass = opt->tol_pass;
+    a.max_iters = opt->max_iters;
+    a.w64 = w64;
+    a.status = status;
+    a.resid = resid;
+    a.iters = iters;
+    OpList ops{};
+    ops.nops = 0;
+    for (int b = 0; b < 6; ++b)
+        if (opt->ops & (1u << b)) ops.op[ops.nops++] = 1u << b;
+    static const char* names[K3MAX + 1] = {"", "weights3d_k1", "weights3d_k2", "weights3d_k3", "weights3d_k4"};
+    KernelTimer timer(c, names[k], st);
+    switch (k) {
+        case 1: launch3<1>(a, ops, st); break;
+        case 2: launch3<2>(a, ops, st); break;
+        case 3: launch3<3>(a, ops, st); break;
+        default: launch3<4>(a, ops, st); break;
+    }
+    LABFM_HIP_CHECK(hipGetLastError());
+    return LABFM_OK;
+}
+
+}  // namespace labfm

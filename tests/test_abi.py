@@ -75,6 +75,9 @@ def test_new_entry_points_validate_before_device_work(lib):
         "labfm_burgers_step": (None, None, None, None, None, 1, 1, None),
         "labfm_poisson_solve": (None, None, None, None, None, None, None, None, None),
         "labfm_ns_step": (None, None, None, None, None, 1, None, None, None),
+        "labfm_build_neighbours3": (None, None, None, None, c.c_int64(0), None, None, None, None, None, None),
+        "labfm_weights3": (None, None, None, None, c.c_int64(0), None, None, 4, None, None, c.c_int64(0), None,
+                           None, None, None, None, None),
     }
     for name, args in calls.items():
         fn = getattr(lib, name)
