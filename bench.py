@@ -92,6 +92,7 @@ def main():
     ap.add_argument("--no-burgers", action="store_true", help="skip the Burgers step measurement")
     ap.add_argument("--no-poisson", action="store_true", help="skip the Poisson solve measurement")
     ap.add_argument("--no-ns", action="store_true", help="skip the Taylor-Green Navier-Stokes measurement")
+    ap.add_argument("--no-3d", action="store_true", help="skip the three-dimensional weights measurement")
     ap.add_argument("--burgers-steps", type=int, default=200)
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-set batched weights measurement")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -229,6 +230,8 @@ def main():
         rec["poisson_1024"] = run_poisson(ctx, torch, np, L, WL)
     if not args.no_ns:
         rec["taylor_green_256"] = run_ns(ctx, torch, np, L, WL)
+    if not args.no_3d:
+        rec["weights3d_64"] = run_weights3d(ctx, torch, np, L, WL)
     if not args.no_batch:
         rec["batch_c3"] = run_batch(ctx, torch, np, L, WL, reps=3)
     rec["mlp_bf16"] = run_mlp(ctx, torch, L, WL)
@@ -440,6 +443,43 @@ def run_ns(ctx, torch, np, L, WL, side=256, k=6, nsteps=10):
     return {"nodes": n, "nnz": col.numel(), "order": k, "steps": nsteps, "ms_per_rk4_step": (t1 - t0) * 1e3 / nsteps,
             "bicgstab_iterations_per_solve": it / (4.0 * nsteps), "all_solves_converged": ok, "L2_error": err,
             "weights_all_ok": bool((st == 0).all().item())}
+
+
+def run_weights3d(ctx, torch, np, L, WL, reps=3):
+    """Three-dimensional FP64 weights {dx, dy, lap, dz} of order 4 (p = 34) on a
+    64^3 periodic lattice: neighbours, then weight sets per second."""
+    dev = torch.device("cuda:0")
+    cfg = WL.config("c3d")
+    side, k = cfg["bench_side"], cfg["bench_k"]
+    x_np, y_np, z_np, s = WL.jittered_lattice3(side, eps=cfg["eps"], seed=cfg["seed"], periodic=True)
+    n = x_np.size
+    x, y, z = (torch.from_numpy(a).to(dev) for a in (x_np, y_np, z_np))
+    R = torch.full((n,), cfg["R_s"][k] * s, dtype=torch.float64, device=dev)
+    dom = WL.unit_domain3(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rp, col = ctx.build_neighbours3(x, y, z, R, dom)
+    torch.cuda.synchronize()
+    t_neigh = (time.perf_counter() - t0) * 1e3
+    ctx.weights3(x, y, z, R, k, rp, col, dom, sigma=cfg["sigma"])  # warm-up
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    for _ in range(reps):
+        w, st, res, it = ctx.weights3(x, y, z, R, k, rp, col, dom, sigma=cfg["sigma"])
+    torch.cuda.synchronize()
+    ctx.timing(False)
+    kw = ctx.timing_read("weights3d")
+    ctx.timing_read(None)
+    ms = kw[1] / max(kw[0], 1)
+    st_np = st.cpu().numpy()
+    N = np.diff(rp.cpu().numpy()).astype(np.float64)
+    its = it.cpu().numpy().astype(np.float64)
+    p, nd = 34, 4
+    flops = float((2 * N * p * p + 2 * p ** 3 / 3 + (1 + its) * (2 * nd * p * p + 4 * N * p * nd)).sum())
+    return {"nodes": n, "nnz": col.numel(), "order": k, "p": p, "mean_N": float(N.mean()), "ms": ms,
+            "neighbours_ms": t_neigh, "weight_sets_per_s": int((st_np == 0).sum()) / (ms / 1e3),
+            "nodes_passing_1e-10": int((st_np == 0).sum()), "max_moment_residual": float(res.max()),
+            "fp64_tflops": flops / (ms / 1e3) / 1e12, "frac_of_fp64_peak": flops / (ms / 1e3) / PEAK_FP64}
 
 
 def run_mlp(ctx, torch, L, WL, B=1 << 20, reps=5):

@@ -263,11 +263,28 @@ __global__ __launch_bounds__(64) void k_weights3(W3Args a, OpList ops) {
                         if (lane == pr) perm = pk;
                     }
                     __syncthreads();
+                    // one pass: lane c > kk updates column c of the trailing rows, lane kk
+                    // stores the multipliers (every lane reads M[r][kk] before lane kk
+                    // overwrites it; rows in groups of eight, loads issued before stores)
                     if (lane >= kk && lane < P) {
                         const double inv = 1.0 / sM[kk * LD + kk];
                         const double u = sM[kk * LD + lane];
                         const bool own = lane == kk;
-                        for (int r = kk + 1; r < P; ++r) {
+                        int r = kk + 1;
+                        for (; r + 8 <= P; r += 8) {
+                            double l[8], a8[8];
+#pragma unroll
+                            for (int e = 0; e < 8; ++e) {
+                                l[e] = sM[(r + e) * LD + kk];
+                                a8[e] = sM[(r + e) * LD + lane];
+                            }
+#pragma unroll
+                            for (int e = 0; e < 8; ++e) {
+                                const double m = l[e] * inv;
+                                sM[(r + e) * LD + lane] = own ? m : fma(-m, u, a8[e]);
+                            }
+                        }
+                        for (; r < P; ++r) {
                             const double m = sM[r * LD + kk] * inv;
                             const double a0 = sM[r * LD + lane];
                             sM[r * LD + lane] = own ? m : fma(-m, u, a0);
