@@ -397,7 +397,8 @@ def test_step_fp32_vs_fp64_oracle(env, adv_ops, offset):
 
 
 # --------------------------------------------------------------------------- mixed precision
-@pytest.mark.parametrize("case", ["c1", "order8_96", "order6_periodic_5ops", "paper_quadratic_k4"])
+@pytest.mark.parametrize("case", ["c1", "order8_96", "order6_periodic_5ops", "paper_quadratic_k4",
+                                  "paper_d1_quadratic_k4", "paper_d1_quadratic_k6"])
 def test_weights_mixed_parity(env, case):
     """FP32 matrix-core assembly + FP32 LU + FP64 refinement: the refined weights
     are the FP64 system's solution, so the gate is the FP64 path's (moment
@@ -416,6 +417,11 @@ def test_weights_mixed_parity(env, case):
         x, y, s = WL.jittered_lattice(40, eps=0.3, seed=3, periodic=True)
         R, order, dom = np.full(x.size, 4.0 * s), np.full(x.size, 6, np.int8), WL.unit_domain(True)
         kw = dict(ops=1 | 2 | 4 | 8 | 16)
+    elif case.startswith("paper_d1"):
+        k = int(case[-1])
+        x, y, s = WL.jittered_lattice(40, eps=WL.paper_jitter(0.5), seed=8, periodic=True)
+        R, order, dom = np.full(x.size, 4.0 * s), np.full(x.size, k, np.int8), WL.unit_domain(True)
+        kw = dict(family=2, rbf=2)
     else:
         x, y, s = WL.jittered_lattice(40, eps=0.3, seed=6, periodic=True)
         R, order, dom = np.full(x.size, 3.2 * s), np.full(x.size, 4, np.int8), WL.unit_domain(True)
