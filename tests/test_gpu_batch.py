@@ -130,3 +130,56 @@ def test_batched_fp64_equals_single_set(env, batch):
         assert np.array_equal(o[2].cpu().numpy(), st.cpu().numpy())
         assert np.array_equal(o[4].cpu().numpy(), it.cpu().numpy())
         assert np.array_equal(st.cpu().numpy(), S["st_or"])
+
+
+def test_batched_full_64_sets(env):
+    """The benchmark's batch at full size (64 sets, 3.49 M nodes, orders 2-8,
+    mixed precision with autotuned routes, one graph launch) against the oracle
+    set by set: statuses equal except where both residuals sit within a factor
+    of three of the 1e-10 gate (rounding order decides those); every GPU node
+    with status OK at the gate; weight parity <= 1e-10 on a 2,000-row sample
+    of every set (at most one row per 10,000 above, none above 1e-8)."""
+    torch = env["torch"]
+    O = env["O"]
+    L = env["L"]
+    cfg = WL.config("c3")
+    sets = WL.batch_sets(cfg)
+    dev = []
+    for S in sets:
+        xt, yt = _dev(env, S["x"]), _dev(env, S["y"])
+        Rt, ot = _dev(env, S["R"].copy()), _dev(env, S["order"])
+        rpg, colg = env["ctx"].build_neighbours(xt, yt, Rt, ot, S["domain"])
+        dev.append(dict(x=xt, y=yt, R=Rt, order=ot, row_ptr=rpg, col=colg, domain=S["domain"]))
+    outs = env["ctx"].weights_batched(dev, prec=L.PREC_MIXED, use_graph=True)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(1)
+    n_total = borderline = 0
+    worst = 0.0
+    above = 0
+    sampled = 0
+    for S, D, o in zip(sets, dev, outs):
+        rp, col, R = O.neighbours(S["x"], S["y"], S["domain"], S["R"], S["order"], grow=True)
+        assert np.array_equal(D["row_ptr"].cpu().numpy(), rp) and np.array_equal(D["col"].cpu().numpy(), col)
+        w_o, st_o, res_o, _ = O.weights(S["x"], S["y"], S["domain"], R, S["order"], rp, col)
+        st = o[2].cpu().numpy()
+        res = o[3].cpu().numpy().astype(np.float64)
+        diff = st != st_o
+        near = (res > 1e-10 / 3) & (res < 3e-10) & (res_o > 1e-10 / 3) & (res_o < 3e-10)
+        assert np.all(near[diff]), np.nonzero(diff & ~near)
+        borderline += int(diff.sum())
+        assert np.all(res[st == 0] <= 1e-10)
+        n = st.size
+        n_total += n
+        rows = rng.choice(n, min(2000, n), replace=False)
+        w = o[0].cpu().numpy()
+        for i in rows:
+            if st[i] != 0 or st_o[i] != 0:
+                continue
+            s, e = rp[i], rp[i + 1]
+            par = max(np.abs(w[d, s:e] - w_o[d, s:e]).max() / np.abs(w_o[d, s:e]).max() for d in range(3))
+            worst = max(worst, par)
+            above += par > 1e-10
+            sampled += 1
+    _say("  full batch: %d nodes, %d borderline status differences, sampled parity max %.2e (%d of %d above 1e-10)" %
+         (n_total, borderline, worst, above, sampled))
+    assert above <= max(1, sampled // 10000) and worst <= 1e-8
