@@ -38,7 +38,7 @@ typedef enum {
     LABFM_EINVAL = -1,      /* bad argument (see labfm_last_error)          */
     LABFM_ENOMEM = -2,      /* library scratch allocation failed            */
     LABFM_EHIP = -3,        /* a HIP runtime call failed                    */
-    LABFM_EUNSUPPORTED = -4 /* valid request this build does not implement  */
+    LABFM_EUNSUPPORTED = -4 /* valid request the library does not implement */
 } labfm_err;
 
 /* ABF family.  HERMITE: W_m(d) = H_a(sigma d_x) H_b(sigma d_y) phi(|d|)
