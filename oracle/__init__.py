@@ -77,7 +77,7 @@ def lib():
         L.or_combine.argtypes = [C.c_int64, C.c_int, dp, dp, dp]
         L.or_rk4.argtypes = [C.c_int64, i64, i32, dp, dp, C.c_double, C.c_double, C.c_int, dp, i8]
         L.or_burgers_rk4.argtypes = [C.c_int64, i64, i32, dp, dp, dp, dp, C.c_double, C.c_double, C.c_int, dp, dp,
-                                     i8]
+                                     i8, dp]
         L.or_num_threads.restype = C.c_int
         L.or_set_num_threads.argtypes = [C.c_int]
         _lib = L
@@ -279,9 +279,13 @@ def rk4(row_ptr, col, w_lin, w_bh, gamma, dt, nsteps, u0, fixed=None):
     return u
 
 
-def burgers_rk4(row_ptr, col, wx, wy, wl, whv, nu, dt, nsteps, u0, v0, fixed=None):
+def burgers_rk4(row_ptr, col, wx, wy, wl, whv, nu, dt, nsteps, u0, v0, fixed=None, boundary=None, t0=0.0):
     """Classical RK4 on the viscous Burgers' equation (Sec. 5.3):
-    du/dt = -(u d/dx + v d/dy) u + nu lap u + L_hv u, the same for v; returns (u, v)."""
+    du/dt = -(u d/dx + v d/dy) u + nu lap u + L_hv u, the same for v; returns (u, v).
+
+    Nodes with fixed != 0 hold their values, or, with boundary(t) -> (du/dt,
+    dv/dt) (arrays over all nodes), follow those derivatives: stage q of the
+    step from t takes them at t + c_q dt, c = (0, 1/2, 1/2, 1)."""
     row_ptr = np.ascontiguousarray(row_ptr, np.int64)
     col = np.ascontiguousarray(col, np.int32)
     ws = [np.ascontiguousarray(a, np.float64) for a in (wx, wy, wl)]
@@ -293,9 +297,21 @@ def burgers_rk4(row_ptr, col, wx, wy, wl, whv, nu, dt, nsteps, u0, v0, fixed=Non
         fixed = np.ascontiguousarray(fixed, np.int8)
         fx = _p(fixed, C.c_int8)
     n = row_ptr.size - 1
-    lib().or_burgers_rk4(n, _p(row_ptr, C.c_int64), _p(col, C.c_int32), _p(ws[0], C.c_double),
-                         _p(ws[1], C.c_double), _p(ws[2], C.c_double), None if hv is None else _p(hv, C.c_double),
-                         float(nu), float(dt), int(nsteps), _p(u, C.c_double), _p(v, C.c_double), fx)
+    args = (n, _p(row_ptr, C.c_int64), _p(col, C.c_int32), _p(ws[0], C.c_double), _p(ws[1], C.c_double),
+            _p(ws[2], C.c_double), None if hv is None else _p(hv, C.c_double), float(nu), float(dt))
+    if boundary is None:
+        lib().or_burgers_rk4(*args, int(nsteps), _p(u, C.c_double), _p(v, C.c_double), fx, None)
+        return u, v
+    if fixed is None:
+        raise ValueError("burgers_rk4: boundary derivatives need a fixed mask")
+    dfix = np.zeros((2, 4, n), np.float64)
+    for s in range(int(nsteps)):
+        t = t0 + s * dt
+        for q, c in enumerate((0.0, 0.5, 0.5, 1.0)):
+            du, dv = boundary(t + c * dt)
+            dfix[0, q] = du
+            dfix[1, q] = dv
+        lib().or_burgers_rk4(*args, 1, _p(u, C.c_double), _p(v, C.c_double), fx, _p(dfix, C.c_double))
     return u, v
 
 

@@ -853,7 +853,10 @@ void or_rk4(int64_t n, const int64_t* row_ptr, const int32_t* col, const double*
  *   dv/dt = -(u L^x(v) + v L^y(v)) + nu L^L(v) + L^hv(v),
  * nu = 1/Re, L^hv an optional hyperviscosity operator whose coefficient is
  * part of its weights (Sec. 4.2), each L by eq. (general_do).  Classical RK4
- * (Sec. 5.1); nodes with fixed[i] != 0 keep their values. */
+ * (Sec. 5.1); nodes with fixed[i] != 0 take, at RK4 stage q, the derivatives
+ * dfix[q * n + i] (for u) and dfix[(4 + q) * n + i] (for v) in place of the
+ * right-hand side: the time derivative of a prescribed boundary solution
+ * (Sec. 5.3, travelling wave), or zero when dfix is NULL (values held). */
 static void or_burgers_rhs(int64_t n, const int64_t* rp, const int32_t* col, const double* wx,
                            const double* wy, const double* wl, const double* whv, double nu,
                            const double* u, const double* v, double* ku, double* kv, double* t) {
@@ -877,7 +880,7 @@ static void or_burgers_rhs(int64_t n, const int64_t* rp, const int32_t* col, con
 
 void or_burgers_rk4(int64_t n, const int64_t* row_ptr, const int32_t* col, const double* wx,
                     const double* wy, const double* wl, const double* whv, double nu, double dt,
-                    int nsteps, double* u, double* v, const int8_t* fixed) {
+                    int nsteps, double* u, double* v, const int8_t* fixed, const double* dfix) {
     size_t sz = sizeof(double) * (size_t)(n > 0 ? n : 1);
     double *ku[4], *kv[4];
     for (int q = 0; q < 4; ++q) { ku[q] = malloc(sz); kv[q] = malloc(sz); }
@@ -895,8 +898,16 @@ void or_burgers_rk4(int64_t n, const int64_t* row_ptr, const int32_t* col, const
                 vq = vs;
             }
             or_burgers_rhs(n, row_ptr, col, wx, wy, wl, whv, nu, uq, vq, ku[q], kv[q], t);
-            or_pin(n, fixed, ku[q]);
-            or_pin(n, fixed, kv[q]);
+            if (fixed && dfix) {
+                for (int64_t i = 0; i < n; ++i)
+                    if (fixed[i]) {
+                        ku[q][i] = dfix[(size_t)q * n + i];
+                        kv[q][i] = dfix[(size_t)(4 + q) * n + i];
+                    }
+            } else {
+                or_pin(n, fixed, ku[q]);
+                or_pin(n, fixed, kv[q]);
+            }
         }
         for (int64_t i = 0; i < n; ++i) {
             u[i] = u[i] + dt / 6.0 * (ku[0][i] + 2.0 * ku[1][i] + 2.0 * ku[2][i] + ku[3][i]);

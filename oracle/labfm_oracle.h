@@ -90,7 +90,8 @@ void or_rk4(int64_t n, const int64_t* row_ptr, const int32_t* col, const double*
 void or_burgers_rk4(int64_t n, const int64_t* row_ptr, const int32_t* col, const double* wx,
                     const double* wy, const double* wl, const double* whv /* or NULL */, double nu,
                     double dt, int nsteps, double* u, double* v,
-                    const int8_t* fixed /* optional [n]: Dirichlet nodes, not advanced */);
+                    const int8_t* fixed /* optional [n]: Dirichlet nodes */,
+                    const double* dfix /* optional [2][4][n]: their stage derivatives, else 0 */);
 /* three dimensions (HERMITE family; k <= 4) */
 int or_p3_of_k(int k);
 void or_index_table3(int k, int* ea, int* eb, int* ec);

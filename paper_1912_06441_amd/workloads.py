@@ -165,7 +165,8 @@ def config(name):
         # no growth
         "c3d": dict(eps=0.3, seed=21, sigma=1.5, R_s={1: 1.5, 2: 1.9, 3: 2.3, 4: 2.7}, bench_side=64, bench_k=4),
         "burgers": dict(abf=2, rbf=2, h_over_dr=2.0, Re=100.0, eps_paper=0.2, seed=11, t_end=0.4,
-                        sides=(21, 41, 81, 161), Re_hv=250.0, hv_coef=100.0, hv_eps_paper=0.5, hv_side=81),
+                        sides=(21, 41, 81, 161), Re_hv=250.0, hv_coef=100.0, hv_eps_paper=0.5, hv_side=81,
+                        wave_ghost=6, wave_seed=13, wave_eps_paper=0.2),
     }
     return dict(cfgs[name])
 
@@ -348,6 +349,53 @@ def burgers_cole_hopf(x, t, Re, H=1.0, nterms=30):
     num = (np.sin(ang) * (n * An * E)).sum(axis=1)
     den = A0 + (np.cos(ang) * (An * E)).sum(axis=1)
     return (4.0 * math.pi / (H * Re) * num / den).reshape(x.shape)
+
+
+def burgers_wave_nodes(M, ghost=6, eps_over_dr=0.2, seed=13, morton=True):
+    """Node set of the travelling-wave case (Sec. 5.3): a cell-centred M x M
+    lattice on [0,1]^2 (dr = 1/M) continued `ghost` layers outward on every
+    side, per-coordinate jitter of the paper's noise level.  Returns
+    (x, y, dr, fixed, domain): fixed = 1 on the nodes whose lattice cell lies
+    outside the unit square (the analytic solution is prescribed there), and a
+    non-periodic domain box that holds every node."""
+    dr = 1.0 / M
+    n1 = M + 2 * ghost
+    rng = np.random.default_rng(seed)
+    jj, ii = np.meshgrid(np.arange(n1), np.arange(n1), indexing="ij")
+    ii = ii.ravel()
+    jj = jj.ravel()
+    eps = paper_jitter(eps_over_dr)
+    x = (ii - ghost + 0.5 + rng.uniform(-eps, eps, ii.size)) * dr
+    y = (jj - ghost + 0.5 + rng.uniform(-eps, eps, ii.size)) * dr
+    fixed = ((ii < ghost) | (ii >= ghost + M) | (jj < ghost) | (jj >= ghost + M)).astype(np.int8)
+    if morton:
+        perm = np.argsort(_morton_key(ii, jj), kind="stable")
+        x, y, fixed = x[perm], y[perm], fixed[perm]
+    lo = -ghost * dr
+    hi = 1.0 + ghost * dr
+    dom = {"lo": (lo, lo), "hi": (hi, hi), "periodic": (False, False)}
+    return np.ascontiguousarray(x), np.ascontiguousarray(y), dr, np.ascontiguousarray(fixed), dom
+
+
+def _wave_arg(x, y, t, Re):
+    return Re * (-t - 4.0 * np.asarray(x, np.float64) + 4.0 * np.asarray(y, np.float64)) / 32.0
+
+
+def burgers_wave(x, y, t, Re):
+    """Travelling-wave solution of Burgers' equation (Sec. 5.3):
+    u = 3/4 - g, v = 3/4 + g with g = 1 / (4 (1 + e^z)), z = Re (-t - 4x + 4y) / 32,
+    evaluated as g = (1 - tanh(z/2)) / 8."""
+    g = (1.0 - np.tanh(0.5 * _wave_arg(x, y, t, Re))) / 8.0
+    return 0.75 - g, 0.75 + g
+
+
+def burgers_wave_dt(x, y, t, Re):
+    """Time derivatives of burgers_wave: dg/dt = (Re / 128) e^z / (1 + e^z)^2,
+    so du/dt = -dg/dt and dv/dt = dg/dt (e^z / (1 + e^z)^2 evaluated as
+    e^-|z| / (1 + e^-|z|)^2)."""
+    e = np.exp(-np.abs(_wave_arg(x, y, t, Re)))
+    d = (Re / 128.0) * e / (1.0 + e) ** 2
+    return -d, d
 
 
 def burgers_dt(h, umax, Re):

@@ -9,6 +9,13 @@ solution it is measured against.
   solver is the linear RK4 on nu * lap.
 * Periodic sawtooth (Re = 100, eps/dr = 0.2, h/dr = 2): the error against the
   exact solution falls with resolution at k = 4 and 6; v stays exactly zero.
+* Travelling wave (Sec. 5.3): the exact (u, v) and its time derivative satisfy
+  Burgers' equation by finite differences; nodes outside the unit square
+  follow the exact time derivative (constant derivatives are integrated
+  exactly, the exact wave to RK4 quadrature accuracy); at Re = 10, k = 6 on a
+  10 x 10 node set the relative error at t = 1 is below 1e-8, as the paper
+  states; at Re = 100 the error falls at order about k (k = 2, 4), inside the
+  paper's band [k - 1/2, k + 1/2] on the finer pair.
 """
 import math
 
@@ -115,3 +122,82 @@ def _sawtooth_error(O, k, side):
 def test_periodic_sawtooth_converges(O, k, e81):
     e41, e81_ = _sawtooth_error(O, k, 41), _sawtooth_error(O, k, 81)
     assert e81_ < e81 and e41 / e81_ > 8.0, (e41, e81_)
+
+
+def test_travelling_wave_solves_burgers():
+    """u_t + u u_x + v u_y = (u_xx + u_yy) / Re and the same for v, by central
+    differences, at points across the front; burgers_wave_dt equals the
+    difference quotient in t."""
+    rng = np.random.default_rng(3)
+    Re = 100.0
+    x = rng.uniform(0.0, 1.0, 40)
+    y = x + rng.uniform(-0.05, 0.05, 40)  # near the front 4x - 4y + t = 0
+    t = 0.3
+    e = 1e-4
+    U = lambda xx, yy, tt: WL.burgers_wave(xx, yy, tt, Re)
+    u, v = U(x, y, t)
+    for c, (f, ft) in enumerate(((u, WL.burgers_wave_dt(x, y, t, Re)[0]), (v, WL.burgers_wave_dt(x, y, t, Re)[1]))):
+        fx = (U(x + e, y, t)[c] - U(x - e, y, t)[c]) / (2 * e)
+        fy = (U(x, y + e, t)[c] - U(x, y - e, t)[c]) / (2 * e)
+        fxx = (U(x + e, y, t)[c] - 2 * f + U(x - e, y, t)[c]) / (e * e)
+        fyy = (U(x, y + e, t)[c] - 2 * f + U(x, y - e, t)[c]) / (e * e)
+        fdt = (U(x, y, t + e)[c] - U(x, y, t - e)[c]) / (2 * e)
+        scale = np.abs(fdt).max() + np.abs(u * fx).max()
+        assert np.abs(fdt - ft).max() < 1e-6 * scale
+        assert np.abs(ft + u * fx + v * fy - (fxx + fyy) / Re).max() < 1e-4 * scale
+
+
+def _wave(O, M, k, Re, t_end):
+    cfg = WL.config("burgers")
+    x, y, dr, fx, dom = WL.burgers_wave_nodes(M, ghost=cfg["wave_ghost"], eps_over_dr=cfg["wave_eps_paper"],
+                                              seed=cfg["wave_seed"])
+    h = cfg["h_over_dr"] * dr
+    order = np.full(x.size, k, np.int8)
+    rp, col, R = O.neighbours(x, y, dom, np.full(x.size, 2 * h), order, grow=True)
+    w, st, _, _ = O.weights(x, y, dom, R, order, rp, col, ops=7, family=cfg["abf"], rbf=cfg["rbf"])
+    inner = fx == 0
+    assert np.all(st[inner] == 0)
+    nsteps = int(math.ceil(t_end / WL.burgers_dt(h, 1.0, Re) - 1e-9))
+    dt = t_end / nsteps
+    u0, v0 = WL.burgers_wave(x, y, 0.0, Re)
+    u, v = O.burgers_rk4(rp, col, w[0], w[1], w[2], None, 1.0 / Re, dt, nsteps, u0, v0, fixed=fx,
+                         boundary=lambda t: WL.burgers_wave_dt(x, y, t, Re))
+    ue, ve = WL.burgers_wave(x, y, t_end, Re)
+    err = math.sqrt((np.sum((u - ue)[inner] ** 2) + np.sum((v - ve)[inner] ** 2)) /
+                    (np.sum(ue[inner] ** 2) + np.sum(ve[inner] ** 2)))
+    gst = fx == 1
+    bnd = max(np.abs(u - ue)[gst].max(), np.abs(v - ve)[gst].max())
+    return err, bnd
+
+
+def test_boundary_derivatives_are_integrated(O):
+    """Fixed nodes given a constant derivative c move by exactly c t; with the
+    exact wave's derivative they end within RK4 quadrature error of the exact
+    values."""
+    rp, col, w = _random_system(12, seed=7)[:3]
+    n = rp.size - 1
+    fixed = np.zeros(n, np.int8)
+    fixed[[1, 4, 9]] = 1
+    u0 = np.linspace(0.1, 1.2, n)
+    v0 = np.linspace(-0.5, 0.4, n)
+    u, v = O.burgers_rk4(rp, col, w[0], w[1], w[2], None, 0.01, 0.01, 25, u0, v0, fixed=fixed,
+                         boundary=lambda t: (np.full(n, 0.5), np.full(n, -2.0)))
+    assert np.abs(u[fixed == 1] - (u0[fixed == 1] + 0.125)).max() < 1e-14
+    assert np.abs(v[fixed == 1] - (v0[fixed == 1] - 0.5)).max() < 1e-14
+    _, bnd = _wave(O, 20, 4, 100.0, 0.2)
+    assert bnd < 1e-8
+
+
+def test_travelling_wave_paper_value(O):
+    """Sec. 5.3: at Re = 10, k = 6, on the coarsest (10 x 10) set the relative
+    error at t = 1 is below 1e-8."""
+    err, _ = _wave(O, 10, 6, 10.0, 1.0)
+    assert err < 1e-8, err
+
+
+@pytest.mark.parametrize("k", [2, 4])
+def test_travelling_wave_converges_at_order_k(O, k):
+    errs = [_wave(O, M, k, 100.0, 0.2)[0] for M in (20, 40, 80)]
+    rates = [math.log(errs[i] / errs[i + 1]) / math.log(2.0) for i in range(2)]
+    assert k - 0.5 <= rates[1] <= k + 0.5, (errs, rates)
+    assert rates[0] >= k - 0.75, (errs, rates)
