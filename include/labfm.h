@@ -285,7 +285,12 @@ labfm_err labfm_step(void* ctx, const labfm_step_plan* plan, void* u, void* scra
  * nu = 1/Re; L^hv is an optional hyperviscosity operator (Sec. 4.2, e.g.
  * -100 h^4 nabla^4 or 8 h^6 nabla^6) whose coefficient the caller has folded
  * into w_hv (labfm_combine).  Dirichlet nodes (fixed[i] != 0) keep their
- * values, as in labfm_step. */
+ * values, as in labfm_step, or, when dfix is given, take at RK4 stage q the
+ * derivatives dfix[q n + i] (u) and dfix[(4 + q) n + i] (v) in place of the
+ * right-hand side: the time derivative of a prescribed solution, e.g. the
+ * analytic travelling wave on the nodes outside the domain (Sec. 5.3).  The
+ * caller rewrites dfix between steps (stage q of the step from t at
+ * t + c_q dt, c = 0, 1/2, 1/2, 1); a captured step reads it at replay. */
 typedef struct {
     const int64_t* row_ptr; /* device int64 [n+1]                   */
     const int32_t* col;     /* device int32 [nnz]                   */
@@ -298,6 +303,8 @@ typedef struct {
     double nu;              /* viscosity 1/Re                       */
     double dt;
     const int8_t* fixed;    /* device int8 [n] or NULL              */
+    const void* dfix;       /* device [2][4][n] of the plan's dtype, or NULL;
+                               needs fixed                           */
 } labfm_burgers_plan;
 
 /* Advance (u, v) (device [n] each, dtype of the plan) by nsteps RK4 steps.

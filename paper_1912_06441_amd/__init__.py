@@ -69,7 +69,8 @@ class NodeSetDesc(C.Structure):
 class BurgersPlan(C.Structure):
     _fields_ = [("row_ptr", C.c_void_p), ("col", C.c_void_p), ("n", C.c_int64), ("nnz", C.c_int64),
                 ("dtype", C.c_int), ("w_x", C.c_void_p), ("w_y", C.c_void_p), ("w_lap", C.c_void_p),
-                ("w_hv", C.c_void_p), ("nu", C.c_double), ("dt", C.c_double), ("fixed", C.c_void_p)]
+                ("w_hv", C.c_void_p), ("nu", C.c_double), ("dt", C.c_double), ("fixed", C.c_void_p),
+                ("dfix", C.c_void_p)]
 
 
 class PoissonPlan(C.Structure):
@@ -412,9 +413,11 @@ class Context:
         return u
 
     def burgers_step(self, row_ptr, col, w_x, w_y, w_lap, nu, dt, u, v, nsteps, w_hv=None, scratch=None,
-                     use_graph=True, fixed=None):
+                     use_graph=True, fixed=None, dfix=None):
         """Advance the velocity (u, v) in place by nsteps RK4 steps of the viscous
-        Burgers' equation du/dt = -(u d/dx + v d/dy) u + nu lap u + L_hv u (same for v)."""
+        Burgers' equation du/dt = -(u d/dx + v d/dy) u + nu lap u + L_hv u (same for v).
+        Nodes with fixed != 0 hold their values or, with dfix ([2, 4, n], the
+        dtype of u), take dfix[0, q] / dfix[1, q] as their stage-q derivatives."""
         torch = self.torch
         n = u.numel()
         if v.numel() != n or v.dtype != u.dtype:
@@ -424,9 +427,13 @@ class Context:
         dtype = 1 if u.dtype == torch.float64 else 0
         if fixed is not None and (fixed.dtype != torch.int8 or fixed.numel() != n or not fixed.is_contiguous()):
             raise ValueError("fixed must be a contiguous int8 tensor of n entries")
+        if dfix is not None and (dfix.dtype != u.dtype or dfix.numel() != 8 * n or not dfix.is_contiguous()
+                                 or fixed is None):
+            raise ValueError("dfix must be a contiguous [2, 4, n] tensor of u's dtype, with a fixed mask")
         plan = BurgersPlan(row_ptr.data_ptr(), col.data_ptr(), n, col.numel(), dtype, w_x.data_ptr(), w_y.data_ptr(),
                            w_lap.data_ptr(), w_hv.data_ptr() if w_hv is not None else None, float(nu), float(dt),
-                           fixed.data_ptr() if fixed is not None else None)
+                           fixed.data_ptr() if fixed is not None else None,
+                           dfix.data_ptr() if dfix is not None else None)
         _check(self.lib.labfm_burgers_step(self.h, C.byref(plan), _ptr(u), _ptr(v), _ptr(scratch), int(nsteps),
                                            int(bool(use_graph)), _stream(torch)), "labfm_burgers_step")
         return u, v

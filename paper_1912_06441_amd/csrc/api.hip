@@ -423,6 +423,8 @@ labfm_err labfm_burgers_step(void* ctx, const labfm_burgers_plan* plan, void* u,
         return fail(LABFM_EINVAL, "labfm_burgers_step: u, v and scratch must be distinct buffers");
     if (!std::isfinite(plan->dt) || !std::isfinite(plan->nu))
         return fail(LABFM_EINVAL, "labfm_burgers_step: dt/nu not finite");
+    if (plan->dfix && !plan->fixed)
+        return fail(LABFM_EINVAL, "labfm_burgers_step: dfix needs a fixed mask");
     Context* c = (Context*)ctx;
     DeviceGuard g(c->device);
     return burgers_launch(c, plan, u, v, scratch, nsteps, use_graph, (hipStream_t)stream);

@@ -3,7 +3,8 @@
 //   du/dt = -(u L^x(u) + v L^y(u)) + nu L^L(u) + L^hv(u)
 //   dv/dt = -(u L^x(v) + v L^y(v)) + nu L^L(v) + L^hv(v)
 // with nu = 1/Re and an optional hyperviscosity operator L^hv (Sec. 4.2) whose
-// coefficient is folded into its weights.  One pass per RK4 stage: each CSR
+// coefficient is folded into its weights; Dirichlet nodes hold their values or
+// follow imposed stage derivatives.  One pass per RK4 stage: each CSR
 // row reads its index stream and the 3 (or 4) weight streams once and gathers
 // both velocity components, so the nonlinear right-hand side and the stage
 // update of both fields come out of a single HBM-bound sweep.  One step is
@@ -20,8 +21,9 @@ using namespace rows;
 template <typename T, int NW>
 __global__ __launch_bounds__(256) void k_burgers_stage(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                                                        int64_t n, WPtrs<T, NW> w, const T* uin, const T* vin, T nu,
-                                                       T dt, int stage, const int8_t* __restrict__ fixed, T* u, T* v,
-                                                       T* accu, T* accv, T* uout, T* vout) {
+                                                       T dt, int stage, const int8_t* __restrict__ fixed,
+                                                       const T* __restrict__ dfix, T* u, T* v, T* accu, T* accv,
+                                                       T* uout, T* vout) {
     constexpr int G = Shape<T>::G, U = Shape<T>::U;
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t row = gid / G;
@@ -44,8 +46,8 @@ __global__ __launch_bounds__(256) void k_burgers_stage(const int64_t* __restrict
         ku += au[NW - 1];
         kv += av[NW - 1];
     }
-    rk4_update<T>(stage, ku, dt, row, fixed, u, accu, uout);
-    rk4_update<T>(stage, kv, dt, row, fixed, v, accv, vout);
+    rk4_update<T>(stage, ku, dt, row, fixed, u, accu, uout, dfix ? dfix + (int64_t)stage * n : nullptr);
+    rk4_update<T>(stage, kv, dt, row, fixed, v, accv, vout, dfix ? dfix + (int64_t)(4 + stage) * n : nullptr);
 }
 
 template <typename T>
@@ -68,11 +70,13 @@ labfm_err enqueue_burgers(const labfm_burgers_plan* p, T* u, T* v, T* scratch, h
         if (p->w_hv) {
             WPtrs<T, 4> w{{(const T*)p->w_x, (const T*)p->w_y, (const T*)p->w_lap, (const T*)p->w_hv}};
             k_burgers_stage<T, 4><<<nb, 256, 0, st>>>(p->row_ptr, p->col, n, w, uin[stage], vin[stage], nu, dt, stage,
-                                                      p->fixed, u, v, au, av, uout[stage], vout[stage]);
+                                                      p->fixed, (const T*)p->dfix, u, v, au, av, uout[stage],
+                                                      vout[stage]);
         } else {
             WPtrs<T, 3> w{{(const T*)p->w_x, (const T*)p->w_y, (const T*)p->w_lap}};
             k_burgers_stage<T, 3><<<nb, 256, 0, st>>>(p->row_ptr, p->col, n, w, uin[stage], vin[stage], nu, dt, stage,
-                                                      p->fixed, u, v, au, av, uout[stage], vout[stage]);
+                                                      p->fixed, (const T*)p->dfix, u, v, au, av, uout[stage],
+                                                      vout[stage]);
         }
     }
     LABFM_HIP_CHECK(hipGetLastError());
@@ -87,7 +91,7 @@ labfm_err enqueue_any(const labfm_burgers_plan* p, void* u, void* v, void* scrat
 bool same_plan(const labfm_burgers_plan& a, const labfm_burgers_plan& b) {
     return a.row_ptr == b.row_ptr && a.col == b.col && a.n == b.n && a.nnz == b.nnz && a.dtype == b.dtype &&
            a.w_x == b.w_x && a.w_y == b.w_y && a.w_lap == b.w_lap && a.w_hv == b.w_hv && a.nu == b.nu &&
-           a.dt == b.dt && a.fixed == b.fixed;
+           a.dt == b.dt && a.fixed == b.fixed && a.dfix == b.dfix;
 }
 
 }  // namespace

@@ -97,10 +97,12 @@ __device__ inline void row_sums2(const int32_t* __restrict__ col, int64_t s, int
     }
 }
 
-// stage update: k is the stage derivative at node i (zero on Dirichlet nodes)
+// stage update: k is the stage derivative at node i; on Dirichlet nodes it is
+// kfix[i] when an imposed derivative is given, else zero
 template <typename T>
-__device__ inline void rk4_update(int stage, T k, T dt, int64_t i, const int8_t* fixed, T* u, T* acc, T* us_out) {
-    if (fixed && fixed[i]) k = T(0);
+__device__ inline void rk4_update(int stage, T k, T dt, int64_t i, const int8_t* fixed, T* u, T* acc, T* us_out,
+                                  const T* kfix = nullptr) {
+    if (fixed && fixed[i]) k = kfix ? kfix[i] : T(0);
     const T ui = u[i];
     if (stage == 0) {
         acc[i] = k;
