@@ -16,6 +16,10 @@ solution it is measured against.
   10 x 10 node set the relative error at t = 1 is below 1e-8, as the paper
   states; at Re = 100 the error falls at order about k (k = 2, 4), inside the
   paper's band [k - 1/2, k + 1/2] on the finer pair.
+* Re = 250 (Sec. 5.3, k = 6, h/H = 2/81): the sixth-order hyperviscosity
+  operator's spectral radius puts the printed 8 h^6 far beyond the RK4 limit
+  at the eq. (tstep) step; without hyperviscosity the run blows up before
+  t = 0.5, with 0.02 h^6 nabla^6 it stays bounded near the Cole-Hopf solution.
 """
 import math
 
@@ -201,3 +205,37 @@ def test_travelling_wave_converges_at_order_k(O, k):
     rates = [math.log(errs[i] / errs[i + 1]) / math.log(2.0) for i in range(2)]
     assert k - 0.5 <= rates[1] <= k + 0.5, (errs, rates)
     assert rates[0] >= k - 0.75, (errs, rates)
+
+
+def test_re250_sixth_order_hyperviscosity(O):
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as sla
+
+    cfg = WL.config("burgers")
+    Re = cfg["Re_hv"]
+    x, y, s = WL.jittered_lattice(cfg["hv_side"], eps=WL.paper_jitter(cfg["hv_eps_paper"]), seed=cfg["seed"],
+                                  periodic=True)
+    dom = WL.unit_domain(True)
+    n = x.size
+    order = np.full(n, 6, np.int8)
+    rp, col, R = O.neighbours(x, y, dom, np.full(n, 2.0 * cfg["h_over_dr"] * s), order, grow=True)
+    w, st, _, _ = O.weights(x, y, dom, R, order, rp, col, family=cfg["abf"], rbf=cfg["rbf"], ops=1 | 2 | 4 | 16)
+    assert np.all(st == 0)
+    h = cfg["h_over_dr"] * s
+    dt = WL.burgers_dt(h, 1.0, Re)
+    A = sp.csr_matrix((w[3], (np.repeat(np.arange(n), np.diff(rp)), col)), shape=(n, n))
+    A = A - sp.diags(np.asarray(A.sum(axis=1)).ravel())
+    lam = sla.eigs(A * h ** 6, k=3, which="LM", return_eigenvectors=False)
+    rho = np.abs(lam).max()
+    assert np.all(lam.real < 0)                # dissipative with a positive coefficient
+    assert 8.0 * rho * dt > 2.8 > 0.02 * rho * dt   # RK4 reaches -2.785 on the real axis
+    u0 = np.sin(2 * math.pi * x)
+    nsteps = int(math.ceil(0.5 / dt))
+    ex = WL.burgers_cole_hopf(x, 0.5, Re)
+    out = {}
+    for label, whv in (("none", None), ("hv6", 0.02 * h ** 6 * w[3])):
+        u, _ = O.burgers_rk4(rp, col, w[0], w[1], w[2], whv, 1.0 / Re, 0.5 / nsteps, nsteps, u0, np.zeros(n))
+        out[label] = (np.abs(u).max() if np.all(np.isfinite(u)) else math.inf,
+                      np.linalg.norm(u - ex) / np.linalg.norm(ex) if np.all(np.isfinite(u)) else math.inf)
+    assert not out["none"][0] < 10.0
+    assert out["hv6"][0] < 1.2 and out["hv6"][1] < 0.15, out
