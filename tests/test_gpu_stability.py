@@ -1,4 +1,6 @@
-"""Stability of the Laplacian operators built by the GPU path (Sec. 4.2,
+"""Stability and critical stencil sizes through the GPU path.
+
+Sec. 4.2: stability of the Laplacian operators built by the GPU path (Sec. 4.2,
 Table noise_limits): on the 441-node periodic noisy lattices, with quadratic
 RBF and the PAPER_D1 family, neighbours and FP64 Laplacian weights come from
 the GPU; the eigenvalues of the global matrix A^L (dense, on the host) put
@@ -80,3 +82,36 @@ def test_noise_limits_through_gpu_weights(env, k, hdr, eps, stable):
         assert max(vals) < 1e-8, vals
     else:
         assert max(vals) > 1e-6, vals
+
+
+@pytest.mark.parametrize("k,crit", [(2, 0.75), (4, 1.15), (6, 1.6), (8, 2.1)])
+def test_critical_stencil_sizes_through_gpu(env, k, crit):
+    """Sec. 3.2 critical h/dr: 0.2 above the printed value every node of the
+    24 x 24 periodic noisy lattice (eps/dr = 0.5) gets weights at the gate
+    from the GPU path, 0.25 below it most nodes have fewer neighbours than p;
+    statuses equal the oracle's node for node, weights within 1e-10."""
+    O, torch = env["O"], env["torch"]
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    for hdr, above in ((crit + 0.2, True), (crit - 0.25, False)):
+        print("critical size k=%d h/dr=%.2f" % (k, hdr), flush=True)
+        x, y, s = WL.jittered_lattice(24, eps=WL.paper_jitter(0.5), seed=5, periodic=True)
+        dom = WL.unit_domain(True)
+        n = x.size
+        order = np.full(n, k, np.int8)
+        Rt = d(np.full(n, 2.0 * hdr * s))
+        rp, col = env["ctx"].build_neighbours(d(x), d(y), Rt, d(order), dom, grow=False)
+        w, _, st, _, _ = env["ctx"].weights(d(x), d(y), Rt, d(order), rp, col, dom, ops=7,
+                                            abf=O.ABF_PAPER_D1, rbf=O.RBF_QUADRATIC)
+        torch.cuda.synchronize()
+        rp, col, w, st = rp.cpu().numpy(), col.cpu().numpy(), w.cpu().numpy(), st.cpu().numpy()
+        rpo, colo, Ro = O.neighbours(x, y, dom, np.full(n, 2.0 * hdr * s), order, grow=False)
+        wo, sto, _, _ = O.weights(x, y, dom, Ro, order, rpo, colo, family=O.ABF_PAPER_D1, rbf=O.RBF_QUADRATIC, ops=7)
+        assert np.array_equal(rp, rpo) and np.array_equal(col, colo) and np.array_equal(st, sto)
+        if above:
+            assert np.all(st == O.ST_OK)
+        else:
+            assert (st == O.ST_TOO_FEW).mean() >= 0.5
+        for i in np.nonzero(st == O.ST_OK)[0]:
+            a, b = rp[i], rp[i + 1]
+            for dd in range(3):
+                assert np.abs(w[dd, a:b] - wo[dd, a:b]).max() <= 1e-10 * np.abs(wo[dd, a:b]).max()
