@@ -1,6 +1,6 @@
 """Stability and critical stencil sizes through the GPU path.
 
-Sec. 4.2: stability of the Laplacian operators built by the GPU path (Sec. 4.2,
+* Stability of the Laplacian operators built by the GPU path (Sec. 4.2,
 Table noise_limits): on the 441-node periodic noisy lattices, with quadratic
 RBF and the PAPER_D1 family, neighbours and FP64 Laplacian weights come from
 the GPU; the eigenvalues of the global matrix A^L (dense, on the host) put
@@ -9,6 +9,9 @@ weights do; the nodes with a usable operator are the oracle's (apart from
 residuals within 3x of the 1e-10 gate) and the weights agree within 1e-10
 per node (at most one node in a hundred above, on ill-conditioned stencils,
 none above 1e-8).
+* Critical stencil sizes (Sec. 3.2): 0.2 above each printed h/dr_crit every
+node passes the gate, 0.25 below most have fewer neighbours than p; statuses
+equal the oracle's node for node.
 """
 import math
 import sys
