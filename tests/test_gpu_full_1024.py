@@ -10,6 +10,8 @@ configuration bench.py times, against the oracle run at full size.
   the small-set test).
 * Burgers (FP32, Re = 100, the benchmark's step): two steps against the
   oracle's FP64 Burgers RK4, same bound.
+* The configured run: 1000 FP32 steps against 1000 FP64 oracle steps at
+  t_end, max |du| <= 1e-3 max |u| (measured 4.1e-7).
 """
 import sys
 
@@ -139,3 +141,36 @@ def test_full_poisson_solve(full):
     _say("  full Poisson: %d iterations, GPU residual %.2e, residual with the oracle's rows %.2e, L2 error %.2e" %
          (it, res, r, err))
     assert ok and r <= 1e-9 and err <= 1e-8
+
+
+def test_full_rk4_1000_steps(full):
+    """The configured run: 1000 FP32 RK4 steps of the advected, diffused and
+    hyperviscous Gaussian pulse on the GPU against 1000 FP64 steps of the
+    oracle at t_end; both against the free-space solution (periodic images)."""
+    f = full
+    torch, O, cfg, nd = f["torch"], f["O"], f["cfg"], f["nd"]
+    a, nu = cfg["a"], cfg["nu"]
+    _, wlin = f["ctx"].combine(f["w64"][:3], [-a[0], -a[1], nu], want64=False, want32=True)
+    wbh = f["w64"][3].to(torch.float32)
+    s = nd["s"]
+    h = 0.5 * cfg["R_s"] * s
+    dt = cfg["dt_s"] * s
+    gamma = cfg["beta"] * h ** 8 / dt
+    nsteps = cfg["nsteps"]
+    u0 = WL.gaussian_pulse(nd["x"], nd["y"])
+    u = torch.from_numpy(u0).cuda().to(torch.float32)
+    scratch = torch.empty(5 * u0.size, dtype=torch.float32, device="cuda")
+    f["ctx"].step(f["rp"], f["col"], wlin, wbh, gamma, dt, u, nsteps, scratch=scratch)
+    torch.cuda.synchronize()
+    _say("  oracle: %d FP64 RK4 steps at 1024^2" % nsteps)
+    wlin_o = O.combine(f["w_o"][:3], [-a[0], -a[1], nu])
+    ref = np.array(u0)
+    for _ in range(nsteps // 50):  # progress lines between legs
+        ref = O.rk4(f["rp_o"], f["col_o"], wlin_o, f["w_o"][3], gamma, dt, 50, ref)
+        _say("  ...")
+    g = u.double().cpu().numpy()
+    err = np.abs(g - ref).max() / np.abs(ref).max()
+    ex = WL.advected_gaussian(nd["x"], nd["y"], nsteps * dt, a, nu)
+    _say("  1000 FP32 steps vs FP64 oracle: %.2e; L2 vs free-space solution: gpu %.2e oracle %.2e" %
+         (err, np.linalg.norm(g - ex) / np.linalg.norm(ex), np.linalg.norm(ref - ex) / np.linalg.norm(ex)))
+    assert err <= 1e-3
