@@ -83,8 +83,8 @@ def run_cpu_baseline(nd, cfg):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--prec", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-rk4", action="store_true")
@@ -151,14 +151,19 @@ def main():
         step()
     torch.cuda.synchronize()
     ctx.timing(True)
+    # per-step events on the stream the library launches on (torch's current stream)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    ev[0].record()
+    for k in range(args.steps):
         rp, col = step()
+        ev[k + 1].record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ctx.timing(False)
     ms = (t1 - t0) * 1e3 / args.steps
+    step_ms = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)])
     # read the order-8 kernel separately, then every weights kernel
     k8 = ctx.timing_read("weights64_k8")
     kw_rest = ctx.timing_read("weights")
@@ -201,6 +206,8 @@ def main():
                                "R0 = 4.4 s + growth, Hermite x Wendland C2 ABFs; step = neighbours + weights "
                                "{dx, dy, lap} + 3-operator application",
                    "nodes": n, "nnz": nnz, "order8_nodes": int(is8.sum()), "prec": args.prec},
+        "step_ms": {"median": float(np.median(step_ms)), "min": float(step_ms.min()), "max": float(step_ms.max()),
+                    "steps": args.steps},
         "stages_ms": {"neighbours": kn[1] / args.steps, "weights": kw[1] / args.steps,
                       "weights_order8_kernel": k8_ms, "apply_3ops": ka_ms},
         "accuracy": {"nodes_passing_1e-10": int((status == 0).sum()), "nodes": n,
