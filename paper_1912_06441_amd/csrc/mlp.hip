@@ -30,6 +30,15 @@ using namespace wk;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
+// Logistic function 1 / (1 + e^-z) = 1 / (1 + 2^(-z log2 e)) from the
+// hardware base-2 exponential and reciprocal (about one ulp each in FP32).
+// The activations it produces are rounded to BF16 (8-bit significand) or
+// enter FP32 gradients of a BF16 network, so the IEEE-rounded exp and divide
+// buy nothing here.  Large |z| saturate correctly: 2^+inf = inf -> 0, 2^-inf = 0 -> 1.
+__device__ inline float logistic(float z) {
+    return __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_exp2f(z * -1.44269504088896341f));
+}
+
 // ------------------------------------------------------------------ features
 
 __global__ __launch_bounds__(64) void k_features(const double* __restrict__ x, const double* __restrict__ y,
@@ -189,14 +198,14 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
                 } else if (EPI == EPI_SILU) {
                     const float z = v + g.bias[cn];
                     if (g.zout) g.zout[o] = z;
-                    g.C[o] = z / (1.f + expf(-z));
+                    g.C[o] = z * logistic(z);
                 } else if (EPI == EPI_LINEAR) {
                     float z = v + (g.bias ? g.bias[cn] : 0.f);
                     if (g.mu) z = g.mu[cn] + g.sd[cn] * z;
                     g.C[o] = z;
                 } else {
                     const float z = g.zin[o];
-                    const float s = 1.f / (1.f + expf(-z));
+                    const float s = logistic(z);
                     g.C[o] = v * s * (1.f + z * (1.f - s));
                 }
             }
@@ -290,7 +299,7 @@ __global__ __launch_bounds__(256) void k_gemm_fwd(GemmArgs g) {
                 if (EPI == EPI_SILU) {
                     const float z = v + g.bias[cn];
                     if (g.zout) g.zout[o] = z;
-                    g.C[o] = z / (1.f + expf(-z));
+                    g.C[o] = z * logistic(z);
                 } else {
                     float z = v + (g.bias ? g.bias[cn] : 0.f);
                     if (g.mu) z = g.mu[cn] + g.sd[cn] * z;
@@ -382,7 +391,7 @@ __global__ __launch_bounds__(256) void k_mlp_fused(FusedArgs f) {
                     if (cn >= N) continue;
                     const float z = acc[i][j][r] + f.b[l][cn];
                     if (!last) {
-                        act[cur ^ 1][row][cn] = (__bf16)(z / (1.f + expf(-z)));
+                        act[cur ^ 1][row][cn] = (__bf16)(z * logistic(z));
                     } else if (r0 + row < f.B) {
                         f.out[(r0 + row) * N + cn] = f.mu ? f.mu[cn] + f.sd[cn] * z : z;
                     }
