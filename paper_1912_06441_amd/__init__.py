@@ -160,6 +160,26 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr()) if t is not None else None
 
 
+def _need(name, t, dtype=None, n=None):
+    """Arguments the kernels dereference must be contiguous GPU tensors of the
+    stated dtype holding at least n elements (None: not given, skipped)."""
+    if t is None:
+        return
+    if not getattr(t, "is_cuda", False):
+        raise ValueError("%s must be a GPU tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError("%s must be %s, not %s" % (name, dtype, t.dtype))
+    if n is not None and t.numel() < n:
+        raise ValueError("%s holds %d elements, %d are needed" % (name, t.numel(), n))
+
+
+def _need_csr(torch, row_ptr, col, n):
+    _need("row_ptr", row_ptr, torch.int64, n + 1)
+    _need("col", col, torch.int32)
+
+
 def _stream(torch):
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
@@ -228,6 +248,9 @@ class Context:
         """CSR neighbour lists.  R is updated in place when grow.  Returns (row_ptr, col)."""
         torch = self.torch
         n = x.numel()
+        for nm, t in (("x", x), ("y", y), ("R", R)):
+            _need(nm, t, torch.float64, n)
+        _need("order", order, torch.int8, n)
         dom = make_domain(domain)
         row_ptr = torch.empty(n + 1, dtype=torch.int64, device=x.device)
         nnz = C.c_int64(0)
@@ -246,6 +269,8 @@ class Context:
         """3-D CSR neighbour lists (no growth).  Returns (row_ptr, col)."""
         torch = self.torch
         n = x.numel()
+        for nm, t in (("x", x), ("y", y), ("z", z), ("R", R)):
+            _need(nm, t, torch.float64, n)
         dom = make_domain3(domain)
         row_ptr = torch.empty(n + 1, dtype=torch.int64, device=x.device)
         nnz = C.c_int64(0)
@@ -264,6 +289,9 @@ class Context:
         torch = self.torch
         n = x.numel()
         nnz = col.numel()
+        for nm, t in (("x", x), ("y", y), ("z", z), ("R", R)):
+            _need(nm, t, torch.float64, n)
+        _need_csr(torch, row_ptr, col, n)
         nop = bin(int(ops) & 63).count("1")
         dev = x.device
         w64 = torch.empty((nop, nnz), dtype=torch.float64, device=dev)
@@ -289,6 +317,10 @@ class Context:
         torch = self.torch
         n = x.numel()
         nnz = col.numel()
+        for nm, t in (("x", x), ("y", y), ("R", R)):
+            _need(nm, t, torch.float64, n)
+        _need("order", order, torch.int8, n)
+        _need_csr(torch, row_ptr, col, n)
         k = nops_of(ops)
         dev = x.device
         if out is None:
@@ -299,6 +331,11 @@ class Context:
             iters = torch.empty(n, dtype=torch.int8, device=dev)
         else:
             w64, w32, status, resid, iters = out
+        _need("w64", w64, torch.float64, k * nnz)
+        _need("w32", w32, torch.float32, k * nnz)
+        _need("status", status, torch.int8, n)
+        _need("resid", resid, torch.float32, n)
+        _need("iters", iters, torch.int8, n)
         o = WOpts(int(abf), int(rbf), float(sigma), int(ops), int(prec), float(tol_stop), float(tol_pass),
                   int(max_iters), None)
         desc = None
@@ -332,6 +369,17 @@ class Context:
                              torch.empty(n, dtype=torch.int8, device=dev),
                              torch.empty(n, dtype=torch.float32, device=dev),
                              torch.empty(n, dtype=torch.int8, device=dev)))
+        for S, o in zip(sets, outs):
+            n, nnz = S["x"].numel(), S["col"].numel()
+            for nm in ("x", "y", "R"):
+                _need(nm, S[nm], torch.float64, n)
+            _need("order", S["order"], torch.int8, n)
+            _need_csr(torch, S["row_ptr"], S["col"], n)
+            _need("w64", o[0], torch.float64, k * nnz)
+            _need("w32", o[1], torch.float32, k * nnz)
+            _need("status", o[2], torch.int8, n)
+            _need("resid", o[3], torch.float32, n)
+            _need("iters", o[4], torch.int8, n)
         table = (NodeSetDesc * len(sets))()
         for t, (S, o) in enumerate(zip(sets, outs)):
             d = table[t]
@@ -359,6 +407,7 @@ class Context:
 
     def combine(self, w64, coef, want64=True, want32=False):
         torch = self.torch
+        _need("w64", w64, torch.float64)
         nsets, nnz = w64.shape
         c = (C.c_double * nsets)(*[float(v) for v in coef])
         o64 = torch.empty(nnz, dtype=torch.float64, device=w64.device) if want64 else None
@@ -376,6 +425,10 @@ class Context:
         nops, nnz = w2.shape
         if w2.dtype != u.dtype:
             raise LabfmError("weights and field must have the same dtype")
+        _need_csr(torch, row_ptr, col, n)
+        _need("w", w2, u.dtype, nops * col.numel())
+        _need("u", u, None, n)
+        _need("out", out, u.dtype, nops * n)
         dtype = 1 if u.dtype == torch.float64 else 0
         if out is None:
             out = torch.empty((nops, n), dtype=u.dtype, device=u.device)
@@ -388,6 +441,10 @@ class Context:
         """[n, 3 kmax] FP32 stencil features (nearest kmax neighbours by scaled distance)."""
         torch = self.torch
         n = x.numel()
+        for nm, t in (("x", x), ("y", y), ("R", R)):
+            _need(nm, t, torch.float64, n)
+        _need_csr(torch, row_ptr, col, n)
+        _need("out", out, torch.float32, 3 * kmax * n)
         feat = out if out is not None else torch.empty((n, 3 * kmax), dtype=torch.float32, device=x.device)
         dom = make_domain(domain)
         _check(self.lib.labfm_mlp_features(self.h, _ptr(x), _ptr(y), n, C.byref(dom), _ptr(R), _ptr(row_ptr),
@@ -400,8 +457,15 @@ class Context:
         nodes with fixed != 0 (int8 device tensor [n]) keep their value."""
         torch = self.torch
         n = u.numel()
+        if u.dtype not in (torch.float32, torch.float64):
+            raise ValueError("u must be float32 or float64")
         if scratch is None:
             scratch = torch.empty(5 * n, dtype=u.dtype, device=u.device)
+        _need_csr(torch, row_ptr, col, n)
+        _need("w_lin", w_lin, u.dtype, col.numel())
+        _need("w_bh", w_bh, u.dtype, col.numel())
+        _need("u", u, None, n)
+        _need("scratch", scratch, u.dtype, 5 * n)
         dtype = 1 if u.dtype == torch.float64 else 0
         if fixed is not None and (fixed.dtype != torch.int8 or fixed.numel() != n or not fixed.is_contiguous()):
             raise ValueError("fixed must be a contiguous int8 tensor of n entries")
@@ -422,8 +486,16 @@ class Context:
         n = u.numel()
         if v.numel() != n or v.dtype != u.dtype:
             raise ValueError("u and v must have the same size and dtype")
+        if u.dtype not in (torch.float32, torch.float64):
+            raise ValueError("u and v must be float32 or float64")
         if scratch is None:
             scratch = torch.empty(6 * n, dtype=u.dtype, device=u.device)
+        _need_csr(torch, row_ptr, col, n)
+        for nm, t in (("w_x", w_x), ("w_y", w_y), ("w_lap", w_lap), ("w_hv", w_hv)):
+            _need(nm, t, u.dtype, col.numel())
+        _need("u", u, None, n)
+        _need("v", v, None, n)
+        _need("scratch", scratch, u.dtype, 6 * n)
         dtype = 1 if u.dtype == torch.float64 else 0
         if fixed is not None and (fixed.dtype != torch.int8 or fixed.numel() != n or not fixed.is_contiguous()):
             raise ValueError("fixed must be a contiguous int8 tensor of n entries")
@@ -451,6 +523,11 @@ class Context:
             phi = torch.zeros_like(F)
         if scratch is None:
             scratch = torch.empty(8 * n, dtype=torch.float64, device=F.device)
+        _need_csr(torch, row_ptr, col, n)
+        _need("w_lap", w_lap, torch.float64, col.numel())
+        _need("F", F, torch.float64, n)
+        _need("phi", phi, torch.float64, n)
+        _need("scratch", scratch, torch.float64, 8 * n)
         if fixed is not None and (fixed.dtype != torch.int8 or fixed.numel() != n or not fixed.is_contiguous()):
             raise ValueError("fixed must be a contiguous int8 tensor of n entries")
         plan = PoissonPlan(row_ptr.data_ptr(), col.data_ptr(), n, col.numel(), w_lap.data_ptr(),
@@ -475,6 +552,13 @@ class Context:
             psi = torch.zeros_like(omega)
         if scratch is None:
             scratch = torch.empty(14 * n, dtype=torch.float64, device=omega.device)
+        _need_csr(torch, row_ptr, col, n)
+        for nm, t in (("w_x", w_x), ("w_y", w_y), ("w_lap", w_lap)):
+            _need(nm, t, torch.float64, col.numel())
+        _need("omega", omega, torch.float64, n)
+        _need("psi", psi, torch.float64, n)
+        _need("psi_fixed", psi_fixed, torch.int8, n)
+        _need("scratch", scratch, torch.float64, 14 * n)
         if psi_fixed is not None and (psi_fixed.dtype != torch.int8 or psi_fixed.numel() != n):
             raise ValueError("psi_fixed must be an int8 tensor of n entries")
         plan = NSPlan(row_ptr.data_ptr(), col.data_ptr(), n, col.numel(), w_x.data_ptr(), w_y.data_ptr(),

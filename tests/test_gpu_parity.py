@@ -470,3 +470,33 @@ def test_weights_mixed_full_c2(env):
          % (np.median(par), par.max(), int((par > 1e-10).sum()), int((it >= 64).sum()), float(it[it < 64].mean())))
     assert (par > 1e-10).sum() <= max(1, n // 10000)
     assert par.max() <= 1e-8
+
+
+def test_binding_rejects_bad_tensors(env):
+    """Arguments the kernels would dereference are checked before any call:
+    host tensors, wrong dtypes, non-contiguous views and short buffers raise
+    ValueError (nothing reaches the library)."""
+    import torch
+
+    ctx = env["ctx"]
+    n = 64
+    xh = torch.rand(n, dtype=torch.float64)
+    xd = xh.cuda()
+    od = torch.full((n,), 4, dtype=torch.int8, device="cuda")
+    Rd = torch.full((n,), 0.1, dtype=torch.float64, device="cuda")
+    dom = WL.unit_domain(False)
+    with pytest.raises(ValueError, match="GPU tensor"):
+        ctx.build_neighbours(xh, xd, Rd, od, dom)
+    with pytest.raises(ValueError, match="float64"):
+        ctx.build_neighbours(xd.float(), xd, Rd, od, dom)
+    with pytest.raises(ValueError, match="contiguous"):
+        ctx.build_neighbours(torch.rand(2 * n, dtype=torch.float64, device="cuda")[::2], xd, Rd, od, dom)
+    rp, col = ctx.build_neighbours(xd, xd.flip(0).contiguous(), Rd, od, dom)
+    with pytest.raises(ValueError, match="int64"):
+        ctx.weights(xd, xd, Rd, od, rp.int(), col, dom)
+    w = torch.zeros((1, col.numel()), dtype=torch.float32, device="cuda")
+    u = torch.zeros(n, dtype=torch.float32, device="cuda")
+    with pytest.raises(ValueError, match="needed"):
+        ctx.step(rp, col, w[0], None, 0.0, 1e-3, u, 1, scratch=torch.empty(n, dtype=torch.float32, device="cuda"))
+    with pytest.raises(ValueError, match="GPU tensor"):
+        ctx.apply_operator(rp, col, w, u.cpu())
