@@ -72,11 +72,12 @@ __global__ __launch_bounds__(256) void k_step_single(const int64_t* __restrict__
     const int64_t row = gid / G;
     const int sub = (int)(gid % G);
     if (row >= n) return;
+    const Rk4Node<T> node = rk4_load<T>(stage, row, fixed, u, acc);
     WPtrs<T, 1> wp{{wl}};
     T a[1] = {T(0)};
     row_sums<T, G, U, 1>(col, rp[row], rp[row + 1], sub, wp, us_in, us_in[row], a);
     const T k = group_sum<T, G>(a[0]);
-    if (sub == 0) rk4_update<T>(stage, k, dt, row, fixed, u, acc, us_out);
+    if (sub == 0) rk4_store<T>(stage, k, dt, row, node, u, acc, us_out);
 }
 
 // pass A: ra = L_lin(us_in), b1 = B(us_in), one read of the index stream
@@ -111,11 +112,13 @@ __global__ __launch_bounds__(256) void k_step_b(const int64_t* __restrict__ rp, 
     const int64_t row = gid / G;
     const int sub = (int)(gid % G);
     if (row >= n) return;
+    const Rk4Node<T> node = rk4_load<T>(stage, row, fixed, u, acc);
+    const T rai = ra[row];
     WPtrs<T, 1> wp{{wb}};
     T c[1] = {T(0)};
     row_sums<T, G, U, 1>(col, rp[row], rp[row + 1], sub, wp, b1, b1[row], c);
     const T bb = group_sum<T, G>(c[0]);
-    if (sub == 0) rk4_update<T>(stage, ra[row] - gamma * bb, dt, row, fixed, u, acc, us_out);
+    if (sub == 0) rk4_store<T>(stage, rai - gamma * bb, dt, row, node, u, acc, us_out);
 }
 
 template <typename T>

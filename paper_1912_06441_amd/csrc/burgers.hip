@@ -30,6 +30,8 @@ __global__ __launch_bounds__(256) void k_burgers_stage(const int64_t* __restrict
     const int sub = (int)(gid % G);
     if (row >= n) return;  // whole groups exit together
     const T ui = uin[row], vi = vin[row];
+    const Rk4Node<T> nu_ = rk4_load<T>(stage, row, fixed, u, accu, dfix ? dfix + (int64_t)stage * n : nullptr);
+    const Rk4Node<T> nv_ = rk4_load<T>(stage, row, fixed, v, accv, dfix ? dfix + (int64_t)(4 + stage) * n : nullptr);
     T au[NW], av[NW];
 #pragma unroll
     for (int d = 0; d < NW; ++d) au[d] = av[d] = T(0);
@@ -46,8 +48,8 @@ __global__ __launch_bounds__(256) void k_burgers_stage(const int64_t* __restrict
         ku += au[NW - 1];
         kv += av[NW - 1];
     }
-    rk4_update<T>(stage, ku, dt, row, fixed, u, accu, uout, dfix ? dfix + (int64_t)stage * n : nullptr);
-    rk4_update<T>(stage, kv, dt, row, fixed, v, accv, vout, dfix ? dfix + (int64_t)(4 + stage) * n : nullptr);
+    rk4_store<T>(stage, ku, dt, row, nu_, u, accu, uout);
+    rk4_store<T>(stage, kv, dt, row, nv_, v, accv, vout);
 }
 
 template <typename T>

@@ -56,13 +56,15 @@ __global__ __launch_bounds__(256) void k_ns_stage(const int64_t* __restrict__ rp
     const int64_t row = gid / G;
     const int sub = (int)(gid % G);
     if (row >= n) return;
+    const Rk4Node<double> node = rk4_load<double>(stage, row, nullptr, om, acc);
+    const double ui = u[row], vi = v[row];
     double a[3] = {0.0, 0.0, 0.0};
     row_sums<double, G, U, 3>(col, rp[row], rp[row + 1], sub, w, om_in, om_in[row], a);
 #pragma unroll
     for (int d = 0; d < 3; ++d) a[d] = group_sum<double, G>(a[d]);
     if (sub != 0) return;
-    const double k = -(u[row] * a[0] + v[row] * a[1]) + nu * a[2];
-    rk4_update<double>(stage, k, dt, row, nullptr, om, acc, om_out);
+    const double k = -(ui * a[0] + vi * a[1]) + nu * a[2];
+    rk4_store<double>(stage, k, dt, row, node, om, acc, om_out);
 }
 
 }  // namespace

@@ -97,24 +97,42 @@ __device__ inline void row_sums2(const int32_t* __restrict__ col, int64_t s, int
     }
 }
 
-// stage update: k is the stage derivative at node i; on Dirichlet nodes it is
-// kfix[i] when an imposed derivative is given, else zero
+// Classical RK4 stage update of one node (Sec. 5.1).  The node's own values
+// are read by rk4_load before the row sums, so that these loads overlap the
+// stencil gathers rather than following the group reduction; rk4_store then
+// applies the stage with the derivative k.  On Dirichlet nodes k is replaced
+// by the imposed derivative kfix[i] when one is given, else by zero.
 template <typename T>
-__device__ inline void rk4_update(int stage, T k, T dt, int64_t i, const int8_t* fixed, T* u, T* acc, T* us_out,
-                                  const T* kfix = nullptr) {
-    if (fixed && fixed[i]) k = kfix ? kfix[i] : T(0);
-    const T ui = u[i];
+struct Rk4Node {
+    T u, acc, kfix;
+    bool fix;
+};
+
+template <typename T>
+__device__ inline Rk4Node<T> rk4_load(int stage, int64_t i, const int8_t* fixed, const T* u, const T* acc,
+                                      const T* kfix = nullptr) {
+    Rk4Node<T> s;
+    s.fix = fixed && fixed[i];
+    s.kfix = (s.fix && kfix) ? kfix[i] : T(0);
+    s.u = u[i];
+    s.acc = stage > 0 ? acc[i] : T(0);
+    return s;
+}
+
+template <typename T>
+__device__ inline void rk4_store(int stage, T k, T dt, int64_t i, const Rk4Node<T>& s, T* u, T* acc, T* us_out) {
+    if (s.fix) k = s.kfix;
     if (stage == 0) {
         acc[i] = k;
-        us_out[i] = ui + T(0.5) * dt * k;
+        us_out[i] = s.u + T(0.5) * dt * k;
     } else if (stage == 1) {
-        acc[i] = acc[i] + T(2) * k;
-        us_out[i] = ui + T(0.5) * dt * k;
+        acc[i] = s.acc + T(2) * k;
+        us_out[i] = s.u + T(0.5) * dt * k;
     } else if (stage == 2) {
-        acc[i] = acc[i] + T(2) * k;
-        us_out[i] = ui + dt * k;
+        acc[i] = s.acc + T(2) * k;
+        us_out[i] = s.u + dt * k;
     } else {
-        u[i] = ui + dt / T(6) * (acc[i] + k);
+        u[i] = s.u + dt / T(6) * (s.acc + k);
     }
 }
 
