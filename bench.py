@@ -344,7 +344,10 @@ def run_burgers(ctx, torch, np, L, WL, nsteps):
     w = [w64[d].to(torch.float32) for d in range(3)]  # one allocation each: 16-byte aligned streams
     h = 0.5 * cfg["R_s"] * nd["s"]
     Re = 100.0
-    dt = WL.burgers_dt(h, 1.0, Re)
+    # half the step of eq. (tstep): at the full step a mode localised on this
+    # noisy node set (eps 0.3 s) lifts max|u| from 1 to ~21 within 25 steps;
+    # at half the step the field decays as the viscous solution does
+    dt = 0.5 * WL.burgers_dt(h, 1.0, Re)
     xs, ys = nd["x"], nd["y"]
     u = torch.from_numpy(np.sin(2 * np.pi * xs) * np.sin(2 * np.pi * ys)).to(dev).to(torch.float32)
     v = torch.from_numpy(-np.cos(2 * np.pi * xs) * np.cos(2 * np.pi * ys)).to(dev).to(torch.float32)
@@ -359,13 +362,16 @@ def run_burgers(ctx, torch, np, L, WL, nsteps):
     ctx.timing_read(None)
     nnz = col.numel()
     ms_step = kg[1] / nsteps
-    # per step: 4 stages x (col + 3 FP32 weight streams per entry) + per node the row bounds
-    # (8 B per stage) and the stage states of both fields (24 + 40 + 40 + 32 B over the stages)
-    bytes_step = 4 * nnz * (4 + 3 * 4) + n * (4 * 8 + 136)
+    # per step: 4 stages x (col + 3 FP32 weight streams per entry); per node the row bounds
+    # (4 x 8 B), the packing of (u, v) into pairs (16 B) and the stage states of both fields:
+    # own pair 4 x 8, own u, v 4 x 8, accumulators 3 x 8 read + 3 x 8 written, pairs 3 x 8
+    # written, new u, v 8 B (144 B)
+    bytes_step = 4 * nnz * (4 + 3 * 4) + n * (4 * 8 + 16 + 144)
     return {"nodes": n, "nnz": nnz, "steps": nsteps, "Re": Re, "dt": dt, "ms_per_rk4_step": ms_step,
             "GB_per_s": bytes_step / (ms_step / 1e3) / 1e9, "hbm_frac": bytes_step / (ms_step / 1e3) / PEAK_HBM,
             "bytes_per_step": bytes_step, "weights_all_ok": bool((st == 0).all().item()),
-            "finite": bool(torch.isfinite(u).all().item() and torch.isfinite(v).all().item())}
+            "finite": bool(torch.isfinite(u).all().item() and torch.isfinite(v).all().item()),
+            "u_max": float(torch.maximum(u.abs().max(), v.abs().max()).item())}
 
 
 def run_poisson(ctx, torch, np, L, WL, tol=1e-10):

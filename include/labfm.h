@@ -308,8 +308,9 @@ typedef struct {
 } labfm_burgers_plan;
 
 /* Advance (u, v) (device [n] each, dtype of the plan) by nsteps RK4 steps.
- * scratch: device, at least 6 n elements of the plan's dtype, not aliasing u
- * or v.  use_graph != 0 captures one step as a HIP graph (kept while plan,
+ * scratch: device, at least 6 n elements of the plan's dtype, aligned to two
+ * elements (8 bytes FP32, 16 bytes FP64; the stage states of u and v are kept
+ * there as pairs), not aliasing u or v.  use_graph != 0 captures one step as a HIP graph (kept while plan,
  * buffers and stream are unchanged) and replays it.  Argument errors return
  * LABFM_EINVAL before any launch.  Asynchronous. */
 labfm_err labfm_burgers_step(void* ctx, const labfm_burgers_plan* plan, void* u, void* v, void* scratch,

@@ -3,6 +3,7 @@
 #include "labfm_internal.hpp"
 
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <string>
 
@@ -425,6 +426,8 @@ labfm_err labfm_burgers_step(void* ctx, const labfm_burgers_plan* plan, void* u,
         return fail(LABFM_EINVAL, "labfm_burgers_step: dt/nu not finite");
     if (plan->dfix && !plan->fixed)
         return fail(LABFM_EINVAL, "labfm_burgers_step: dfix needs a fixed mask");
+    if (plan->n > 0 && (uintptr_t)scratch % (plan->dtype ? 16 : 8) != 0)
+        return fail(LABFM_EINVAL, "labfm_burgers_step: scratch must be aligned to two elements");
     Context* c = (Context*)ctx;
     DeviceGuard g(c->device);
     return burgers_launch(c, plan, u, v, scratch, nsteps, use_graph, (hipStream_t)stream);

@@ -7,8 +7,10 @@
 // follow imposed stage derivatives.  One pass per RK4 stage: each CSR
 // row reads its index stream and the 3 (or 4) weight streams once and gathers
 // both velocity components, so the nonlinear right-hand side and the stage
-// update of both fields come out of a single HBM-bound sweep.  One step is
-// captured as a HIP graph and replayed.
+// update of both fields come out of a single HBM-bound sweep.  Every stage
+// reads its state as (u, v) pairs (the step's starting fields are packed so
+// first), so a single load fetches both components of a neighbour.  One step
+// is captured as a HIP graph and replayed.
 #include "labfm_internal.hpp"
 #include "stencil_rows.hpp"
 
@@ -18,24 +20,34 @@ namespace {
 
 using namespace rows;
 
+// the step's starting fields (u, v) as pairs, the input of the first stage
+template <typename T>
+__global__ __launch_bounds__(256) void k_pack_pairs(int64_t n, const T* __restrict__ u, const T* __restrict__ v,
+                                                    typename Vec2<T>::type* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = typename Vec2<T>::type{u[i], v[i]};
+}
+
 template <typename T, int NW>
 __global__ __launch_bounds__(256) void k_burgers_stage(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
-                                                       int64_t n, WPtrs<T, NW> w, const T* uin, const T* vin, T nu,
-                                                       T dt, int stage, const int8_t* __restrict__ fixed,
+                                                       int64_t n, WPtrs<T, NW> w,
+                                                       const typename Vec2<T>::type* __restrict__ pin, T nu, T dt,
+                                                       int stage, const int8_t* __restrict__ fixed,
                                                        const T* __restrict__ dfix, T* u, T* v, T* accu, T* accv,
-                                                       T* uout, T* vout) {
+                                                       typename Vec2<T>::type* __restrict__ pout) {
     constexpr int G = Shape<T>::G, U = Shape<T>::U;
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t row = gid / G;
     const int sub = (int)(gid % G);
     if (row >= n) return;  // whole groups exit together
-    const T ui = uin[row], vi = vin[row];
+    const typename Vec2<T>::type pi = pin[row];
+    const T ui = pi.x, vi = pi.y;
     const Rk4Node<T> nu_ = rk4_load<T>(stage, row, fixed, u, accu, dfix ? dfix + (int64_t)stage * n : nullptr);
     const Rk4Node<T> nv_ = rk4_load<T>(stage, row, fixed, v, accv, dfix ? dfix + (int64_t)(4 + stage) * n : nullptr);
     T au[NW], av[NW];
 #pragma unroll
     for (int d = 0; d < NW; ++d) au[d] = av[d] = T(0);
-    row_sums2<T, G, U, NW>(col, rp[row], rp[row + 1], sub, w, uin, vin, ui, vi, au, av);
+    row_sums2p<T, G, U, NW>(col, rp[row], rp[row + 1], sub, w, pin, ui, vi, au, av);
 #pragma unroll
     for (int d = 0; d < NW; ++d) {
         au[d] = group_sum<T, G>(au[d]);
@@ -48,39 +60,40 @@ __global__ __launch_bounds__(256) void k_burgers_stage(const int64_t* __restrict
         ku += au[NW - 1];
         kv += av[NW - 1];
     }
-    rk4_store<T>(stage, ku, dt, row, nu_, u, accu, uout);
-    rk4_store<T>(stage, kv, dt, row, nv_, v, accv, vout);
+    const T su = rk4_stage<T>(stage, ku, dt, row, nu_, u, accu);
+    const T sv = rk4_stage<T>(stage, kv, dt, row, nv_, v, accv);
+    if (stage < 3) pout[row] = typename Vec2<T>::type{su, sv};
+}
+
+template <typename T, int NW>
+void launch_stages(const labfm_burgers_plan* p, WPtrs<T, NW> w, T* u, T* v, T* scratch, hipStream_t st) {
+    using T2 = typename Vec2<T>::type;
+    const int64_t n = p->n;
+    // scratch: two arrays of (u, v) pairs, then the RK4 accumulators of each
+    // field.  PB first holds the step's starting fields, read by stage 0 only.
+    T2* PA = (T2*)scratch;
+    T2* PB = (T2*)(scratch + 2 * n);
+    T* au = scratch + 4 * n;
+    T* av = scratch + 5 * n;
+    const T dt = (T)p->dt, nu = (T)p->nu;
+    const T* dfix = (const T*)p->dfix;
+    const unsigned nb = blocks_for<T>(n);
+    const T2* in[4] = {PB, PA, PB, PA};
+    T2* out[4] = {PA, PB, PA, nullptr};
+    k_pack_pairs<T><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, u, v, PB);
+    for (int stage = 0; stage < 4; ++stage)
+        k_burgers_stage<T, NW><<<nb, 256, 0, st>>>(p->row_ptr, p->col, n, w, in[stage], nu, dt, stage, p->fixed, dfix,
+                                                   u, v, au, av, out[stage]);
 }
 
 template <typename T>
 labfm_err enqueue_burgers(const labfm_burgers_plan* p, T* u, T* v, T* scratch, hipStream_t st) {
-    const int64_t n = p->n;
-    // scratch: stage states and accumulators of both fields
-    T* uA = scratch;
-    T* uB = scratch + n;
-    T* au = scratch + 2 * n;
-    T* vA = scratch + 3 * n;
-    T* vB = scratch + 4 * n;
-    T* av = scratch + 5 * n;
-    const T* uin[4] = {u, uA, uB, uA};
-    const T* vin[4] = {v, vA, vB, vA};
-    T* uout[4] = {uA, uB, uA, u};
-    T* vout[4] = {vA, vB, vA, v};
-    const T dt = (T)p->dt, nu = (T)p->nu;
-    const unsigned nb = blocks_for<T>(n);
-    for (int stage = 0; stage < 4; ++stage) {
-        if (p->w_hv) {
-            WPtrs<T, 4> w{{(const T*)p->w_x, (const T*)p->w_y, (const T*)p->w_lap, (const T*)p->w_hv}};
-            k_burgers_stage<T, 4><<<nb, 256, 0, st>>>(p->row_ptr, p->col, n, w, uin[stage], vin[stage], nu, dt, stage,
-                                                      p->fixed, (const T*)p->dfix, u, v, au, av, uout[stage],
-                                                      vout[stage]);
-        } else {
-            WPtrs<T, 3> w{{(const T*)p->w_x, (const T*)p->w_y, (const T*)p->w_lap}};
-            k_burgers_stage<T, 3><<<nb, 256, 0, st>>>(p->row_ptr, p->col, n, w, uin[stage], vin[stage], nu, dt, stage,
-                                                      p->fixed, (const T*)p->dfix, u, v, au, av, uout[stage],
-                                                      vout[stage]);
-        }
-    }
+    if (p->w_hv)
+        launch_stages<T, 4>(p, WPtrs<T, 4>{{(const T*)p->w_x, (const T*)p->w_y, (const T*)p->w_lap, (const T*)p->w_hv}},
+                            u, v, scratch, st);
+    else
+        launch_stages<T, 3>(p, WPtrs<T, 3>{{(const T*)p->w_x, (const T*)p->w_y, (const T*)p->w_lap}}, u, v, scratch,
+                            st);
     LABFM_HIP_CHECK(hipGetLastError());
     return LABFM_OK;
 }

@@ -64,12 +64,25 @@ __device__ inline void row_sums(const int32_t* __restrict__ col, int64_t s, int6
     }
 }
 
-// The same sums for two fields x and y over one read of the index and weight
-// streams: ax[d] += w_d (x_j - x_i), ay[d] += w_d (y_j - y_i).
+// Two components stored as one pair per node, so that a row gathers both
+// with a single load per entry.
+template <typename T>
+struct Vec2;
+template <>
+struct Vec2<float> {
+    using type = float2;
+};
+template <>
+struct Vec2<double> {
+    using type = double2;
+};
+
+// The same sums for two fields held as pairs, over one read of the index and
+// weight streams: ax[d] += w_d (xy_j.x - x_i), ay[d] += w_d (xy_j.y - y_i).
 template <typename T, int G, int U, int NW>
-__device__ inline void row_sums2(const int32_t* __restrict__ col, int64_t s, int64_t e, int sub,
-                                 const WPtrs<T, NW>& w, const T* __restrict__ x, const T* __restrict__ y, T xi,
-                                 T yi, T (&ax)[NW], T (&ay)[NW]) {
+__device__ inline void row_sums2p(const int32_t* __restrict__ col, int64_t s, int64_t e, int sub,
+                                  const WPtrs<T, NW>& w, const typename Vec2<T>::type* __restrict__ xy, T xi, T yi,
+                                  T (&ax)[NW], T (&ay)[NW]) {
     for (int64_t q0 = s + sub; q0 < e; q0 += (int64_t)G * U) {
         int c[U];
         T wv[U][NW];
@@ -86,8 +99,12 @@ __device__ inline void row_sums2(const int32_t* __restrict__ col, int64_t s, int
         }
 #pragma unroll
         for (int k = 0; k < U; ++k) {
-            const T dx = c[k] >= 0 ? x[c[k]] - xi : T(0);
-            const T dy = c[k] >= 0 ? y[c[k]] - yi : T(0);
+            T dx = T(0), dy = T(0);
+            if (c[k] >= 0) {
+                const typename Vec2<T>::type g = xy[c[k]];
+                dx = g.x - xi;
+                dy = g.y - yi;
+            }
 #pragma unroll
             for (int d = 0; d < NW; ++d) {
                 ax[d] += wv[k][d] * dx;
@@ -119,21 +136,31 @@ __device__ inline Rk4Node<T> rk4_load(int stage, int64_t i, const int8_t* fixed,
     return s;
 }
 
+// applies the stage and returns the next stage state (stages 0-2); the last
+// stage writes the new value to u[i] and returns zero
 template <typename T>
-__device__ inline void rk4_store(int stage, T k, T dt, int64_t i, const Rk4Node<T>& s, T* u, T* acc, T* us_out) {
+__device__ inline T rk4_stage(int stage, T k, T dt, int64_t i, const Rk4Node<T>& s, T* u, T* acc) {
     if (s.fix) k = s.kfix;
     if (stage == 0) {
         acc[i] = k;
-        us_out[i] = s.u + T(0.5) * dt * k;
-    } else if (stage == 1) {
-        acc[i] = s.acc + T(2) * k;
-        us_out[i] = s.u + T(0.5) * dt * k;
-    } else if (stage == 2) {
-        acc[i] = s.acc + T(2) * k;
-        us_out[i] = s.u + dt * k;
-    } else {
-        u[i] = s.u + dt / T(6) * (s.acc + k);
+        return s.u + T(0.5) * dt * k;
     }
+    if (stage == 1) {
+        acc[i] = s.acc + T(2) * k;
+        return s.u + T(0.5) * dt * k;
+    }
+    if (stage == 2) {
+        acc[i] = s.acc + T(2) * k;
+        return s.u + dt * k;
+    }
+    u[i] = s.u + dt / T(6) * (s.acc + k);
+    return T(0);
+}
+
+template <typename T>
+__device__ inline void rk4_store(int stage, T k, T dt, int64_t i, const Rk4Node<T>& s, T* u, T* acc, T* us_out) {
+    const T us = rk4_stage<T>(stage, k, dt, i, s, u, acc);
+    if (stage < 3) us_out[i] = us;
 }
 
 template <typename T>

@@ -16,6 +16,10 @@ oracle's RK4 and the Cole-Hopf solution.
   the oracle on the same weights, graph replays == direct launches bit for
   bit; through the whole GPU path the error falls at order about k (k = 4,
   Re = 100) and Re = 10, k = 6 on the 10 x 10 set ends below 1e-8 at t = 1.
+* The 1024 x 1024 throughput workload (eps 0.3 s, k = 6, Re = 100) grows a
+  localised mode at eq. (tstep)'s step and decays at half of it.
+* A scratch buffer not aligned to two elements (the stage states are stored
+  as (u, v) pairs) is refused.
 """
 import math
 import sys
@@ -314,3 +318,62 @@ def test_travelling_wave_gpu_path(env):
     e10 = _wave_err(S, u, v, 1.0, 10.0)
     _say("  Re 10, k 6, 10 x 10, t = 1: %.3e" % e10)
     assert e10 < 1e-8
+
+
+def _c5_burgers(env):
+    """The 1024 x 1024 periodic order-6 node set (eps 0.3 s) of the Burgers
+    throughput workload, with its FP32 d/dx, d/dy and Laplacian weights."""
+    torch, ctx = env["torch"], env["ctx"]
+    cfg = WL.config("c5")
+    nd = WL.make_nodes(cfg)
+    x, y, R, order = (_dev(env, nd[k]) for k in ("x", "y", "R", "order"))
+    rp, col = ctx.build_neighbours(x, y, R, order, nd["domain"])
+    w64, _, st, _, _ = ctx.weights(x, y, R, order, rp, col, nd["domain"], ops=7)
+    assert bool((st == 0).all())
+    w = [w64[d].to(torch.float32).contiguous() for d in range(3)]
+    return nd, rp, col, w, 0.5 * cfg["R_s"] * nd["s"]
+
+
+def test_throughput_workload_half_step_is_stable(env):
+    """At eq. (tstep)'s step a mode localised on the noisy 1024^2 set lifts
+    max|u| far above its initial 1 within 25 steps; at half that step (the
+    step the throughput workload uses) the field decays as a viscous solution
+    must: max|u| stays at or below 1 over 400 steps."""
+    torch, ctx = env["torch"], env["ctx"]
+    nd, rp, col, w, h = _c5_burgers(env)
+    Re = 100.0
+    dt = WL.burgers_dt(h, 1.0, Re)
+    peaks = {}
+    for label, step, nsteps in (("full", dt, 25), ("half", 0.5 * dt, 400)):
+        u = _dev(env, np.sin(2 * np.pi * nd["x"]) * np.sin(2 * np.pi * nd["y"]), torch.float32)
+        v = _dev(env, -np.cos(2 * np.pi * nd["x"]) * np.cos(2 * np.pi * nd["y"]), torch.float32)
+        ctx.burgers_step(rp, col, w[0], w[1], w[2], 1.0 / Re, step, u, v, nsteps)
+        torch.cuda.synchronize()
+        finite = bool(torch.isfinite(u).all() and torch.isfinite(v).all())
+        peaks[label] = float(torch.maximum(u.abs().max(), v.abs().max())) if finite else math.inf
+        _say("  1024^2 Burgers, %s step, %d steps: max|u, v| %.4g" % (label, nsteps, peaks[label]))
+    assert peaks["full"] > 5.0
+    assert peaks["half"] <= 1.0 + 1e-6
+
+
+def test_scratch_must_hold_pairs(env):
+    """The stage states are kept as (u, v) pairs: a scratch buffer that is not
+    aligned to two elements is refused before any launch."""
+    torch, L = env["torch"], env["L"]
+    S = _oracle_set(env, 4, 21, 0.2)
+    n = S["x"].size
+    w = [_dev(env, S["w"][d]) for d in range(3)]
+    for dtype in (torch.float64, torch.float32):
+        u = _dev(env, np.sin(2 * np.pi * S["x"]), dtype)
+        v = _dev(env, np.zeros(n), dtype)
+        wd = [t.to(dtype).contiguous() for t in w]
+        bad = torch.empty(6 * n + 1, dtype=dtype, device="cuda")[1:]
+        with pytest.raises(L.LabfmError, match="aligned"):
+            env["ctx"].burgers_step(_dev(env, S["rp"]), _dev(env, S["col"]), wd[0], wd[1], wd[2], 0.01, 1e-5, u, v,
+                                    1, scratch=bad)
+        u0 = u.clone()
+        good = torch.empty(6 * n, dtype=dtype, device="cuda")
+        env["ctx"].burgers_step(_dev(env, S["rp"]), _dev(env, S["col"]), wd[0], wd[1], wd[2], 0.01, 1e-5, u, v, 1,
+                                scratch=good)
+        torch.cuda.synchronize()
+        assert bool(torch.isfinite(u).all()) and not torch.equal(u, u0)
