@@ -54,16 +54,22 @@ __global__ __launch_bounds__(256) void k_spmv(const int64_t* __restrict__ rp, co
                                               int64_t n, const double* __restrict__ w,
                                               const int8_t* __restrict__ fixed, const double* __restrict__ x,
                                               double* __restrict__ y, const double* __restrict__ S) {
-    if (S && S[S_STOP] != 0.0) return;
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t row = gid / SG;
     const int sub = (int)(gid % SG);
     if (row >= n) return;  // whole groups exit together
+    // the stop flag, the row bounds and the row's own values are requested
+    // together, ahead of the dependent index and gather loads
+    const bool stop = S && S[S_STOP] != 0.0;
+    const int64_t s = rp[row], e = rp[row + 1];
+    const double xi = x[row];
+    const bool ident = fixed && fixed[row];
+    if (stop) return;
     WPtrs<double, 1> wp{{w}};
     double acc[1] = {0.0};
-    row_sums<double, SG, SU, 1>(col, rp[row], rp[row + 1], sub, wp, x, x[row], acc);
+    row_sums<double, SG, SU, 1>(col, s, e, sub, wp, x, xi, acc);
     const double v = group_sum<double, SG>(acc[0]);
-    if (sub == 0) y[row] = (fixed && fixed[row]) ? x[row] : v;
+    if (sub == 0) y[row] = ident ? xi : v;
 }
 
 // inverse diagonal of A^L (1 on identity rows and where the diagonal is zero)
