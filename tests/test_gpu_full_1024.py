@@ -8,8 +8,9 @@ configuration bench.py times, against the oracle run at full size.
   state, graph-replayed (the benchmark's step): two steps against the oracle's
   FP64 RK4 on its own weights, max |du| <= 1e-4 max |u| (the FP32 bound of
   the small-set test).
-* Burgers (FP32, Re = 100, the benchmark's step): two steps against the
-  oracle's FP64 Burgers RK4, same bound.
+* Burgers (FP32, Re = 100, the benchmark's step, half of eq. (tstep)): ten
+  steps of the paired-state stage kernel against the oracle's FP64 Burgers
+  RK4, same bound.
 * The configured run: 1000 FP32 steps against 1000 FP64 oracle steps at
   t_end, max |du| <= 1e-3 max |u| (measured 4.1e-7).
 """
@@ -102,20 +103,21 @@ def test_full_burgers_fp32_step(full):
     torch, O, nd = f["torch"], f["O"], f["nd"]
     Re = 100.0
     h = 0.5 * f["cfg"]["R_s"] * nd["s"]
-    dt = WL.burgers_dt(h, 1.0, Re)
+    dt = 0.5 * WL.burgers_dt(h, 1.0, Re)  # the benchmark's step: half of eq. (tstep) on this node set
     xs, ys = nd["x"], nd["y"]
     u0 = np.sin(2 * np.pi * xs) * np.sin(2 * np.pi * ys)
     v0 = -np.cos(2 * np.pi * xs) * np.cos(2 * np.pi * ys)
     w = [f["w64"][d].to(torch.float32) for d in range(3)]
     u = torch.from_numpy(u0).cuda().to(torch.float32)
     v = torch.from_numpy(v0).cuda().to(torch.float32)
-    f["ctx"].burgers_step(f["rp"], f["col"], w[0], w[1], w[2], 1.0 / Re, dt, u, v, 2)
+    nsteps = 10
+    f["ctx"].burgers_step(f["rp"], f["col"], w[0], w[1], w[2], 1.0 / Re, dt, u, v, nsteps)
     torch.cuda.synchronize()
-    uo, vo = O.burgers_rk4(f["rp_o"], f["col_o"], f["w_o"][0], f["w_o"][1], f["w_o"][2], None, 1.0 / Re, dt, 2,
+    uo, vo = O.burgers_rk4(f["rp_o"], f["col_o"], f["w_o"][0], f["w_o"][1], f["w_o"][2], None, 1.0 / Re, dt, nsteps,
                            u0, v0)
     err = max(np.abs(u.double().cpu().numpy() - uo).max() / np.abs(uo).max(),
               np.abs(v.double().cpu().numpy() - vo).max() / np.abs(vo).max())
-    _say("  full Burgers (2 FP32 steps) vs FP64 oracle: %.2e" % err)
+    _say("  full Burgers (%d FP32 steps) vs FP64 oracle: %.2e" % (nsteps, err))
     assert err <= 1e-4
 
 
