@@ -86,3 +86,17 @@ def test_new_entry_points_validate_before_device_work(lib):
         assert lib.labfm_last_error(), name
     lib.labfm_mlp_cache_floats.restype = c.c_int64
     assert lib.labfm_mlp_cache_floats(None, c.c_int64(10)) == -1
+
+
+def test_missing_library_fails_loudly():
+    """Without the built library the binding raises; there is no other path."""
+    code = ("import paper_1912_06441_amd as L\n"
+            "try:\n"
+            "    L.load_library('/nonexistent/liblabfm.so')\n"
+            "except L.LabfmError as e:\n"
+            "    print('raised:', e)\n"
+            "else:\n"
+            "    raise SystemExit('loaded a library that does not exist')\n")
+    r = subprocess.run([os.sys.executable, "-c", code], capture_output=True, text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 0, r.stderr
+    assert "raised:" in r.stdout and "not built" in r.stdout
