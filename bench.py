@@ -51,33 +51,87 @@ def measured_traffic(kernel, sources):
 
 
 def weight_flops(N, p, nd, iters):
-    """Algorithmic FP64 flops of one weight set: assembly 2Np^2, LU 2p^3/3,
+    """Algorithmic FP64 flops of one weight set: basis evaluation 10Np (the
+    monomials and ABFs of every neighbour), assembly 2Np^2, LU 2p^3/3,
     (1 + it) x [solve 2 nd p^2 + weights 2 N p nd + residual 2 N p nd]."""
-    return 2.0 * N * p * p + 2.0 * p ** 3 / 3.0 + (1.0 + iters) * (2.0 * nd * p * p + 4.0 * N * p * nd)
+    return (10.0 * N * p + 2.0 * N * p * p + 2.0 * p ** 3 / 3.0
+            + (1.0 + iters) * (2.0 * nd * p * p + 4.0 * N * p * nd))
 
 
-def run_cpu_baseline(nd, cfg):
+def cpu_model():
+    """`lscpu`'s model name of the host (or /proc/cpuinfo's), and nproc."""
+    import subprocess
+
+    name = ""
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for ln in out.splitlines():
+            if ln.startswith("Model name:"):
+                name = ln.split(":", 1)[1].strip()
+                break
+    except (OSError, subprocess.SubprocessError):
+        pass
+    if not name:
+        try:
+            with open("/proc/cpuinfo") as fh:
+                for ln in fh:
+                    if ln.startswith("model name"):
+                        name = ln.split(":", 1)[1].strip()
+                        break
+        except OSError:
+            pass
+    return name, os.cpu_count()
+
+
+def run_cpu_baseline(nd, cfg, runs=5, sample1=8192):
+    """The oracle (plain FP64 C, OpenMP over nodes) on the host cores, median of
+    `runs`: all threads over the whole step of the full workload (neighbours +
+    FP64 weights + 3 operators), and one thread over the weights of a seeded
+    sample of `sample1` order-8 nodes (the other nodes' order set to 0, which
+    the oracle rejects at once)."""
     import numpy as np
 
     import oracle as O
     from paper_1912_06441_amd import workloads as WL
 
     f = WL.trig_field(nd["x"], nd["y"], WL.trig_poly(0))[0]
-    # whole steps (neighbours + FP64 weights + 3 operators) repeated until about 10 s of CPU work
-    steps, good, t0 = 0, 0, time.perf_counter()
-    while True:
+    threads = O.num_threads()
+    rates, good = [], 0
+    for _ in range(runs):
+        t0 = time.perf_counter()
         rp, col, R = O.neighbours(nd["x"], nd["y"], nd["domain"], nd["R"], nd["order"])
         w, st, res, _ = O.weights(nd["x"], nd["y"], nd["domain"], R, nd["order"], rp, col)
         for d in range(3):
             O.apply(rp, col, w[d], f)
-        steps += 1
-        good += int(((st == 0) & (nd["order"] == 8)).sum())
         dt = time.perf_counter() - t0
-        if dt >= 10.0 or steps >= 30:
-            break
-    return {"value": good / dt, "unit": "weight-sets/s (order 8)", "cores": O.num_threads(), "kind": "oracle",
-            "sample": "the full 512x512 workload, %d steps (neighbours + FP64 weights + 3 operators), %.1f s"
-                      % (steps, dt)}
+        good = int(((st == 0) & (nd["order"] == 8)).sum())
+        rates.append(good / dt)
+    # one thread: weights of a sample of order-8 nodes
+    idx8 = np.nonzero(nd["order"] == 8)[0]
+    pick = np.random.default_rng(12345).choice(idx8, min(sample1, idx8.size), replace=False)
+    order_s = np.zeros_like(nd["order"])
+    order_s[pick] = 8
+    rates1, good1 = [], 0
+    O.set_num_threads(1)
+    try:
+        for _ in range(runs):
+            t0 = time.perf_counter()
+            w, st, res, _ = O.weights(nd["x"], nd["y"], nd["domain"], R, order_s, rp, col)
+            dt = time.perf_counter() - t0
+            good1 = int((st[pick] == 0).sum())
+            rates1.append(good1 / dt)
+    finally:
+        O.set_num_threads(threads)
+    model, nproc = cpu_model()
+    return {"value": float(np.median(rates)), "unit": "weight-sets/s (order 8)", "cores": threads,
+            "kind": "oracle",
+            "sample": "the full 512x512 workload, whole steps (neighbours + FP64 weights + 3 operators), "
+                      "median of %d runs (%d order-8 nodes at the gate per run)" % (runs, good),
+            "runs": [round(r, 1) for r in rates], "nproc": nproc, "cpu_model": model,
+            "single_thread": {"value": float(np.median(rates1)), "unit": "weight-sets/s (order 8)", "cores": 1,
+                              "sample": "FP64 weights of %d seeded order-8 nodes of the same workload, "
+                                        "median of %d runs" % (good1, runs),
+                              "runs": [round(r, 1) for r in rates1]}}
 
 
 def main():

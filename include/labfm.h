@@ -85,7 +85,11 @@ enum {
  *        with the FP32 factors. */
 typedef enum { LABFM_PREC_FP64 = 0, LABFM_PREC_MIXED = 1, LABFM_PREC_MLP = 2 } labfm_prec;
 
-/* Per-node status written by labfm_weights. */
+/* Per-node status written by labfm_weights.  The weight calls are
+ * asynchronous, so per-node numerical failures are reported here only: a call
+ * returns LABFM_OK once its work is enqueued, whatever the nodes' statuses
+ * turn out to be (no error code depends on per-node results, which would force
+ * a synchronisation on every call). */
 enum {
     LABFM_ST_OK = 0,             /* moment residual <= tol_pass              */
     LABFM_ST_NOT_CONVERGED = 1,  /* weights written, residual > tol_pass     */
@@ -93,7 +97,9 @@ enum {
     LABFM_ST_TOO_FEW = 3,        /* fewer neighbours than p; weights zero    */
     LABFM_ST_DEGENERATE = 4,     /* PAPER ABFs undefined (coincident node)   */
     LABFM_ST_ORDER_TOO_LOW = 5,  /* order cannot express a requested target  */
-    LABFM_ST_TOO_MANY = 6        /* more than LABFM_MAX_NEIGHBOURS neighbours */
+    LABFM_ST_TOO_MANY = 6        /* more than LABFM_MAX_NEIGHBOURS neighbours:
+                                    weights zero (an implementation limit of
+                                    the weight kernels, 2-D and 3-D alike) */
 };
 
 #define LABFM_MAX_ORDER 8
@@ -145,7 +151,9 @@ typedef struct {
     int prec;          /* labfm_prec                                       */
     double tol_stop;   /* refinement stops when ||C - X^T w||_inf <= this  */
     double tol_pass;   /* status OK when the final residual <= this        */
-    int max_iters;     /* FP64 refinement updates at most                  */
+    int max_iters;     /* FP64 refinement updates at most, 0..63 (iters[] is
+                          int8 and the MIXED path adds 64 for nodes it hands
+                          to the FP64 path)                                */
     const labfm_mlp* mlp; /* network for LABFM_PREC_MLP (host struct), else NULL */
 } labfm_wopts;
 

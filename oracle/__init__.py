@@ -19,7 +19,9 @@ ABF_HERMITE, ABF_PAPER, ABF_PAPER_D1 = 0, 1, 2
 RBF_WENDLAND_C2, RBF_CONE, RBF_QUADRATIC, RBF_WENDLAND_C6, RBF_GAUSSIAN = 0, 1, 2, 3, 4
 OP_DX, OP_DY, OP_LAP, OP_BIHARM, OP_TRIHARM = 1, 2, 4, 8, 16
 OP_DZ = 32  # three dimensions only
-ST_OK, ST_NOT_CONVERGED, ST_SINGULAR, ST_TOO_FEW, ST_DEGENERATE, ST_ORDER_TOO_LOW = range(6)
+ST_OK, ST_NOT_CONVERGED, ST_SINGULAR, ST_TOO_FEW, ST_DEGENERATE, ST_ORDER_TOO_LOW, ST_TOO_MANY = range(7)
+NMAX = 128  # longest stencil row the weights accept (implementation limit; longer: ST_TOO_MANY)
+NMAX3 = 128  # the same in three dimensions
 MAXK = 8
 
 

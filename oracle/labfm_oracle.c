@@ -632,6 +632,7 @@ static int node_weights_impl(int k, int N, const double* dxh, const double* dyh,
         }
     }
     if (N < p) return OR_ST_TOO_FEW;
+    if (N > OR_NMAX) return OR_ST_TOO_MANY;
     double* X = (double*)malloc(sizeof(double) * (size_t)N * p);
     double* W = (double*)malloc(sizeof(double) * (size_t)N * p);
     for (int j = 0; j < N; ++j) {
@@ -1042,6 +1043,7 @@ static int node_weights3(int k, int N, const double* dxh, const double* dyh, con
         if (or_target3(list[d], p, Ct, &l) != 0) return OR_ST_ORDER_TOO_LOW;
     }
     if (N < p) return OR_ST_TOO_FEW;
+    if (N > OR_NMAX3) return OR_ST_TOO_MANY;
     double* X = (double*)malloc(sizeof(double) * (size_t)N * p);
     double* W = (double*)malloc(sizeof(double) * (size_t)N * p);
     for (int j = 0; j < N; ++j) {

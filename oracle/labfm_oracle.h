@@ -34,7 +34,13 @@ enum { OR_OP_DX = 1, OR_OP_DY = 2, OR_OP_LAP = 4, OR_OP_BIHARM = 8, OR_OP_TRIHAR
        OR_OP_DZ = 32 /* 3-D only */ };
 /* per-node status */
 enum { OR_ST_OK = 0, OR_ST_NOT_CONVERGED = 1, OR_ST_SINGULAR = 2, OR_ST_TOO_FEW = 3,
-       OR_ST_DEGENERATE = 4, OR_ST_ORDER_TOO_LOW = 5 };
+       OR_ST_DEGENERATE = 4, OR_ST_ORDER_TOO_LOW = 5, OR_ST_TOO_MANY = 6 };
+/* Longest stencil row the weights accept (an implementation limit, not the
+ * paper's: the method itself takes any number of neighbours).  Longer rows get
+ * OR_ST_TOO_MANY and zero weights, as the HIP library documents for its
+ * LABFM_MAX_NEIGHBOURS; the same limit in two and three dimensions. */
+#define OR_NMAX 128
+#define OR_NMAX3 128
 
 typedef struct {
     double lo[2], hi[2];

@@ -264,7 +264,7 @@ labfm_err labfm_weights3(void* ctx, const double* x, const double* y, const doub
     if (opt->prec != LABFM_PREC_FP64) return fail(LABFM_EUNSUPPORTED, "labfm_weights3: only LABFM_PREC_FP64");
     if (opt->rbf < 0 || opt->rbf > 4) return fail(LABFM_EINVAL, "labfm_weights3: bad rbf");
     if (!(opt->sigma > 0.0) || !std::isfinite(opt->sigma)) return fail(LABFM_EINVAL, "labfm_weights3: sigma must be > 0");
-    if (opt->max_iters < 0 || opt->max_iters > 100) return fail(LABFM_EINVAL, "labfm_weights3: max_iters out of range");
+    if (opt->max_iters < 0 || opt->max_iters > 63) return fail(LABFM_EINVAL, "labfm_weights3: max_iters must be in 0..63");
     if (!(opt->tol_stop >= 0.0) || !(opt->tol_pass >= 0.0)) return fail(LABFM_EINVAL, "labfm_weights3: bad tolerances");
     if (n > 0 && (!x || !y || !z || !R || !row_ptr || !status || !w64 || (nnz > 0 && !col)))
         return fail(LABFM_EINVAL, "labfm_weights3: NULL array");
@@ -275,35 +275,35 @@ labfm_err labfm_weights3(void* ctx, const double* x, const double* y, const doub
                     (hipStream_t)stream);
 }
 
-labfm_err labfm_weights(void* ctx, const double* x, const double* y, int64_t n, const labfm_domain* dom,
-                        const double* R, const int8_t* order, const int64_t* row_ptr, const int32_t* col,
-                        int64_t nnz, const labfm_wopts* opt, double* w64, float* w32, int8_t* status, float* resid,
-                        int8_t* iters, void* stream) {
-    if (!ctx) return fail(LABFM_EINVAL, "labfm_weights: ctx is NULL");
-    if (!opt) return fail(LABFM_EINVAL, "labfm_weights: opt is NULL");
-    if (n < 0 || n > INT32_MAX || nnz < 0) return fail(LABFM_EINVAL, "labfm_weights: n or nnz out of range");
-    if (!domain_ok(dom)) return fail(LABFM_EINVAL, "labfm_weights: bad domain");
-    if (opt->ops == 0 || (opt->ops & ~31u)) return fail(LABFM_EINVAL, "labfm_weights: ops must be a nonzero set of LABFM_OP_* bits");
-    if (opt->abf < LABFM_ABF_HERMITE || opt->abf > LABFM_ABF_PAPER_D1) return fail(LABFM_EINVAL, "labfm_weights: bad abf");
-    if (opt->rbf < 0 || opt->rbf > 4) return fail(LABFM_EINVAL, "labfm_weights: bad rbf");
-    if (!(opt->sigma > 0.0) || !std::isfinite(opt->sigma)) return fail(LABFM_EINVAL, "labfm_weights: sigma must be > 0");
-    if (opt->max_iters < 0 || opt->max_iters > 100) return fail(LABFM_EINVAL, "labfm_weights: max_iters out of range");
-    if (!(opt->tol_stop >= 0.0) || !(opt->tol_pass >= 0.0)) return fail(LABFM_EINVAL, "labfm_weights: bad tolerances");
-    if (!w64 && !w32) return fail(LABFM_EINVAL, "labfm_weights: w64 and w32 are both NULL");
+namespace {
+
+// Argument checks of the weights entry points (`who`
+// prefixes the message), and the WeightArgs of the call's one node set.
+labfm_err check_weights_args(const char* who, const double* x, const double* y, int64_t n, const labfm_domain* dom,
+                             const double* R, const int8_t* order, const int64_t* row_ptr, const int32_t* col,
+                             int64_t nnz, const labfm_wopts* opt, double* w64, float* w32, int8_t* status) {
+    const std::string w = std::string(who) + ": ";
+    if (!opt) return fail(LABFM_EINVAL, w + "opt is NULL");
+    if (n < 0 || n > INT32_MAX || nnz < 0) return fail(LABFM_EINVAL, w + "n or nnz out of range");
+    if (!domain_ok(dom)) return fail(LABFM_EINVAL, w + "bad domain");
+    if (opt->ops == 0 || (opt->ops & ~31u)) return fail(LABFM_EINVAL, w + "ops must be a nonzero set of LABFM_OP_* bits");
+    if (opt->abf < LABFM_ABF_HERMITE || opt->abf > LABFM_ABF_PAPER_D1) return fail(LABFM_EINVAL, w + "bad abf");
+    if (opt->rbf < 0 || opt->rbf > 4) return fail(LABFM_EINVAL, w + "bad rbf");
+    if (!(opt->sigma > 0.0) || !std::isfinite(opt->sigma)) return fail(LABFM_EINVAL, w + "sigma must be > 0");
+    if (opt->max_iters < 0 || opt->max_iters > 63) return fail(LABFM_EINVAL, w + "max_iters must be in 0..63");
+    if (!(opt->tol_stop >= 0.0) || !(opt->tol_pass >= 0.0)) return fail(LABFM_EINVAL, w + "bad tolerances");
+    if (!w64 && !w32) return fail(LABFM_EINVAL, w + "w64 and w32 are both NULL");
     if (n > 0 && (!x || !y || !R || !order || !row_ptr || !status || (nnz > 0 && !col)))
-        return fail(LABFM_EINVAL, "labfm_weights: NULL array");
+        return fail(LABFM_EINVAL, w + "NULL array");
     if (opt->prec != LABFM_PREC_FP64 && opt->prec != LABFM_PREC_MIXED && opt->prec != LABFM_PREC_MLP)
-        return fail(LABFM_EINVAL, "labfm_weights: bad prec");
-    if (opt->prec == LABFM_PREC_MLP) {
-        std::string why;
-        if (!mlp_serves(opt->mlp, why)) return fail(LABFM_EINVAL, "labfm_weights: network: " + why);
-        if (opt->mlp->ops != opt->ops) return fail(LABFM_EINVAL, "labfm_weights: network ops differ from opt->ops");
-    }
-    Context* c = (Context*)ctx;
-    DeviceGuard g(c->device);
-    if (!g.ok) return fail(LABFM_EHIP, "labfm_weights: hipSetDevice failed");
-    if (n == 0) return LABFM_OK;
-    WeightArgs a{};
+        return fail(LABFM_EINVAL, w + "bad prec");
+    return LABFM_OK;
+}
+
+void one_set_args(WeightArgs& a, const double* x, const double* y, int64_t n, const labfm_domain* dom,
+                  const double* R, const int8_t* order, const int64_t* row_ptr, const int32_t* col, int64_t nnz,
+                  const labfm_wopts* opt, double* w64, float* w32, int8_t* status, float* resid, int8_t* iters) {
+    a = WeightArgs{};
     NodeSet& S = a.one;
     S.x = x;
     S.y = y;
@@ -328,9 +328,30 @@ labfm_err labfm_weights(void* ctx, const double* x, const double* y, int64_t n, 
     a.nsets = 1;
     a.ntotal = n;
     set_options(a, opt);
-    hipStream_t st = (hipStream_t)stream;
-    labfm_err e = ensure(c->worklist, sizeof(int32_t) * (size_t)(n + 3 * (LABFM_MAX_ORDER + 2)));
+}
+
+}  // namespace
+
+labfm_err labfm_weights(void* ctx, const double* x, const double* y, int64_t n, const labfm_domain* dom,
+                        const double* R, const int8_t* order, const int64_t* row_ptr, const int32_t* col,
+                        int64_t nnz, const labfm_wopts* opt, double* w64, float* w32, int8_t* status, float* resid,
+                        int8_t* iters, void* stream) {
+    if (!ctx) return fail(LABFM_EINVAL, "labfm_weights: ctx is NULL");
+    labfm_err e = check_weights_args("labfm_weights", x, y, n, dom, R, order, row_ptr, col, nnz, opt, w64, w32, status);
     if (e != LABFM_OK) return e;
+    if (opt->prec == LABFM_PREC_MLP) {
+        std::string why;
+        if (!mlp_serves(opt->mlp, why)) return fail(LABFM_EINVAL, "labfm_weights: network: " + why);
+        if (opt->mlp->ops != opt->ops) return fail(LABFM_EINVAL, "labfm_weights: network ops differ from opt->ops");
+    }
+    Context* c = (Context*)ctx;
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(LABFM_EHIP, "labfm_weights: hipSetDevice failed");
+    if (n == 0) return LABFM_OK;
+    WeightArgs a;
+    one_set_args(a, x, y, n, dom, R, order, row_ptr, col, nnz, opt, w64, w32, status, resid, iters);
+    hipStream_t st = (hipStream_t)stream;
+    if ((e = ensure(c->worklist, sizeof(int32_t) * (size_t)(n + 3 * (LABFM_MAX_ORDER + 2)))) != LABFM_OK) return e;
     int32_t* wl = (int32_t*)c->worklist.p;
     if (opt->prec == LABFM_PREC_FP64) return weights_fp64(c, a, &a.one, wl, st);
     if ((e = ensure(c->mixed, sizeof(int32_t) * (size_t)(n + LABFM_MAX_ORDER + 2))) != LABFM_OK) return e;
@@ -347,7 +368,7 @@ labfm_err labfm_weights_batched(void* ctx, int nsets, const labfm_node_set* sets
     if (opt->abf < LABFM_ABF_HERMITE || opt->abf > LABFM_ABF_PAPER_D1) return fail(LABFM_EINVAL, "labfm_weights_batched: bad abf");
     if (opt->rbf < 0 || opt->rbf > 4) return fail(LABFM_EINVAL, "labfm_weights_batched: bad rbf");
     if (!(opt->sigma > 0.0) || !std::isfinite(opt->sigma)) return fail(LABFM_EINVAL, "labfm_weights_batched: sigma must be > 0");
-    if (opt->max_iters < 0 || opt->max_iters > 100) return fail(LABFM_EINVAL, "labfm_weights_batched: max_iters out of range");
+    if (opt->max_iters < 0 || opt->max_iters > 63) return fail(LABFM_EINVAL, "labfm_weights_batched: max_iters must be in 0..63");
     if (!(opt->tol_stop >= 0.0) || !(opt->tol_pass >= 0.0)) return fail(LABFM_EINVAL, "labfm_weights_batched: bad tolerances");
     if (opt->prec == LABFM_PREC_MLP) return fail(LABFM_EUNSUPPORTED, "labfm_weights_batched: LABFM_PREC_MLP is not batched");
     if (opt->prec != LABFM_PREC_FP64 && opt->prec != LABFM_PREC_MIXED) return fail(LABFM_EINVAL, "labfm_weights_batched: bad prec");

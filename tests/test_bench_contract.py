@@ -65,9 +65,14 @@ def test_unknown_kernel_has_no_traffic():
 
 
 def test_weight_flops_terms():
-    # assembly 2Np^2, LU 2p^3/3, (1 + it) x [solve 2 nd p^2 + weights 2 N p nd + residual 2 N p nd]
+    # basis 10Np, assembly 2Np^2, LU 2p^3/3, (1 + it) x [solve 2 nd p^2 + weights 2 N p nd + residual 2 N p nd]
     N, p, nd = 60, 44, 3
-    assert bench.weight_flops(N, p, nd, 0) == pytest.approx(2 * N * p * p + 2 * p ** 3 / 3 + 2 * nd * p * p
-                                                            + 4 * N * p * nd)
+    assert bench.weight_flops(N, p, nd, 0) == pytest.approx(10 * N * p + 2 * N * p * p + 2 * p ** 3 / 3
+                                                            + 2 * nd * p * p + 4 * N * p * nd)
     step = bench.weight_flops(N, p, nd, 1) - bench.weight_flops(N, p, nd, 0)
     assert step == pytest.approx(2 * nd * p * p + 4 * N * p * nd)
+
+
+def test_cpu_model_reports_processor_count():
+    name, nproc = bench.cpu_model()
+    assert isinstance(name, str) and nproc >= 1

@@ -117,6 +117,15 @@ def test_batched_graph_replays_match(env, batch):
             assert np.array_equal(o[2].cpu().numpy(), first_st[t]), (rep, t)
 
 
+def _split_window(res, res_o):
+    """Nodes where an OK / NOT_CONVERGED split between the GPU and the oracle is
+    a rounding-order effect at the 1e-10 gate: both final residuals at most
+    3e-10 and one of them within a factor of three of the gate.  A GPU node
+    left above 3e-10 is never excused, whatever the oracle's residual."""
+    lo, hi = 1e-10 / 3, 3e-10
+    return (res <= hi) & (res_o <= hi) & (((res > lo) & (res < hi)) | ((res_o > lo) & (res_o < hi)))
+
+
 def test_batched_fp64_equals_single_set(env, batch):
     torch = env["torch"]
     L = env["L"]
@@ -135,9 +144,10 @@ def test_batched_fp64_equals_single_set(env, batch):
 def test_batched_full_64_sets(env):
     """The benchmark's batch at full size (64 sets, 3.49 M nodes, orders 2-8,
     mixed precision with autotuned routes, one graph launch) against the oracle
-    set by set: statuses equal except OK / NOT_CONVERGED splits where either
-    side's residual sits within a factor of three of the 1e-10 gate (rounding
-    order decides those: refinement stalls at the rounding floor); every GPU node
+    set by set: statuses equal except OK / NOT_CONVERGED splits where both
+    residuals are at most 3e-10 and one of them sits within a factor of three of
+    the 1e-10 gate (rounding order decides those: refinement stalls at the
+    rounding floor), at most one such split per 100,000 nodes (10 allowed); every GPU node
     with status OK at the gate; weight parity <= 1e-10 on a 2,000-row sample
     of every set (at most one row per 10,000 above, none above 1e-8)."""
     torch = env["torch"]
@@ -165,7 +175,7 @@ def test_batched_full_64_sets(env):
         st = o[2].cpu().numpy()
         res = o[3].cpu().numpy().astype(np.float64)
         diff = st != st_o
-        near = ((res > 1e-10 / 3) & (res < 3e-10)) | ((res_o > 1e-10 / 3) & (res_o < 3e-10))
+        near = _split_window(res, res_o)
         assert np.all(near[diff]), [(j, st[j], res[j], st_o[j], res_o[j]) for j in np.nonzero(diff & ~near)[0]]
         assert np.all(np.isin(st[diff], (0, 1)) & np.isin(st_o[diff], (0, 1)))
         borderline += int(diff.sum())
@@ -185,3 +195,4 @@ def test_batched_full_64_sets(env):
     _say("  full batch: %d nodes, %d borderline status differences, sampled parity max %.2e (%d of %d above 1e-10)" %
          (n_total, borderline, worst, above, sampled))
     assert above <= max(1, sampled // 10000) and worst <= 1e-8
+    assert borderline <= max(10, n_total // 100000)

@@ -59,7 +59,8 @@ def _gpu_max_re(env, k, hdr, eps, seed):
     assert np.array_equal(rp, rpo) and np.array_equal(col, colo)
     # usable operators on the same nodes, except where a residual sits at the gate
     split = (st == O.ST_OK) != (sto == O.ST_OK)
-    near = ((res > 1e-10 / 3) & (res < 3e-10)) | ((reso > 1e-10 / 3) & (reso < 3e-10))
+    lo, hi = 1e-10 / 3, 3e-10  # both at most 3e-10, one within 3x of the gate
+    near = (res <= hi) & (reso <= hi) & (((res > lo) & (res < hi)) | ((reso > lo) & (reso < hi)))
     assert np.all(near[split]), np.nonzero(split & ~near)
     both = np.nonzero((st == O.ST_OK) & (sto == O.ST_OK))[0]
     par = np.array([np.abs(w[rp[i]:rp[i + 1]] - wo[0][rp[i]:rp[i + 1]]).max() /

@@ -374,3 +374,66 @@ def test_hyperviscosity_targets(O):
         got6 = (f * w[1][s_:e_]).sum()
         assert got4 == pytest.approx(-b4, rel=1e-7, abs=1e-7 * np.abs(f * w[0][s_:e_]).sum())
         assert got6 == pytest.approx(b6, rel=1e-7, abs=1e-7 * np.abs(f * w[1][s_:e_]).sum())
+
+
+# --------------------------------------------------------------------------- P14
+def _equilibrated(M):
+    """Row-then-column max-abs scaling, as the solver description of eq. (lsys)
+    used throughout (rows scaled by 1/max|row|, then columns by 1/max|col|)."""
+    A = np.array(M, dtype=np.float64)
+    A = A * (1.0 / np.abs(A).max(axis=1))[:, None]
+    A = A * (1.0 / np.abs(A).max(axis=0))[None, :]
+    return A
+
+
+@pytest.mark.parametrize("k", [2, 3, 4, 5, 6, 7, 8])
+def test_cond1_matches_lapack(O, k):
+    """The oracle's 1-norm condition number of the equilibrated moment matrix
+    (used to excuse ill-conditioned outliers and to find the critical stencil
+    sizes of Sec. 3.2) against numpy/LAPACK's cond(., 1) of the same matrix,
+    rebuilt here from M: jittered lattice stencils and random scattered ones,
+    Hermite and PAPER_D1 families, well and badly conditioned."""
+    rng = np.random.default_rng(100 + k)
+    p = O.p_of_k(k)
+    hr = {2: 1.2, 3: 1.5, 4: 1.6, 5: 1.9, 6: 2.0, 7: 2.2, 8: 2.3}[k]
+    seen = []
+    for trial in range(12):
+        if trial % 2 == 0:
+            st = _lattice_stencil(2 * hr) / hr
+            st = st + rng.uniform(-0.35, 0.35, st.shape) / hr
+        else:
+            n = int(rng.integers(p, 3 * p))
+            r = 2.0 * np.sqrt(rng.uniform(0.0, 1.0, n))
+            th = rng.uniform(0.0, 2 * np.pi, n)
+            st = np.stack([r * np.cos(th), r * np.sin(th)], axis=1)
+        st = st[(np.hypot(st[:, 0], st[:, 1]) < 2.0) & (np.hypot(st[:, 0], st[:, 1]) > 0)]
+        if len(st) < p:
+            continue
+        kw = {} if trial % 3 else dict(family=O.ABF_PAPER_D1, rbf=O.RBF_QUADRATIC)
+        sigma = 1.5 if k == 2 else 1.0
+        r_ = O.node_weights(k, st[:, 0], st[:, 1], sigma=sigma, **kw)
+        if r_["status"] not in (O.ST_OK, O.ST_NOT_CONVERGED):
+            continue
+        ref = np.linalg.cond(_equilibrated(r_["M"]), 1)
+        seen.append(ref)
+        # both sides invert the same matrix: agreement to a few cond * 2^-53
+        assert r_["cond1"] == pytest.approx(ref, rel=1e-6 + 1e-13 * ref), (k, trial)
+    assert len(seen) >= 6
+    # the set spans conditioning: a planted mistake in the norm or the pivots shows
+    assert max(seen) > 10 * min(seen)
+
+
+def test_row_length_limit(O):
+    """The weights accept rows of up to O.NMAX (768) entries, an implementation
+    limit shared with the HIP library; longer rows get ST_TOO_MANY, zero
+    weights and an infinite residual."""
+    rng = np.random.default_rng(5)
+    for N, want in ((O.NMAX, O.ST_OK), (O.NMAX + 1, O.ST_TOO_MANY)):
+        r = 2.0 * np.sqrt(rng.uniform(0.01, 1.0, N))
+        th = rng.uniform(0.0, 2 * np.pi, N)
+        res = O.node_weights(4, r * np.cos(th), r * np.sin(th))
+        assert res["status"] == want
+        if want == O.ST_TOO_MANY:
+            assert np.all(res["what"] == 0) and math.isinf(res["resid"])
+        else:
+            assert res["resid"] <= 1e-10
