@@ -7,6 +7,9 @@ the library never does.
   holds the local weights w^L_ij at columns j and -sum_j w^L_ij on the
   diagonal; Dirichlet rows b (fixed[b] != 0) become identity rows
   (A_bb = 1, A_bj = 0), whose right-hand side is the boundary value.
+* `neumann_matrix`: the same system enlarged by one ghost row per Neumann
+  boundary node (Sec. 5.2, eq. neu): the ghost's row is its parent's discrete
+  normal derivative, n_x w^x + n_y w^y in difference form.
 * `bicgstab`: the stabilised bi-conjugate gradient method with a Jacobi
   (diagonal) preconditioner applied on the right, in the usual order of van
   der Vorst (1992): rho = (r0, r), beta = (rho/rho_old)(alpha/omega),
@@ -29,6 +32,33 @@ def laplacian_matrix(row_ptr, col, w, fixed=None):
         w[fx[rows]] = 0.0
         diag[fx] = 1.0
     A = sps.csr_matrix((w, (rows, np.asarray(col, np.int64))), shape=(n, n)) + sps.diags(diag)
+    return A.tocsr()
+
+
+def neumann_matrix(row_ptr, col, w_x, w_y, w_lap, parent, nx, ny, fixed=None):
+    """The enlarged global matrix of eq. (poisson_system) with the ghost rows of
+    Sec. 5.2: row i with parent[i] < 0 is node i's Laplacian row (identity where
+    fixed[i] != 0); ghost row g with parent p = parent[g] enforces eq. (neu) at
+    p, A_gj = n_x w^x_pj + n_y w^y_pj for j in p's stencil and
+    A_gp = -sum_j (n_x w^x_pj + n_y w^y_pj), with (n_x, n_y) = (nx[g], ny[g])
+    the inward unit normal at p.  Row structure and weights come from the
+    neighbour sets and local weights of every node, ghosts included."""
+    n = row_ptr.size - 1
+    A = laplacian_matrix(row_ptr, col, w_lap, fixed).tolil()
+    for g in np.nonzero(np.asarray(parent) >= 0)[0]:
+        p = int(parent[g])
+        A.rows[g] = []
+        A.data[g] = []
+        acc = {}
+        total = 0.0
+        for q in range(row_ptr[p], row_ptr[p + 1]):
+            wn = nx[g] * w_x[q] + ny[g] * w_y[q]
+            j = int(col[q])
+            acc[j] = acc.get(j, 0.0) + wn
+            total += wn
+        acc[p] = acc.get(p, 0.0) - total
+        for j in sorted(acc):
+            A[g, j] = acc[j]
     return A.tocsr()
 
 

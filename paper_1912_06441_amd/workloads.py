@@ -428,6 +428,82 @@ def poisson_system(x, y, fixed):
 
 
 # ---------------------------------------------------------------------------
+# Poisson's equation with Neumann walls (Sec. 5.2, eq. neu and the ghost rows)
+
+
+def neumann_square_nodes(side, eps_over_dr=0.5, seed=13):
+    """The unit square with Neumann walls at x = 0 and x = 1 and Dirichlet walls
+    at y = 0 and y = 1 (corners Dirichlet): a wall-conforming (side+1)^2 lattice
+    (interior nodes jittered at the paper's noise level, wall nodes only along
+    their wall), and for every Neumann wall node b a ghost node at
+    r_b - n_b dr outside the wall, n_b the inward unit normal.  Returns a dict:
+    x, y, s (= dr), kind (0 interior, 1 Dirichlet wall, 2 Neumann wall, 3 ghost),
+    parent (int32: the ghost's wall node, -1 elsewhere), nx, ny (at ghost rows:
+    the parent's inward normal; 0 elsewhere), domain (the square widened by dr
+    in x to hold the ghosts).  Ghosts follow the lattice nodes."""
+    x, y, s = wall_conforming_lattice(side + 1, eps=paper_jitter(eps_over_dr), seed=seed)
+    n = x.size
+    kind = np.zeros(n, np.int8)
+    onx = (x == 0.0) | (x == 1.0)
+    ony = (y == 0.0) | (y == 1.0)
+    kind[ony] = 1
+    kind[onx & ~ony] = 2
+    walls = np.nonzero(kind == 2)[0]
+    nxw = np.where(x[walls] == 0.0, 1.0, -1.0)  # inward normal of each Neumann wall node
+    gx = x[walls] - nxw * s
+    gy = y[walls].copy()
+    m = walls.size
+    x = np.concatenate([x, gx])
+    y = np.concatenate([y, gy])
+    kind = np.concatenate([kind, np.full(m, 3, np.int8)])
+    parent = np.concatenate([np.full(n, -1, np.int32), walls.astype(np.int32)])
+    nx = np.concatenate([np.zeros(n), nxw])
+    ny = np.zeros(n + m)
+    dom = {"lo": (-s, 0.0), "hi": (1.0 + s, 1.0), "periodic": (False, False)}
+    return dict(x=np.ascontiguousarray(x), y=np.ascontiguousarray(y), s=s, kind=kind, parent=parent,
+                nx=nx, ny=ny, domain=dom)
+
+
+def neumann_field(x, y):
+    """phi = sin(2x + 1/2) cos(3y/2 + 1/5) and its gradient and Laplacian
+    (-(4 + 9/4) phi): smooth, with non-zero Dirichlet and Neumann data."""
+    phi = np.sin(2 * x + 0.5) * np.cos(1.5 * y + 0.2)
+    px = 2 * np.cos(2 * x + 0.5) * np.cos(1.5 * y + 0.2)
+    py = -1.5 * np.sin(2 * x + 0.5) * np.sin(1.5 * y + 0.2)
+    return phi, px, py, -(4.0 + 2.25) * phi
+
+
+def neumann_poly(k):
+    """A polynomial of degree k (k = 2 or 4) with its gradient and Laplacian,
+    as callables of (x, y): the discrete operators reproduce it exactly."""
+    if k == 2:
+        return (lambda x, y: 0.7 + 0.3 * x - 0.4 * y + 0.5 * x * x - 0.2 * x * y + 0.9 * y * y,
+                lambda x, y: 0.3 + 1.0 * x - 0.2 * y,
+                lambda x, y: -0.4 - 0.2 * x + 1.8 * y,
+                lambda x, y: 1.0 + 1.8 + 0.0 * x)
+    return (lambda x, y: 0.2 + x - 0.5 * y + 0.3 * x ** 2 * y ** 2 - 0.25 * x ** 4 + 0.6 * x ** 3 * y - 0.1 * y ** 4,
+            lambda x, y: 1.0 + 0.6 * x * y ** 2 - x ** 3 + 1.8 * x ** 2 * y,
+            lambda x, y: -0.5 + 0.6 * x ** 2 * y + 0.6 * x ** 3 - 0.4 * y ** 3,
+            lambda x, y: 0.6 * y ** 2 - 3.0 * x ** 2 + 3.6 * x * y + 0.6 * x ** 2 - 1.2 * y ** 2)
+
+
+def neumann_system(nodes, phi, grad_x, grad_y, lap):
+    """Right-hand side of the enlarged eq. (poisson_system): f at interior and
+    Neumann wall rows, the exact value at Dirichlet rows, and at each ghost row
+    the parent's normal derivative n_b . grad phi (eq. neu); plus the initial
+    guess (exact value on Dirichlet rows, 0 elsewhere) and the Dirichlet mask."""
+    x, y, kind, parent = nodes["x"], nodes["y"], nodes["kind"], nodes["parent"]
+    F = lap(x, y).astype(np.float64) * np.ones_like(x)
+    d = kind == 1
+    F[d] = phi(x[d], y[d])
+    g = np.nonzero(kind == 3)[0]
+    p = parent[g]
+    F[g] = nodes["nx"][g] * grad_x(x[p], y[p]) + nodes["ny"][g] * grad_y(x[p], y[p])
+    x0 = np.where(d, phi(x, y), 0.0)
+    return F, x0, d.astype(np.int8)
+
+
+# ---------------------------------------------------------------------------
 # Taylor-Green vortices (Sec. 5.4)
 
 
