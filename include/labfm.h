@@ -205,6 +205,25 @@ labfm_err labfm_weights(void* ctx, const double* x, const double* y, int64_t n,
                         const labfm_wopts* opt, double* w64, float* w32, int8_t* status,
                         float* resid, int8_t* iters, void* stream);
 
+/* labfm_weights without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc): the same computation, kernels and results as
+ * labfm_weights, for opt->prec LABFM_PREC_FP64 or LABFM_PREC_MIXED
+ * (LABFM_PREC_MLP returns LABFM_EUNSUPPORTED).  Its work lists live in a
+ * fixed library array of (2 LABFM_NOALLOC_MAX_NODES + 40) int32 (about 8 MiB)
+ * that every GPU the library runs on holds until the process ends; n above
+ * LABFM_NOALLOC_MAX_NODES returns LABFM_EINVAL.  Every call on one GPU shares
+ * that array (it keeps the last call's contents; what must start at zero is
+ * cleared by a kernel inside the call), so calls that overlap in time on one
+ * GPU race: issue them on one stream, or order them.  No kernel timing is
+ * recorded.  Arguments, layouts and outputs as labfm_weights; asynchronous. */
+#define LABFM_NOALLOC_MAX_NODES (1 << 20)
+labfm_err labfm_weights_noalloc(void* ctx, const double* x, const double* y, int64_t n,
+                                const labfm_domain* dom, const double* R, const int8_t* order,
+                                const int64_t* row_ptr, const int32_t* col, int64_t nnz,
+                                const labfm_wopts* opt, double* w64, float* w32, int8_t* status,
+                                float* resid, int8_t* iters, void* stream);
+
 /* Batched weights: nsets independent node sets, each with its own arrays,
  * domain and outputs (layouts as in labfm_weights; col holds indices within
  * the set).  One persistent kernel per order covers the nodes of every set,

@@ -20,6 +20,7 @@ RBF_WENDLAND_C2, RBF_CONE, RBF_QUADRATIC, RBF_WENDLAND_C6, RBF_GAUSSIAN = 0, 1, 
 OP_DX, OP_DY, OP_LAP, OP_BIHARM, OP_TRIHARM = 1, 2, 4, 8, 16
 OP_DZ = 32  # three-dimensional calls only
 PREC_FP64, PREC_MIXED, PREC_MLP = 0, 1, 2
+NOALLOC_MAX_NODES = 1 << 20  # largest n of labfm_weights_noalloc
 ST_OK, ST_NOT_CONVERGED, ST_SINGULAR, ST_TOO_FEW, ST_DEGENERATE, ST_ORDER_TOO_LOW, ST_TOO_MANY = range(7)
 MAX_NEIGHBOURS = 128
 EXPORTED = sorted(["labfm_last_error", "labfm_create", "labfm_destroy", "labfm_build_neighbours", "labfm_weights",
@@ -27,7 +28,8 @@ EXPORTED = sorted(["labfm_last_error", "labfm_create", "labfm_destroy", "labfm_b
                    "labfm_timing_read", "labfm_mlp_features", "labfm_mlp_forward", "labfm_mlp_cache_floats",
                    "labfm_mlp_backward", "labfm_mlp_moment_loss", "labfm_mlp_adam", "labfm_mlp_cast_bf16",
                    "labfm_weights_batched", "labfm_autotune_query", "labfm_burgers_step",
-                   "labfm_poisson_solve", "labfm_ns_step", "labfm_build_neighbours3", "labfm_weights3"])
+                   "labfm_poisson_solve", "labfm_ns_step", "labfm_build_neighbours3", "labfm_weights3",
+                   "labfm_weights_noalloc"])
 MLP_MAX_LAYERS = 8
 
 
@@ -111,6 +113,7 @@ def load_library(path=LIB_PATH):
                                          C.POINTER(i64), vp]
     L.labfm_weights.argtypes = [vp, vp, vp, i64, C.POINTER(Domain), vp, vp, vp, vp, i64, C.POINTER(WOpts), vp, vp,
                                 vp, vp, vp, vp]
+    L.labfm_weights_noalloc.argtypes = L.labfm_weights.argtypes
     L.labfm_combine.argtypes = [vp, vp, C.c_int, C.POINTER(dp), i64, vp, vp, vp]
     L.labfm_build_neighbours3.argtypes = [vp, vp, vp, vp, i64, C.POINTER(Domain3), vp, vp, vp, C.POINTER(i64), vp]
     L.labfm_weights3.argtypes = [vp, vp, vp, vp, i64, C.POINTER(Domain3), vp, C.c_int, vp, vp, i64,
@@ -309,11 +312,13 @@ class Context:
     # ------------------------------------------------------------------ weights
     def weights(self, x, y, R, order, row_ptr, col, domain, ops=OP_DX | OP_DY | OP_LAP, abf=ABF_HERMITE,
                 rbf=RBF_WENDLAND_C2, sigma=1.0, prec=PREC_FP64, tol_stop=1e-13, tol_pass=1e-10, max_iters=5,
-                want64=True, want32=False, out=None, mlp=None):
+                want64=True, want32=False, out=None, mlp=None, noalloc=False):
         """Weights [nops, nnz] (FP64 and/or FP32), status[n] int8, resid[n] f32, iters[n] int8.
 
         prec=PREC_MLP starts the refinement of the network's order from
-        `mlp` (an MLP) instead of from a first solve."""
+        `mlp` (an MLP) instead of from a first solve.  noalloc=True calls
+        labfm_weights_noalloc (no library allocation; the outputs are still
+        allocated here unless `out` is given)."""
         torch = self.torch
         n = x.numel()
         nnz = col.numel()
@@ -345,9 +350,10 @@ class Context:
             desc = mlp.desc()
             o.mlp = C.pointer(desc)
         dom = make_domain(domain)
-        _check(self.lib.labfm_weights(self.h, _ptr(x), _ptr(y), n, C.byref(dom), _ptr(R), _ptr(order),
-                                      _ptr(row_ptr), _ptr(col), nnz, C.byref(o), _ptr(w64), _ptr(w32),
-                                      _ptr(status), _ptr(resid), _ptr(iters), _stream(torch)), "labfm_weights")
+        fn = self.lib.labfm_weights_noalloc if noalloc else self.lib.labfm_weights
+        _check(fn(self.h, _ptr(x), _ptr(y), n, C.byref(dom), _ptr(R), _ptr(order), _ptr(row_ptr), _ptr(col), nnz,
+                  C.byref(o), _ptr(w64), _ptr(w32), _ptr(status), _ptr(resid), _ptr(iters), _stream(torch)),
+               "labfm_weights_noalloc" if noalloc else "labfm_weights")
         return w64, w32, status, resid, iters
 
     def weights_batched(self, sets, ops=OP_DX | OP_DY | OP_LAP, abf=ABF_HERMITE, rbf=RBF_WENDLAND_C2, sigma=1.0,

@@ -2,6 +2,8 @@
 // argument validation, context and scratch management, launch dispatch.
 #include "labfm_internal.hpp"
 
+#include <mutex>
+
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -162,11 +164,17 @@ extern "C" {
 
 const char* labfm_last_error(void) { return g_last_error.c_str(); }
 
+namespace {
+labfm_err scratch_setup(int device);
+}
+
 labfm_err labfm_create(void** ctx, int device) {
     if (!ctx) return fail(LABFM_EINVAL, "labfm_create: ctx is NULL");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(LABFM_EHIP, "labfm_create: no HIP device");
     if (device < 0 || device >= ndev) return fail(LABFM_EINVAL, "labfm_create: bad device id");
+    labfm_err e = scratch_setup(device);
+    if (e != LABFM_OK) return e;
     Context* c = new Context();
     c->device = device;
     *ctx = c;
@@ -277,7 +285,7 @@ labfm_err labfm_weights3(void* ctx, const double* x, const double* y, const doub
 
 namespace {
 
-// Argument checks of the weights entry points (`who`
+// Argument checks shared by labfm_weights and labfm_weights_noalloc (`who`
 // prefixes the message), and the WeightArgs of the call's one node set.
 labfm_err check_weights_args(const char* who, const double* x, const double* y, int64_t n, const labfm_domain* dom,
                              const double* R, const int8_t* order, const int64_t* row_ptr, const int32_t* col,
@@ -330,6 +338,34 @@ void one_set_args(WeightArgs& a, const double* x, const double* y, int64_t n, co
     set_options(a, opt);
 }
 
+// ---- the weights entry point that allocates nothing -----------------------
+// Its work lists (n + 3 (KMAX + 2) int32) and the mixed path's retry list
+// (n + KMAX + 2 int32) live in this file-scope array, one copy per GPU, held
+// until the process ends.  Host code never passes the array's name to a
+// kernel: each device's address comes from hipGetSymbolAddress, taken once
+// per device in labfm_create with that device current.
+constexpr int64_t NOALLOC_MAX_NODES = LABFM_NOALLOC_MAX_NODES;
+constexpr int64_t NOALLOC_WL_INTS = NOALLOC_MAX_NODES + 3 * (LABFM_MAX_ORDER + 2);
+constexpr int64_t NOALLOC_RL_INTS = NOALLOC_MAX_NODES + (LABFM_MAX_ORDER + 2);
+static __device__ __align__(256) int32_t scratch[NOALLOC_WL_INTS + NOALLOC_RL_INTS];
+constexpr int NOALLOC_MAX_DEVICES = 64;
+int32_t* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+std::mutex g_scratch_mu;
+
+labfm_err scratch_setup(int device) {
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) return fail(LABFM_EINVAL, "labfm_create: device id above 63");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return LABFM_OK;
+    DeviceGuard g(device);
+    if (!g.ok) return fail(LABFM_EHIP, "labfm_create: hipSetDevice failed");
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+        return fail(LABFM_EHIP, std::string("labfm_create: hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[device] = (int32_t*)p;
+    return LABFM_OK;
+}
+
 }  // namespace
 
 labfm_err labfm_weights(void* ctx, const double* x, const double* y, int64_t n, const labfm_domain* dom,
@@ -358,6 +394,41 @@ labfm_err labfm_weights(void* ctx, const double* x, const double* y, int64_t n, 
     int32_t* rl = (int32_t*)c->mixed.p;
     if (opt->prec == LABFM_PREC_MIXED) return weights_mixed(c, a, &a.one, wl, rl, 0u, st);
     return weights_mlp(c, a, wl, rl, opt->mlp, st);
+}
+
+labfm_err labfm_weights_noalloc(void* ctx, const double* x, const double* y, int64_t n, const labfm_domain* dom,
+                                const double* R, const int8_t* order, const int64_t* row_ptr, const int32_t* col,
+                                int64_t nnz, const labfm_wopts* opt, double* w64, float* w32, int8_t* status,
+                                float* resid, int8_t* iters, void* stream) {
+    if (!ctx) return fail(LABFM_EINVAL, "labfm_weights_noalloc: ctx is NULL");
+    labfm_err e =
+        check_weights_args("labfm_weights_noalloc", x, y, n, dom, R, order, row_ptr, col, nnz, opt, w64, w32, status);
+    if (e != LABFM_OK) return e;
+    if (opt->prec == LABFM_PREC_MLP)
+        return fail(LABFM_EUNSUPPORTED, "labfm_weights_noalloc: LABFM_PREC_MLP needs library scratch; use labfm_weights");
+    if (n > NOALLOC_MAX_NODES)
+        return fail(LABFM_EINVAL, "labfm_weights_noalloc: n = " + std::to_string(n) + " exceeds LABFM_NOALLOC_MAX_NODES (" +
+                                      std::to_string(NOALLOC_MAX_NODES) + ")");
+    Context* c = (Context*)ctx;
+    int32_t* base = (c->device >= 0 && c->device < NOALLOC_MAX_DEVICES) ? g_scratch_ptr[c->device] : nullptr;
+    if (!base) return fail(LABFM_EINVAL, "labfm_weights_noalloc: no scratch address for this device (context not from labfm_create)");
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(LABFM_EHIP, "labfm_weights_noalloc: hipSetDevice failed");
+    if (n == 0) return LABFM_OK;
+    WeightArgs a;
+    one_set_args(a, x, y, n, dom, R, order, row_ptr, col, nnz, opt, w64, w32, status, resid, iters);
+    // kernel timing records HIP events, which this entry point does not create
+    struct TimingOff {
+        Context* c;
+        bool was;
+        explicit TimingOff(Context* cc) : c(cc), was(cc->timing) { c->timing = false; }
+        ~TimingOff() { c->timing = was; }
+    } off(c);
+    hipStream_t st = (hipStream_t)stream;
+    int32_t* wl = base;                    // work lists: counters are cleared by a kernel inside
+    int32_t* rl = base + NOALLOC_WL_INTS;  // retry list of the mixed path: the same
+    if (opt->prec == LABFM_PREC_FP64) return weights_fp64(c, a, &a.one, wl, st);
+    return weights_mixed(c, a, &a.one, wl, rl, 0u, st);
 }
 
 labfm_err labfm_weights_batched(void* ctx, int nsets, const labfm_node_set* sets, const labfm_wopts* opt,
