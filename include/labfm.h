@@ -359,7 +359,34 @@ typedef struct {
     double tol;             /* relative residual target, > 0                 */
     int max_iters;          /* >= 0                                          */
     int check_every;        /* iterations between host reads of the residual */
+    const int32_t* center;  /* device int32 [n], values in [0, n), or NULL: row i
+                               takes its differences about node center[i]
+                               (Neumann ghost rows, see labfm_neumann_rows);
+                               NULL: about node i itself.  Not range-checked,
+                               like col */
 } labfm_poisson_plan;
+
+/* Rows of the global system enlarged by Neumann ghost rows (Sec. 5.2, eq. neu):
+ * every node b on a Neumann boundary has a ghost node (outside the boundary,
+ * part of the node set and of the neighbour sets), whose row enforces the
+ * boundary condition at b through b's discrete normal derivative,
+ *   A_gj = n_x w^x_bj + n_y w^y_bj (j in b's stencil), A_gb = -sum_j A_gj,
+ * with (n_x, n_y) the unit normal at b pointing into the domain; every other
+ * node keeps its own row with its Laplacian weights.  Inputs: the neighbour
+ * sets of every node (row_ptr int64 [n+1], col int32 [nnz]) and its FP64 d/dx,
+ * d/dy and Laplacian weights (w_x, w_y, w_lap [nnz]); parent int32 [n]: the
+ * boundary node of a ghost, -1 for every other node (a value outside [0, n)
+ * counts as -1); nx, ny FP64 [n]: the inward normal, read at ghost rows.
+ * Outputs, in two passes as labfm_build_neighbours: out_col == NULL fills
+ * out_row_ptr [n+1] and *nnz_host (synchronises stream); then out_col int32,
+ * out_w FP64 [nnz_out] and out_center int32 [n] (out_center[g] = b for a
+ * ghost, out_center[i] = i otherwise) for labfm_poisson_plan.  The right-hand
+ * side of a ghost row is the Neumann datum at b.  All arrays device memory;
+ * asynchronous (fill pass). */
+labfm_err labfm_neumann_rows(void* ctx, const int64_t* row_ptr, const int32_t* col, int64_t n, int64_t nnz,
+                             const double* w_x, const double* w_y, const double* w_lap, const int32_t* parent,
+                             const double* nx, const double* ny, int64_t* out_row_ptr, int32_t* out_col,
+                             double* out_w, int32_t* out_center, int64_t* nnz_host, void* stream);
 
 /* Solve in place: phi (device FP64 [n]) holds the initial guess on entry and
  * the solution on exit; F (device FP64 [n]) is not modified.  scratch: device,

@@ -29,7 +29,7 @@ EXPORTED = sorted(["labfm_last_error", "labfm_create", "labfm_destroy", "labfm_b
                    "labfm_mlp_backward", "labfm_mlp_moment_loss", "labfm_mlp_adam", "labfm_mlp_cast_bf16",
                    "labfm_weights_batched", "labfm_autotune_query", "labfm_burgers_step",
                    "labfm_poisson_solve", "labfm_ns_step", "labfm_build_neighbours3", "labfm_weights3",
-                   "labfm_weights_noalloc"])
+                   "labfm_weights_noalloc", "labfm_neumann_rows"])
 MLP_MAX_LAYERS = 8
 
 
@@ -78,7 +78,7 @@ class BurgersPlan(C.Structure):
 class PoissonPlan(C.Structure):
     _fields_ = [("row_ptr", C.c_void_p), ("col", C.c_void_p), ("n", C.c_int64), ("nnz", C.c_int64),
                 ("w_lap", C.c_void_p), ("fixed", C.c_void_p), ("tol", C.c_double), ("max_iters", C.c_int),
-                ("check_every", C.c_int)]
+                ("check_every", C.c_int), ("center", C.c_void_p)]
 
 
 class NSPlan(C.Structure):
@@ -123,6 +123,7 @@ def load_library(path=LIB_PATH):
     L.labfm_burgers_step.argtypes = [vp, C.POINTER(BurgersPlan), vp, vp, vp, C.c_int, C.c_int, vp]
     L.labfm_ns_step.argtypes = [vp, C.POINTER(NSPlan), vp, vp, vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                 vp]
+    L.labfm_neumann_rows.argtypes = [vp, vp, vp, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.POINTER(i64), vp]
     L.labfm_poisson_solve.argtypes = [vp, C.POINTER(PoissonPlan), vp, vp, vp, C.POINTER(C.c_int),
                                       C.POINTER(C.c_double), C.POINTER(C.c_int), vp]
     L.labfm_mlp_features.argtypes = [vp, vp, vp, i64, C.POINTER(Domain), vp, vp, vp, C.c_int, vp, vp]
@@ -516,11 +517,39 @@ class Context:
                                            int(bool(use_graph)), _stream(torch)), "labfm_burgers_step")
         return u, v
 
+    def neumann_rows(self, row_ptr, col, w_x, w_y, w_lap, parent, nx, ny):
+        """Rows of the global system with Neumann ghost rows (Sec. 5.2): a node
+        with parent[g] = b >= 0 gets b's normal-derivative row along (nx[g],
+        ny[g]), every other node its Laplacian row.  Returns (row_ptr, col, w,
+        center) for poisson_solve(..., center=center)."""
+        torch = self.torch
+        n = row_ptr.numel() - 1
+        _need_csr(torch, row_ptr, col, n)
+        for nm, t in (("w_x", w_x), ("w_y", w_y), ("w_lap", w_lap)):
+            _need(nm, t, torch.float64, col.numel())
+        _need("parent", parent, torch.int32, n)
+        _need("nx", nx, torch.float64, n)
+        _need("ny", ny, torch.float64, n)
+        dev = row_ptr.device
+        orp = torch.empty(n + 1, dtype=torch.int64, device=dev)
+        nnz = C.c_int64(0)
+        st = _stream(torch)
+        args = (self.h, _ptr(row_ptr), _ptr(col), n, col.numel(), _ptr(w_x), _ptr(w_y), _ptr(w_lap), _ptr(parent),
+                _ptr(nx), _ptr(ny), _ptr(orp))
+        _check(self.lib.labfm_neumann_rows(*args, None, None, None, C.byref(nnz), st), "labfm_neumann_rows(count)")
+        ocol = torch.empty(max(nnz.value, 1), dtype=torch.int32, device=dev)
+        ow = torch.empty(max(nnz.value, 1), dtype=torch.float64, device=dev)
+        ocen = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        _check(self.lib.labfm_neumann_rows(*args, _ptr(ocol), _ptr(ow), _ptr(ocen), None, st),
+               "labfm_neumann_rows(fill)")
+        return orp, ocol[:nnz.value], ow[:nnz.value], ocen[:n]
+
     def poisson_solve(self, row_ptr, col, w_lap, F, phi=None, fixed=None, tol=1e-10, max_iters=10000,
-                      check_every=16, scratch=None):
+                      check_every=16, scratch=None, center=None):
         """Solve A^L phi = F (FP64, Jacobi-BiCGStab on the GPU); rows with
-        fixed != 0 are identity rows.  Returns (phi, iterations, relative
-        residual, converged)."""
+        fixed != 0 are identity rows; with center (from neumann_rows) row i
+        takes its differences about node center[i].  Returns (phi,
+        iterations, relative residual, converged)."""
         torch = self.torch
         n = F.numel()
         if F.dtype != torch.float64 or w_lap.dtype != torch.float64:
@@ -536,9 +565,11 @@ class Context:
         _need("scratch", scratch, torch.float64, 8 * n)
         if fixed is not None and (fixed.dtype != torch.int8 or fixed.numel() != n or not fixed.is_contiguous()):
             raise ValueError("fixed must be a contiguous int8 tensor of n entries")
+        if center is not None:
+            _need("center", center, torch.int32, n)
         plan = PoissonPlan(row_ptr.data_ptr(), col.data_ptr(), n, col.numel(), w_lap.data_ptr(),
                            fixed.data_ptr() if fixed is not None else None, float(tol), int(max_iters),
-                           int(check_every))
+                           int(check_every), center.data_ptr() if center is not None else None)
         it, res, conv = C.c_int(0), C.c_double(0.0), C.c_int(0)
         _check(self.lib.labfm_poisson_solve(self.h, C.byref(plan), _ptr(F), _ptr(phi), _ptr(scratch), C.byref(it),
                                             C.byref(res), C.byref(conv), _stream(torch)), "labfm_poisson_solve")

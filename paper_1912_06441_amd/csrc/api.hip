@@ -543,6 +543,33 @@ labfm_err labfm_poisson_solve(void* ctx, const labfm_poisson_plan* plan, const d
     return poisson_solve(c, plan, F, phi, (double*)scratch, iters, rel_resid, converged, (hipStream_t)stream);
 }
 
+labfm_err labfm_neumann_rows(void* ctx, const int64_t* row_ptr, const int32_t* col, int64_t n, int64_t nnz,
+                             const double* w_x, const double* w_y, const double* w_lap, const int32_t* parent,
+                             const double* nx, const double* ny, int64_t* out_row_ptr, int32_t* out_col,
+                             double* out_w, int32_t* out_center, int64_t* nnz_host, void* stream) {
+    if (!ctx) return fail(LABFM_EINVAL, "labfm_neumann_rows: ctx is NULL");
+    if (n < 0 || nnz < 0 || n > INT32_MAX) return fail(LABFM_EINVAL, "labfm_neumann_rows: n or nnz out of range");
+    if (!out_col && !nnz_host) return fail(LABFM_EINVAL, "labfm_neumann_rows: count pass needs nnz_host");
+    if (out_col && (!out_w || !out_center)) return fail(LABFM_EINVAL, "labfm_neumann_rows: fill pass needs out_w and out_center");
+    if (n > 0 && (!row_ptr || !out_row_ptr || (nnz > 0 && (!col || !w_x || !w_y || !w_lap)) || (parent && (!nx || !ny))))
+        return fail(LABFM_EINVAL, "labfm_neumann_rows: NULL array");
+    Context* c = (Context*)ctx;
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(LABFM_EHIP, "labfm_neumann_rows: hipSetDevice failed");
+    hipStream_t st = (hipStream_t)stream;
+    if (n == 0) {
+        if (!out_col) {
+            labfm_err e = exclusive_scan_i64(c, nullptr, out_row_ptr, 0, st);
+            if (e != LABFM_OK) return e;
+            *nnz_host = 0;
+            LABFM_HIP_CHECK(hipStreamSynchronize(st));
+        }
+        return LABFM_OK;
+    }
+    return neumann_rows(c, row_ptr, col, n, w_x, w_y, w_lap, parent, nx, ny, out_row_ptr, out_col, out_w, out_center,
+                        nnz_host, st);
+}
+
 labfm_err labfm_ns_step(void* ctx, const labfm_ns_plan* plan, double* omega, double* psi, void* scratch, int nsteps,
                         int* solver_iters, int* all_converged, void* stream) {
     if (!ctx || !plan) return fail(LABFM_EINVAL, "labfm_ns_step: ctx or plan is NULL");

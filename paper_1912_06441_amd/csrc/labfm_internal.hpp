@@ -240,6 +240,9 @@ labfm_err burgers_launch(Context* c, const labfm_burgers_plan* plan, void* u, vo
                          int use_graph, hipStream_t st);
 labfm_err poisson_solve(Context* c, const labfm_poisson_plan* plan, const double* F, double* phi, double* scratch,
                         int* iters, double* rel_resid, int* converged, hipStream_t st);
+labfm_err neumann_rows(Context* c, const int64_t* rp, const int32_t* col, int64_t n, const double* wx,
+                       const double* wy, const double* wl, const int32_t* parent, const double* nx, const double* ny,
+                       int64_t* orp, int32_t* ocol, double* ow, int32_t* ocenter, int64_t* nnz_host, hipStream_t st);
 labfm_err ns_step(Context* c, const labfm_ns_plan* plan, double* omega, double* psi, double* scratch, int nsteps,
                   int* solver_iters, int* all_converged, hipStream_t st);
 

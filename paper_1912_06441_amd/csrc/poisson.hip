@@ -49,11 +49,13 @@ __device__ inline double block_sum(double v, double* sh) {
 // against 0.41 ms at 16 x 4).
 constexpr int SG = 8, SU = 8;
 
-// y = A x (difference-form rows; identity rows where fixed[i] != 0)
+// y = A x (difference-form rows about center[i], or node i itself when center
+// is NULL; identity rows where fixed[i] != 0)
 __global__ __launch_bounds__(256) void k_spmv(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                                               int64_t n, const double* __restrict__ w,
-                                              const int8_t* __restrict__ fixed, const double* __restrict__ x,
-                                              double* __restrict__ y, const double* __restrict__ S) {
+                                              const int8_t* __restrict__ fixed, const int32_t* __restrict__ center,
+                                              const double* __restrict__ x, double* __restrict__ y,
+                                              const double* __restrict__ S) {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t row = gid / SG;
     const int sub = (int)(gid % SG);
@@ -62,25 +64,69 @@ __global__ __launch_bounds__(256) void k_spmv(const int64_t* __restrict__ rp, co
     // together, ahead of the dependent index and gather loads
     const bool stop = S && S[S_STOP] != 0.0;
     const int64_t s = rp[row], e = rp[row + 1];
-    const double xi = x[row];
+    const double xr = x[row];
+    const double xi = center ? x[center[row]] : xr;
     const bool ident = fixed && fixed[row];
     if (stop) return;
     WPtrs<double, 1> wp{{w}};
     double acc[1] = {0.0};
     row_sums<double, SG, SU, 1>(col, s, e, sub, wp, x, xi, acc);
     const double v = group_sum<double, SG>(acc[0]);
-    if (sub == 0) y[row] = ident ? xi : v;
+    if (sub == 0) y[row] = ident ? xr : v;
 }
 
-// inverse diagonal of A^L (1 on identity rows and where the diagonal is zero)
-__global__ void k_jacobi(const int64_t* __restrict__ rp, int64_t n, const double* __restrict__ w,
-                         const int8_t* __restrict__ fixed, double* __restrict__ dinv) {
+// inverse diagonal of A^L (1 on identity rows and where the diagonal is zero):
+// the coefficient of x_i in row i, sum_{col[q] = i} w[q] - [center_i = i] sum_q w[q]
+__global__ void k_jacobi(const int64_t* __restrict__ rp, const int32_t* __restrict__ col, int64_t n,
+                         const double* __restrict__ w, const int8_t* __restrict__ fixed,
+                         const int32_t* __restrict__ center, double* __restrict__ dinv) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const bool own = !center || center[i] == i;
     double d = 0.0;
-    for (int64_t q = rp[i]; q < rp[i + 1]; ++q) d -= w[q];
+    for (int64_t q = rp[i]; q < rp[i + 1]; ++q) {
+        if (own) d -= w[q];
+        if (col[q] == i) d += w[q];
+    }
     if (fixed && fixed[i]) d = 1.0;
     dinv[i] = d != 0.0 ? 1.0 / d : 1.0;
+}
+
+// ---- rows of the enlarged system with Neumann ghost rows (Sec. 5.2, eq. neu)
+__device__ inline int64_t nr_source(const int32_t* parent, int64_t i, int64_t n) {
+    const int64_t p = parent ? (int64_t)parent[i] : -1;
+    return (p >= 0 && p < n) ? p : i;  // an out-of-range parent counts as none
+}
+__global__ void k_nr_count(const int64_t* __restrict__ rp, const int32_t* __restrict__ parent, int64_t n,
+                           int64_t* __restrict__ len) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t src = nr_source(parent, i, n);
+    len[i] = rp[src + 1] - rp[src];
+}
+__global__ void k_nr_fill(const int64_t* __restrict__ rp, const int32_t* __restrict__ col, int64_t n,
+                          const double* __restrict__ wx, const double* __restrict__ wy,
+                          const double* __restrict__ wl, const int32_t* __restrict__ parent,
+                          const double* __restrict__ nx, const double* __restrict__ ny,
+                          const int64_t* __restrict__ orp, int32_t* __restrict__ ocol, double* __restrict__ ow,
+                          int32_t* __restrict__ ocenter) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t src = nr_source(parent, i, n);
+    const int64_t s = rp[src], e = rp[src + 1], o = orp[i];
+    if (src == i) {
+        for (int64_t q = s; q < e; ++q) {
+            ocol[o + (q - s)] = col[q];
+            ow[o + (q - s)] = wl[q];
+        }
+    } else {  // ghost row: the parent's normal derivative
+        const double a = nx[i], b = ny[i];
+        for (int64_t q = s; q < e; ++q) {
+            ocol[o + (q - s)] = col[q];
+            ow[o + (q - s)] = a * wx[q] + b * wy[q];
+        }
+    }
+    ocenter[i] = (int32_t)src;
 }
 
 // partial sums of a.b and (optionally) c.d over a fixed grid of DOT_BLOCKS
@@ -246,11 +292,11 @@ void enqueue_iteration(const labfm_poisson_plan* pl, double* x, const Bufs& b, h
     const unsigned nv = (unsigned)((n + 255) / 256);
     const unsigned nm = spmv_blocks(n);
     k_update_p<<<nv, 256, 0, st>>>(n, b.S, b.r, b.v, b.dinv, b.p, b.y);
-    k_spmv<<<nm, 256, 0, st>>>(pl->row_ptr, pl->col, n, pl->w_lap, pl->fixed, b.y, b.v, b.S);
+    k_spmv<<<nm, 256, 0, st>>>(pl->row_ptr, pl->col, n, pl->w_lap, pl->fixed, pl->center, b.y, b.v, b.S);
     k_dot2<<<DOT_BLOCKS, DOT_THREADS, 0, st>>>(b.r0, b.v, nullptr, nullptr, n, b.part, b.S);
     k_dot_final<<<1, FINAL_THREADS, 0, st>>>(b.part, DOT_BLOCKS, b.S, OP_RV);
     k_update_s<<<nv, 256, 0, st>>>(n, b.S, b.r, b.v, b.dinv, x, b.y, b.s);
-    k_spmv<<<nm, 256, 0, st>>>(pl->row_ptr, pl->col, n, pl->w_lap, pl->fixed, b.y, b.t, b.S);
+    k_spmv<<<nm, 256, 0, st>>>(pl->row_ptr, pl->col, n, pl->w_lap, pl->fixed, pl->center, b.y, b.t, b.S);
     k_dot2<<<DOT_BLOCKS, DOT_THREADS, 0, st>>>(b.t, b.s, b.t, b.t, n, b.part, b.S);
     k_dot_final<<<1, FINAL_THREADS, 0, st>>>(b.part, DOT_BLOCKS, b.S, OP_OMEGA);
     k_update_r<<<nv, 256, 0, st>>>(n, b.S, b.y, b.s, b.t, b.r0, x, b.r, b.part);
@@ -285,8 +331,8 @@ labfm_err poisson_solve(Context* c, const labfm_poisson_plan* pl, const double* 
         k_set_tol<<<1, 1, 0, st>>>(b.S, pl->tol * pl->tol);
         k_dot2<<<DOT_BLOCKS, DOT_THREADS, 0, st>>>(F, F, nullptr, nullptr, n, b.part, nullptr);
         k_dot_final<<<1, FINAL_THREADS, 0, st>>>(b.part, DOT_BLOCKS, b.S, OP_BB);
-        k_jacobi<<<nv, 256, 0, st>>>(pl->row_ptr, n, pl->w_lap, pl->fixed, b.dinv);
-        k_spmv<<<nm, 256, 0, st>>>(pl->row_ptr, pl->col, n, pl->w_lap, pl->fixed, x, b.t, nullptr);
+        k_jacobi<<<nv, 256, 0, st>>>(pl->row_ptr, pl->col, n, pl->w_lap, pl->fixed, pl->center, b.dinv);
+        k_spmv<<<nm, 256, 0, st>>>(pl->row_ptr, pl->col, n, pl->w_lap, pl->fixed, pl->center, x, b.t, nullptr);
         k_init<<<nv, 256, 0, st>>>(n, F, b.t, b.r, b.r0, b.p, b.v);
         k_dot2<<<DOT_BLOCKS, DOT_THREADS, 0, st>>>(b.r, b.r, nullptr, nullptr, n, b.part, nullptr);
         k_dot_final<<<1, FINAL_THREADS, 0, st>>>(b.part, DOT_BLOCKS, b.S, OP_RR0);
@@ -340,6 +386,26 @@ labfm_err poisson_solve(Context* c, const labfm_poisson_plan* pl, const double* 
     if (iters) *iters = (int)hs[S_ITERS];
     if (rel_resid) *rel_resid = hs[S_BB] > 0.0 ? std::sqrt(hs[S_RR] / hs[S_BB]) : 0.0;
     if (converged) *converged = hs[S_STOP] == 1.0 ? 1 : 0;
+    return LABFM_OK;
+}
+
+labfm_err neumann_rows(Context* c, const int64_t* rp, const int32_t* col, int64_t n, const double* wx,
+                       const double* wy, const double* wl, const int32_t* parent, const double* nx, const double* ny,
+                       int64_t* orp, int32_t* ocol, double* ow, int32_t* ocenter, int64_t* nnz_host, hipStream_t st) {
+    const unsigned nb = (unsigned)((n + 255) / 256);
+    if (!ocol) {  // count pass
+        labfm_err e = ensure(c->counts, sizeof(int64_t) * (size_t)n);
+        if (e != LABFM_OK) return e;
+        int64_t* len = (int64_t*)c->counts.p;
+        k_nr_count<<<nb, 256, 0, st>>>(rp, parent, n, len);
+        LABFM_HIP_CHECK(hipGetLastError());
+        if ((e = exclusive_scan_i64(c, len, orp, n, st)) != LABFM_OK) return e;
+        LABFM_HIP_CHECK(hipMemcpyAsync(nnz_host, orp + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        LABFM_HIP_CHECK(hipStreamSynchronize(st));
+        return LABFM_OK;
+    }
+    k_nr_fill<<<nb, 256, 0, st>>>(rp, col, n, wx, wy, wl, parent, nx, ny, orp, ocol, ow, ocenter);
+    LABFM_HIP_CHECK(hipGetLastError());
     return LABFM_OK;
 }
 
