@@ -21,8 +21,9 @@ OP_DX, OP_DY, OP_LAP, OP_BIHARM, OP_TRIHARM = 1, 2, 4, 8, 16
 OP_DZ = 32  # three dimensions only
 ST_OK, ST_NOT_CONVERGED, ST_SINGULAR, ST_TOO_FEW, ST_DEGENERATE, ST_ORDER_TOO_LOW, ST_TOO_MANY = range(7)
 NMAX = 128  # longest stencil row the weights accept (implementation limit; longer: ST_TOO_MANY)
-NMAX3 = 128  # the same in three dimensions
+NMAX3 = 256  # three dimensions (orders 5 and 6 need well over 100 neighbours)
 MAXK = 8
+MAXK3 = 6  # highest three-dimensional order
 
 
 class _Domain(C.Structure):

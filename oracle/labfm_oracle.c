@@ -921,7 +921,8 @@ void or_burgers_rk4(int64_t n, const int64_t* row_ptr, const int32_t* col, const
 
 /* ======================================================================== */
 /* Three dimensions.  Sec. 3.1: in 3-D, p is the sum of the triangular       */
-/* numbers 2..k+1 (3, 9, 19, 34 for k = 1..4).  Element order (a reading):    */
+/* numbers 2..k+1 (3, 9, 19, 34, 55, 83 for k = 1..6).  Element order (a     */
+/* reading):                                                                 */
 /* total order n = 1..k; within n, a = n..0, then b = n-a..0, c = n-a-b.      */
 /* X_m = x^a y^b z^c / (a! b! c!) (the Taylor coefficients, as eq. (1));      */
 /* ABFs of the HERMITE family H_a(s x) H_b(s y) H_c(s z) phi(|d|).            */
@@ -933,6 +934,7 @@ int or_p3_of_k(int k) {
 }
 
 void or_index_table3(int k, int* ea, int* eb, int* ec) {
+    if (k < 1 || k > OR_MAXK3) return;
     int m = 0;
     for (int n = 1; n <= k; ++n)
         for (int a = n; a >= 0; --a)
@@ -945,6 +947,7 @@ void or_index_table3(int k, int* ea, int* eb, int* ec) {
 }
 
 void or_monomials3(int k, double dx, double dy, double dz, double* X) {
+    if (k < 1 || k > OR_MAXK3) return;
     int ea[OR_MAXP], eb[OR_MAXP], ec[OR_MAXP];
     or_index_table3(k, ea, eb, ec);
     int p = or_p3_of_k(k);
@@ -958,6 +961,7 @@ void or_monomials3(int k, double dx, double dy, double dz, double* X) {
 }
 
 int or_abfs3(int rbf, double sigma, int k, double dx, double dy, double dz, double* W) {
+    if (k < 1 || k > OR_MAXK3) return -1;
     int ea[OR_MAXP], eb[OR_MAXP], ec[OR_MAXP];
     or_index_table3(k, ea, eb, ec);
     int p = or_p3_of_k(k);
@@ -1036,7 +1040,7 @@ static int node_weights3(int k, int N, const double* dxh, const double* dyh, con
     *resid = INFINITY;
     *iters = 0;
     for (int i = 0; i < nops * N; ++i) what[i] = 0.0;
-    if (k < 1 || p > OR_MAXP) return OR_ST_ORDER_TOO_LOW;
+    if (k < 1 || k > OR_MAXK3) return OR_ST_ORDER_TOO_LOW;
     for (int d = 0; d < nops; ++d) {
         double Ct[OR_MAXP];
         int l;

@@ -22,7 +22,10 @@
 #include <stdint.h>
 
 #define OR_MAXK 8
-#define OR_MAXP 44
+/* largest number of elements p: 44 for a 2-D scheme of order 8, 83 for a 3-D
+ * scheme of order 6 (the highest 3-D order here) */
+#define OR_MAXP 84
+#define OR_MAXK3 6
 
 /* ABF families: HERMITE = H_a(s dx) H_b(s dy) phi(|d|); PAPER = D^(a,b) W0(|d|)
  * with the App. A truncation (only the dW0/dr term for total order >= 4). */
@@ -38,9 +41,10 @@ enum { OR_ST_OK = 0, OR_ST_NOT_CONVERGED = 1, OR_ST_SINGULAR = 2, OR_ST_TOO_FEW 
 /* Longest stencil row the weights accept (an implementation limit, not the
  * paper's: the method itself takes any number of neighbours).  Longer rows get
  * OR_ST_TOO_MANY and zero weights, as the HIP library documents for its
- * LABFM_MAX_NEIGHBOURS; the same limit in two and three dimensions. */
+ * LABFM_MAX_NEIGHBOURS (2-D) and LABFM_MAX_NEIGHBOURS3 (3-D, where orders 5
+ * and 6 need 55 and 83 elements and so well over 100 neighbours). */
 #define OR_NMAX 128
-#define OR_NMAX3 128
+#define OR_NMAX3 256
 
 typedef struct {
     double lo[2], hi[2];

@@ -161,9 +161,10 @@ def config(name):
         "taylor_green": dict(abf=2, rbf=2, Re=100.0, h_over_dr=2.0, eps_paper=0.5, seed=17, tol=1e-10,
                              t_end=0.5, sides=(10, 20, 40, 80)),
         # three dimensions: periodic n^3 lattices, eps 0.3, Hermite (sigma 1.5) x Wendland C2, one
-        # order per set, R0 by order for mean N about 14, 29, 51, 82 (k = 1..4; p = 3, 9, 19, 34),
-        # no growth
-        "c3d": dict(eps=0.3, seed=21, sigma=1.5, R_s={1: 1.5, 2: 1.9, 3: 2.3, 4: 2.7}, bench_side=64, bench_k=4),
+        # order per set, R0 by order for mean N about 14, 29, 51, 82, 111, 165 (k = 1..6; p = 3, 9, 19,
+        # 34, 55, 83), no growth
+        "c3d": dict(eps=0.3, seed=21, sigma=1.5, R_s={1: 1.5, 2: 1.9, 3: 2.3, 4: 2.7, 5: 3.0, 6: 3.4}, bench_side=64,
+                    bench_k=4),
         "burgers": dict(abf=2, rbf=2, h_over_dr=2.0, Re=100.0, eps_paper=0.2, seed=11, t_end=0.4,
                         sides=(21, 41, 81, 161), Re_hv=250.0, hv_coef=100.0, hv_eps_paper=0.5, hv_side=81,
                         wave_ghost=6, wave_seed=13, wave_eps_paper=0.2),

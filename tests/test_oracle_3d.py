@@ -6,7 +6,7 @@
   random polynomial of degree k (sympy), which fixes the 1/(a! b! c!) factors.
 * Hermite ABFs against numpy's hermval product times the Wendland C2 factor.
 * Neighbour lists against scipy's periodic k-d tree.
-* Weights reproduce d/dx, d/dy, d/dz and the Laplacian of random polynomials
+* Weights (k = 1..6, p up to 83) reproduce d/dx, d/dy, d/dz and the Laplacian of random polynomials
   of degree <= k exactly, and converge at rates ~k (gradients), ~k-1
   (Laplacian) on a smooth field.
 """
@@ -28,7 +28,7 @@ def test_p3_matches_sec31(O):
         assert O.p3_of_k(k) == p
 
 
-@pytest.mark.parametrize("k", [1, 2, 3, 4])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6])
 def test_index_table3(O, k):
     idx = O.index_table3(k)
     want = {t for t in itertools.product(range(k + 1), repeat=3) if 1 <= sum(t) <= k}
@@ -36,8 +36,8 @@ def test_index_table3(O, k):
     assert [sum(t) for t in idx] == sorted(sum(t) for t in idx)
 
 
-def test_monomials3_are_taylor_coefficients(O):
-    k = 4
+@pytest.mark.parametrize("k", [4, 6])
+def test_monomials3_are_taylor_coefficients(O, k):
     xs, ys, zs = sp.symbols("x y z")
     rng = np.random.default_rng(2)
     P = sum(sp.Rational(int(rng.integers(-9, 10)), int(rng.integers(1, 5))) * xs ** a * ys ** b * zs ** c
@@ -50,10 +50,10 @@ def test_monomials3_are_taylor_coefficients(O):
         assert np.dot(X, D) == pytest.approx(lhs, rel=1e-12, abs=1e-12)
 
 
-def test_hermite_abfs3(O):
+@pytest.mark.parametrize("k", [4, 6])
+def test_hermite_abfs3(O, k):
     from numpy.polynomial import hermite as H
 
-    k = 4
     idx = O.index_table3(k)
     for d in np.random.default_rng(3).uniform(-1.2, 1.2, (5, 3)):
         for sigma in (1.0, 1.5):
@@ -80,10 +80,10 @@ def test_neighbours3_against_kdtree(O, periodic):
         assert set(want) <= set(got.tolist()) <= set(near)
 
 
-@pytest.mark.parametrize("k", [2, 3, 4])
-def test_weights3_reproduce_polynomials(O, k):
+@pytest.mark.parametrize("k,side", [(2, 8), (3, 8), (4, 8), (5, 10), (6, 12)])
+def test_weights3_reproduce_polynomials(O, k, side):
     cfg = WL.config("c3d")
-    x, y, z, s = WL.jittered_lattice3(8, eps=0.3, seed=5, periodic=False)
+    x, y, z, s = WL.jittered_lattice3(side, eps=0.3, seed=5, periodic=False)
     dom = WL.unit_domain3(False)
     R = cfg["R_s"][k] * s
     rp, col = O.neighbours3(x, y, z, dom, R)
@@ -111,7 +111,7 @@ def test_weights3_reproduce_polynomials(O, k):
         assert np.abs(got - exact[d])[ok].max() <= 1e-8 * scale * (1 / s) ** (2 if d == 2 else 1), d
 
 
-@pytest.mark.parametrize("k,rg,rl", [(2, 1.7, 0.9), (3, 2.6, 1.6), (4, 3.5, 2.4)])
+@pytest.mark.parametrize("k,rg,rl", [(2, 1.7, 0.9), (3, 2.6, 1.6), (4, 3.5, 2.4), (5, 4.5, 3.5), (6, 5.5, 4.5)])
 def test_weights3_convergence(O, k, rg, rl):
     cfg = WL.config("c3d")
     errs = []
@@ -127,3 +127,26 @@ def test_weights3_convergence(O, k, rg, rl):
                      for d, ref in enumerate((fx, fy, lap, fz))])
     r = np.log2(np.array(errs[0]) / np.array(errs[1]))
     assert min(r[0], r[1], r[3]) >= rg and r[2] >= rl, r
+
+
+def test_row_length_limit3(O):
+    """3-D rows of up to O.NMAX3 (256) entries are accepted (orders 5 and 6
+    need well over 100 neighbours); longer rows get ST_TOO_MANY, zero weights
+    and an infinite residual, as in two dimensions."""
+    rng = np.random.default_rng(6)
+    dom = WL.unit_domain3(False)
+    for N, want in ((O.NMAX3, O.ST_OK), (O.NMAX3 + 1, O.ST_TOO_MANY)):
+        v = rng.normal(size=(N, 3))
+        v *= (0.9 * 0.2 * rng.uniform(0.05, 1.0, N) ** (1 / 3) / np.linalg.norm(v, axis=1))[:, None]
+        pts = np.vstack([[0.5, 0.5, 0.5], 0.5 + v])
+        n = N + 1
+        rp = np.zeros(n + 1, np.int64)
+        rp[1:] = N
+        col = np.arange(1, n, dtype=np.int32)
+        R = np.full(n, 0.2)
+        w, st, res, _ = O.weights3(pts[:, 0], pts[:, 1], pts[:, 2], dom, R, 4, rp, col, sigma=1.5)
+        assert st[0] == want and np.all(st[1:] == O.ST_TOO_FEW)
+        if want == O.ST_TOO_MANY:
+            assert np.all(w == 0) and math.isinf(res[0])
+        else:
+            assert res[0] <= 1e-10

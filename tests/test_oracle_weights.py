@@ -424,7 +424,7 @@ def test_cond1_matches_lapack(O, k):
 
 
 def test_row_length_limit(O):
-    """The weights accept rows of up to O.NMAX (768) entries, an implementation
+    """The weights accept rows of up to O.NMAX (128) entries, an implementation
     limit shared with the HIP library; longer rows get ST_TOO_MANY, zero
     weights and an infinite residual."""
     rng = np.random.default_rng(5)
