@@ -97,13 +97,16 @@ enum {
     LABFM_ST_TOO_FEW = 3,        /* fewer neighbours than p; weights zero    */
     LABFM_ST_DEGENERATE = 4,     /* PAPER ABFs undefined (coincident node)   */
     LABFM_ST_ORDER_TOO_LOW = 5,  /* order cannot express a requested target  */
-    LABFM_ST_TOO_MANY = 6        /* more than LABFM_MAX_NEIGHBOURS neighbours:
+    LABFM_ST_TOO_MANY = 6        /* more than LABFM_MAX_NEIGHBOURS (2-D) or
+                                    LABFM_MAX_NEIGHBOURS3 (3-D) neighbours:
                                     weights zero (an implementation limit of
-                                    the weight kernels, 2-D and 3-D alike) */
+                                    the weight kernels) */
 };
 
 #define LABFM_MAX_ORDER 8
 #define LABFM_MAX_NEIGHBOURS 128
+#define LABFM_MAX_ORDER3 6
+#define LABFM_MAX_NEIGHBOURS3 256 /* 3-D orders 5 and 6 (p = 55, 83) need > 100 */
 
 /* Axis-aligned domain; periodic axes use the minimum-image offset. */
 typedef struct {
@@ -452,7 +455,8 @@ labfm_err labfm_build_neighbours3(void* ctx, const double* x, const double* y, c
                                   const labfm_domain3* dom, const double* R, int64_t* row_ptr, int32_t* col,
                                   int64_t* nnz_host, void* stream);
 
-/* 3-D weights of order k (1..4) for every node, FP64 (opt->prec must be
+/* 3-D weights of order k (1..LABFM_MAX_ORDER3 = 6; p = 3, 9, 19, 34, 55, 83,
+ * Sec. 3.1) for every node, FP64 (opt->prec must be
  * LABFM_PREC_FP64 and opt->abf LABFM_ABF_HERMITE, else LABFM_EUNSUPPORTED);
  * the refinement, status, residual and iteration outputs are those of
  * labfm_weights.  w64: device [nops][nnz]; status int8 [n]; resid FP32 [n]

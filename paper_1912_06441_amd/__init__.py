@@ -23,6 +23,8 @@ PREC_FP64, PREC_MIXED, PREC_MLP = 0, 1, 2
 NOALLOC_MAX_NODES = 1 << 20  # largest n of labfm_weights_noalloc
 ST_OK, ST_NOT_CONVERGED, ST_SINGULAR, ST_TOO_FEW, ST_DEGENERATE, ST_ORDER_TOO_LOW, ST_TOO_MANY = range(7)
 MAX_NEIGHBOURS = 128
+MAX_NEIGHBOURS3 = 256  # three-dimensional weights
+MAX_ORDER3 = 6
 EXPORTED = sorted(["labfm_last_error", "labfm_create", "labfm_destroy", "labfm_build_neighbours", "labfm_weights",
                    "labfm_combine", "labfm_apply_operator", "labfm_step", "labfm_timing_enable",
                    "labfm_timing_read", "labfm_mlp_features", "labfm_mlp_forward", "labfm_mlp_cache_floats",

@@ -264,7 +264,7 @@ labfm_err labfm_weights3(void* ctx, const double* x, const double* y, const doub
     if (!opt) return fail(LABFM_EINVAL, "labfm_weights3: opt is NULL");
     if (n < 0 || n > INT32_MAX || nnz < 0) return fail(LABFM_EINVAL, "labfm_weights3: n or nnz out of range");
     if (!domain3_ok(dom)) return fail(LABFM_EINVAL, "labfm_weights3: bad domain");
-    if (k < 1 || k > 4) return fail(LABFM_EINVAL, "labfm_weights3: k must be 1..4");
+    if (k < 1 || k > LABFM_MAX_ORDER3) return fail(LABFM_EINVAL, "labfm_weights3: k must be 1..6");
     const unsigned allowed = LABFM_OP_DX | LABFM_OP_DY | LABFM_OP_LAP | LABFM_OP_DZ;
     if (opt->ops == 0 || (opt->ops & ~allowed))
         return fail(LABFM_EINVAL, "labfm_weights3: ops must be a nonzero set of DX, DY, DZ, LAP");

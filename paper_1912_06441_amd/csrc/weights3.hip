@@ -1,12 +1,13 @@
 // weights3.hip -- per-node LABFM weights in three dimensions, FP64 (Sec. 3.1
-// of King, Lind & Nasar with the third coordinate: p = 3, 9, 19, 34 for
-// k = 1..4).  Element m is (a, b, c) over total order n = 1..k with a = n..0,
+// of King, Lind & Nasar with the third coordinate: p = 3, 9, 19, 34, 55, 83
+// for k = 1..6).  Element m is (a, b, c) over total order n = 1..k with a = n..0,
 // then b = n-a..0, c = n-a-b; X_m = x^a y^b z^c / (a! b! c!), ABFs of the
 // Hermite family H_a(s x) H_b(s y) H_c(s z) phi(|d|).  The node system is
 // built and solved as in the two-dimensional FP64 kernel: one wavefront per
 // node, M accumulated in registers from basis chunks in LDS, row/column
 // equilibration, partial-pivot LU in LDS, FP64 refinement on the moment
-// residual, unscaling by h^l.
+// residual, unscaling by h^l.  At k = 6 the system has more elements (83)
+// than a wavefront has lanes: k_weights3w gives each lane two rows.
 #include "weights_common.hpp"
 
 namespace labfm {
@@ -15,13 +16,14 @@ namespace {
 
 using namespace wk;
 
-constexpr int K3MAX = 4;
+constexpr int K3MAX = LABFM_MAX_ORDER3;
+constexpr int NM3 = LABFM_MAX_NEIGHBOURS3;  // longest 3-D row
 constexpr int p3_of_k(int k) {
     int p = 0;
     for (int m = 2; m <= k + 1; ++m) p += m * (m + 1) / 2;
     return p;
 }
-constexpr int P3MAX = p3_of_k(K3MAX);  // 34
+constexpr int P3MAX = p3_of_k(K3MAX);  // 83
 
 struct Elem3Table {
     int a[P3MAX], b[P3MAX], c[P3MAX];
@@ -95,6 +97,80 @@ __device__ inline double target3(unsigned op, int m) {
     return 0.0;
 }
 
+// M = sum_j X(d_j) W(d_j)^T into sM (row stride P + 1).  Lane (lr, lc) of an
+// 8 x 8 grid owns the BS x BS block at (lr BS, lc BS) of the padded matrix;
+// the block's rows are accumulated RB at a time (one pass over the basis
+// chunks per group of RB rows), which bounds the accumulator registers.  Each
+// entry sums over j in ascending order whatever RB is.
+template <int K, int RB>
+__device__ inline void assemble3(double* sM, double* sChunk, const double (*sD)[NM3], int N, int rbf, double sigma) {
+    constexpr int P = p3_of_k(K);
+    constexpr int BS = (P + 7) / 8;
+    constexpr int PP = 8 * BS;
+    constexpr int LD = P + 1;
+    const int lane = threadIdx.x;
+    const int lr = lane / 8, lc = lane % 8;
+    double* sX = sChunk;
+    double* sW = sChunk + CH * PP;
+#pragma unroll
+    for (int r0 = 0; r0 < BS; r0 += RB) {
+        double acc[RB][BS];
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int c = 0; c < BS; ++c) acc[r][c] = 0.0;
+        for (int j0 = 0; j0 < N; j0 += CH) {
+            if (lane < 2 * CH) {
+                const int jj = lane % CH;
+                const int j = j0 + jj;
+                double* dst = (lane < CH ? sX : sW) + jj * PP;
+                if (j < N) {
+                    Basis3<K> B;
+                    basis3_prepare<K>(B, sD[0][j], sD[1][j], sD[2][j], rbf, sigma);
+                    if (lane < CH) {
+#pragma unroll
+                        for (int m = 0; m < P; ++m) dst[m] = monomial3<K>(B, m);
+                    } else {
+#pragma unroll
+                        for (int m = 0; m < P; ++m) dst[m] = abf3<K>(B, m);
+                    }
+                } else {
+#pragma unroll
+                    for (int m = 0; m < P; ++m) dst[m] = 0.0;
+                }
+#pragma unroll
+                for (int m = P; m < PP; ++m) dst[m] = 0.0;
+            }
+            __syncthreads();
+            const int jmax = min(CH, N - j0);
+            for (int jj = 0; jj < jmax; ++jj) {
+                double xv[RB], wv[BS];
+#pragma unroll
+                for (int r = 0; r < RB; ++r) xv[r] = (r0 + r < BS) ? sX[jj * PP + lr * BS + r0 + r] : 0.0;
+#pragma unroll
+                for (int c = 0; c < BS; ++c) wv[c] = sW[jj * PP + lc * BS + c];
+#pragma unroll
+                for (int r = 0; r < RB; ++r)
+#pragma unroll
+                    for (int c = 0; c < BS; ++c) acc[r][c] = fma(xv[r], wv[c], acc[r][c]);
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int c = 0; c < BS; ++c) {
+                const int m = lr * BS + r0 + r, nn = lc * BS + c;
+                if (r0 + r < BS && m < P && nn < P) sM[m * LD + nn] = acc[r][c];
+            }
+    }
+    __syncthreads();
+}
+
+// accumulator rows per pass of assemble3: the whole block up to k = 4, four
+// rows at a time above (BS = 7 at k = 5, 11 at k = 6)
+constexpr int rb3(int K) { return (p3_of_k(K) + 7) / 8 <= 5 ? (p3_of_k(K) + 7) / 8 : 4; }
+
 struct W3Args {
     const double *x, *y, *z, *R;
     const int64_t* row_ptr;
@@ -117,12 +193,13 @@ __global__ __launch_bounds__(64) void k_weights3(W3Args a, OpList ops) {
     constexpr int BS = (P + 7) / 8;
     constexpr int PP = 8 * BS;
     constexpr int LD = P + 1;
-    constexpr int JS = NMAX / 64;
+    constexpr int JS = NM3 / 64;
+    static_assert(P <= 64, "one row per lane");
 
     __shared__ double sM[P * LD];
     __shared__ double sChunk[2 * CH * PP];
-    __shared__ double sD[3][NMAX];
-    __shared__ double sWl[MAXOPS][NMAX];
+    __shared__ double sD[3][NM3];
+    __shared__ double sWl[MAXOPS][NM3];
     __shared__ double sPsi[MAXOPS][PP];
     __shared__ double sRs[P], sCs[P];
     __shared__ int sPerm[P];
@@ -140,7 +217,7 @@ __global__ __launch_bounds__(64) void k_weights3(W3Args a, OpList ops) {
         for (int d = 0; d < nops; ++d)
             if (ops.op[d] == LABFM_OP_LAP && K < 2) status = LABFM_ST_ORDER_TOO_LOW;
         if (status == LABFM_ST_OK && N < P) status = LABFM_ST_TOO_FEW;
-        if (status == LABFM_ST_OK && N > NMAX) status = LABFM_ST_TOO_MANY;
+        if (status == LABFM_ST_OK && N > NM3) status = LABFM_ST_TOO_MANY;
 
         double dxr[JS], dyr[JS], dzr[JS];
         if (status == LABFM_ST_OK) {
@@ -164,59 +241,7 @@ __global__ __launch_bounds__(64) void k_weights3(W3Args a, OpList ops) {
 
         if (status == LABFM_ST_OK) {
             // ---- assembly: M = sum_j X(d_j) W(d_j)^T, register-blocked
-            const int lr = lane / 8, lc = lane % 8;
-            double acc[BS][BS];
-#pragma unroll
-            for (int r = 0; r < BS; ++r)
-#pragma unroll
-                for (int c = 0; c < BS; ++c) acc[r][c] = 0.0;
-            double* sX = sChunk;
-            double* sW = sChunk + CH * PP;
-            for (int j0 = 0; j0 < N; j0 += CH) {
-                if (lane < 2 * CH) {
-                    const int jj = lane % CH;
-                    const int j = j0 + jj;
-                    double* dst = (lane < CH ? sX : sW) + jj * PP;
-                    if (j < N) {
-                        Basis3<K> B;
-                        basis3_prepare<K>(B, sD[0][j], sD[1][j], sD[2][j], a.rbf, a.sigma);
-                        if (lane < CH) {
-#pragma unroll
-                            for (int m = 0; m < P; ++m) dst[m] = monomial3<K>(B, m);
-                        } else {
-#pragma unroll
-                            for (int m = 0; m < P; ++m) dst[m] = abf3<K>(B, m);
-                        }
-                    } else {
-#pragma unroll
-                        for (int m = 0; m < P; ++m) dst[m] = 0.0;
-                    }
-#pragma unroll
-                    for (int m = P; m < PP; ++m) dst[m] = 0.0;
-                }
-                __syncthreads();
-                const int jmax = min(CH, N - j0);
-                for (int jj = 0; jj < jmax; ++jj) {
-                    double xv[BS], wv[BS];
-#pragma unroll
-                    for (int r = 0; r < BS; ++r) xv[r] = sX[jj * PP + lr * BS + r];
-#pragma unroll
-                    for (int c = 0; c < BS; ++c) wv[c] = sW[jj * PP + lc * BS + c];
-#pragma unroll
-                    for (int r = 0; r < BS; ++r)
-#pragma unroll
-                        for (int c = 0; c < BS; ++c) acc[r][c] = fma(xv[r], wv[c], acc[r][c]);
-                }
-                __syncthreads();
-            }
-#pragma unroll
-            for (int r = 0; r < BS; ++r)
-#pragma unroll
-                for (int c = 0; c < BS; ++c) {
-                    const int m = lr * BS + r, nn = lc * BS + c;
-                    if (m < P && nn < P) sM[m * LD + nn] = acc[r][c];
-                }
-            __syncthreads();
+            assemble3<K, rb3(K)>(sM, sChunk, sD, N, a.rbf, a.sigma);
 
             // ---- equilibration: rows, then columns
             bool sing = false;
@@ -436,24 +461,422 @@ __global__ __launch_bounds__(64) void k_weights3(W3Args a, OpList ops) {
     }
 }
 
+// ---- systems with more elements than lanes (p = 83 at k = 6) --------------
+// Lane l holds rows (and columns) l and l + 64.
+
+// Solve M z = b with the equilibrated, pivoted LU in LDS: b[s][d] holds the
+// right-hand side of original row lane + 64 s on entry, z[d] of unknown
+// lane + 64 s on exit.
+template <int P, int LD>
+__device__ inline void lu_solve_w(const double* sM, const double* sRs, const double* sCs, const int* sPerm,
+                                  double (&b)[2][MAXOPS], int nops) {
+    const int lane = threadIdx.x;
+    double bs[2][MAXOPS], t[2][MAXOPS];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const int m = lane + 64 * s;
+        const double rs = m < P ? sRs[m] : 0.0;
+#pragma unroll
+        for (int d = 0; d < MAXOPS; ++d) bs[s][d] = b[s][d] * rs;
+    }
+    // position r takes the scaled right-hand side of original row perm[r]
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const int r = lane + 64 * s;
+        const int src = r < P ? sPerm[r] : 0;
+#pragma unroll
+        for (int d = 0; d < MAXOPS; ++d) {
+            const double v0 = __shfl(bs[0][d], src & 63, 64);
+            const double v1 = __shfl(bs[1][d], src & 63, 64);
+            t[s][d] = src >= 64 ? v1 : v0;
+        }
+    }
+    // forward: unit lower triangle
+    for (int c = 0; c < P - 1; ++c) {
+        double l[2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int r = lane + 64 * s;
+            l[s] = (r > c && r < P) ? sM[r * LD + c] : 0.0;
+        }
+#pragma unroll
+        for (int d = 0; d < MAXOPS; ++d)
+            if (d < nops) {
+                const double tc = bcast(c < 64 ? t[0][d] : t[1][d], c & 63);
+#pragma unroll
+                for (int s = 0; s < 2; ++s) t[s][d] -= l[s] * tc;
+            }
+    }
+    // backward
+    for (int c = P - 1; c >= 0; --c) {
+        const double diag = sM[c * LD + c];
+        double u[2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int r = lane + 64 * s;
+            u[s] = r < c ? sM[r * LD + c] : 0.0;
+        }
+#pragma unroll
+        for (int d = 0; d < MAXOPS; ++d)
+            if (d < nops) {
+                if (lane == (c & 63)) {
+                    if (c < 64)
+                        t[0][d] = t[0][d] / diag;
+                    else
+                        t[1][d] = t[1][d] / diag;
+                }
+                const double tc = bcast(c < 64 ? t[0][d] : t[1][d], c & 63);
+#pragma unroll
+                for (int s = 0; s < 2; ++s) t[s][d] -= u[s] * tc;
+            }
+    }
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const int m = lane + 64 * s;
+        const double cs = m < P ? sCs[m] : 0.0;
+#pragma unroll
+        for (int d = 0; d < MAXOPS; ++d) b[s][d] = t[s][d] * cs;
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(64) void k_weights3w(W3Args a, OpList ops) {
+    constexpr int P = p3_of_k(K);
+    static_assert(P > 64 && P <= 128, "two rows per lane");
+    constexpr int BS = (P + 7) / 8;
+    constexpr int PP = 8 * BS;
+    constexpr int LD = P + 1;
+    constexpr int JS = NM3 / 64;
+
+    __shared__ double sM[P * LD];
+    __shared__ double sChunk[2 * CH * PP];
+    __shared__ double sD[3][NM3];
+    __shared__ double sWl[MAXOPS][NM3];
+    __shared__ double sPsi[MAXOPS][PP];
+    __shared__ double sRs[P], sCs[P];
+    __shared__ int sPerm[P];
+
+    const int lane = threadIdx.x;
+    const int nops = ops.nops;
+
+    for (int64_t i = blockIdx.x; i < a.n; i += gridDim.x) {
+        const int64_t s0 = a.row_ptr[i];
+        const int N = (int)(a.row_ptr[i + 1] - s0);
+        const double h = 0.5 * a.R[i];
+        int status = LABFM_ST_OK;
+        double res = INFINITY;
+        int iters = 0;
+        if (status == LABFM_ST_OK && N < P) status = LABFM_ST_TOO_FEW;
+        if (status == LABFM_ST_OK && N > NM3) status = LABFM_ST_TOO_MANY;
+
+        double dxr[JS], dyr[JS], dzr[JS];
+        if (status == LABFM_ST_OK) {
+            const double xi = a.x[i], yi = a.y[i], zi = a.z[i];
+#pragma unroll
+            for (int js = 0; js < JS; ++js) {
+                const int q = lane + 64 * js;
+                dxr[js] = dyr[js] = dzr[js] = 0.0;
+                if (q < N) {
+                    const int32_t j = a.col[s0 + q];
+                    dxr[js] = min_image(a.x[j] - xi, a.L[0], a.per[0]) / h;
+                    dyr[js] = min_image(a.y[j] - yi, a.L[1], a.per[1]) / h;
+                    dzr[js] = min_image(a.z[j] - zi, a.L[2], a.per[2]) / h;
+                    sD[0][q] = dxr[js];
+                    sD[1][q] = dyr[js];
+                    sD[2][q] = dzr[js];
+                }
+            }
+        }
+        __syncthreads();
+
+        if (status == LABFM_ST_OK) {
+            assemble3<K, rb3(K)>(sM, sChunk, sD, N, a.rbf, a.sigma);
+
+            // ---- equilibration: rows, then columns (lane: rows / columns lane, lane + 64)
+            bool sing = false;
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const int m = lane + 64 * s;
+                if (m < P) {
+                    double mx = 0.0;
+                    for (int c = 0; c < P; ++c) mx = fmax(mx, fabs(sM[m * LD + c]));
+                    if (!(mx > 0.0) || !isfinite(mx)) sing = true;
+                    const double rs = 1.0 / mx;
+                    sRs[m] = rs;
+                    for (int c = 0; c < P; ++c) sM[m * LD + c] *= rs;
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const int m = lane + 64 * s;
+                if (m < P) {
+                    double mx = 0.0;
+                    for (int r = 0; r < P; ++r) mx = fmax(mx, fabs(sM[r * LD + m]));
+                    if (!(mx > 0.0) || !isfinite(mx)) sing = true;
+                    const double cs = 1.0 / mx;
+                    sCs[m] = cs;
+                    for (int r = 0; r < P; ++r) sM[r * LD + m] *= cs;
+                }
+            }
+            __syncthreads();
+            if (__any(sing)) status = LABFM_ST_SINGULAR;
+
+            // ---- LU with partial pivoting (ties: lowest row).  Per column: pivot,
+            // swap, multipliers stored in place, barrier, trailing update.
+            int perm[2] = {lane, lane + 64};
+            if (status == LABFM_ST_OK) {
+                for (int kk = 0; kk < P; ++kk) {
+                    double v[2];
+#pragma unroll
+                    for (int s = 0; s < 2; ++s) {
+                        const int r = lane + 64 * s;
+                        v[s] = (r >= kk && r < P) ? fabs(sM[r * LD + kk]) : -1.0;
+                    }
+                    const double vmax = wave_max_double(fmax(v[0], v[1]));
+                    const unsigned long long h0 = __ballot(v[0] == vmax);
+                    const unsigned long long h1 = __ballot(v[1] == vmax);
+                    if (!(vmax > 0.0) || !isfinite(vmax) || (h0 | h1) == 0ull) {
+                        status = LABFM_ST_SINGULAR;
+                        break;
+                    }
+                    const int pr = h0 ? __ffsll((long long)h0) - 1 : 64 + __ffsll((long long)h1) - 1;
+                    if (pr != kk) {
+#pragma unroll
+                        for (int s = 0; s < 2; ++s) {
+                            const int c = lane + 64 * s;
+                            if (c < P) {
+                                const double u = sM[kk * LD + c];
+                                sM[kk * LD + c] = sM[pr * LD + c];
+                                sM[pr * LD + c] = u;
+                            }
+                        }
+                        const int pk = __builtin_amdgcn_readlane(kk < 64 ? perm[0] : perm[1], kk & 63);
+                        const int pp = __builtin_amdgcn_readlane(pr < 64 ? perm[0] : perm[1], pr & 63);
+                        if (lane == (kk & 63)) {
+                            if (kk < 64)
+                                perm[0] = pp;
+                            else
+                                perm[1] = pp;
+                        }
+                        if (lane == (pr & 63)) {
+                            if (pr < 64)
+                                perm[0] = pk;
+                            else
+                                perm[1] = pk;
+                        }
+                    }
+                    __syncthreads();
+                    const double inv = 1.0 / sM[kk * LD + kk];
+#pragma unroll
+                    for (int s = 0; s < 2; ++s) {
+                        const int r = lane + 64 * s;
+                        if (r > kk && r < P) sM[r * LD + kk] = sM[r * LD + kk] * inv;
+                    }
+                    __syncthreads();
+#pragma unroll
+                    for (int s = 0; s < 2; ++s) {
+                        const int c = lane + 64 * s;
+                        if (c > kk && c < P) {
+                            const double u = sM[kk * LD + c];
+                            for (int r = kk + 1; r < P; ++r) sM[r * LD + c] = fma(-sM[r * LD + kk], u, sM[r * LD + c]);
+                        }
+                    }
+                    __syncthreads();
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+                if (lane + 64 * s < P) sPerm[lane + 64 * s] = perm[s];
+            __syncthreads();
+
+            if (status == LABFM_ST_OK) {
+                // ---- initial solve
+                double b[2][MAXOPS];
+#pragma unroll
+                for (int s = 0; s < 2; ++s)
+#pragma unroll
+                    for (int d = 0; d < MAXOPS; ++d) b[s][d] = (d < nops) ? target3(ops.op[d], lane + 64 * s) : 0.0;
+                lu_solve_w<P, LD>(sM, sRs, sCs, sPerm, b, nops);
+#pragma unroll
+                for (int s = 0; s < 2; ++s)
+                    if (lane + 64 * s < P)
+#pragma unroll
+                        for (int d = 0; d < MAXOPS; ++d)
+                            if (d < nops) sPsi[d][lane + 64 * s] = b[s][d];
+                __syncthreads();
+
+                // ---- w_j = W(d_j) . Psi
+                double wreg[JS][MAXOPS];
+#pragma unroll
+                for (int js = 0; js < JS; ++js) {
+                    const int q = lane + 64 * js;
+#pragma unroll
+                    for (int d = 0; d < MAXOPS; ++d) wreg[js][d] = 0.0;
+                    if (q < N) {
+                        Basis3<K> B;
+                        basis3_prepare<K>(B, dxr[js], dyr[js], dzr[js], a.rbf, a.sigma);
+#pragma unroll
+                        for (int m = 0; m < P; ++m) {
+                            const double wm = abf3<K>(B, m);
+#pragma unroll
+                            for (int d = 0; d < MAXOPS; ++d)
+                                if (d < nops) wreg[js][d] = fma(wm, sPsi[d][m], wreg[js][d]);
+                        }
+#pragma unroll
+                        for (int d = 0; d < MAXOPS; ++d)
+                            if (d < nops) sWl[d][q] = wreg[js][d];
+                    }
+                }
+                __syncthreads();
+
+                // ---- refinement on the moment residual (FP64)
+                int ma[2], mb[2], mc[2];
+                double mf[2];
+#pragma unroll
+                for (int s = 0; s < 2; ++s) {
+                    const int m = lane + 64 * s;
+                    ma[s] = m < P ? ELEM3.a[m] : 0;
+                    mb[s] = m < P ? ELEM3.b[m] : 0;
+                    mc[s] = m < P ? ELEM3.c[m] : 0;
+                    mf[s] = m < P ? inv_fact(ma[s]) * inv_fact(mb[s]) * inv_fact(mc[s]) : 0.0;
+                }
+                for (;;) {
+                    double r[2][MAXOPS];
+                    double rm = 0.0;
+#pragma unroll
+                    for (int s = 0; s < 2; ++s) {
+                        const int m = lane + 64 * s;
+#pragma unroll
+                        for (int d = 0; d < MAXOPS; ++d) r[s][d] = 0.0;
+                        if (m < P) {
+                            double accr[MAXOPS];
+#pragma unroll
+                            for (int d = 0; d < MAXOPS; ++d) accr[d] = 0.0;
+                            for (int q = 0; q < N; ++q) {
+                                const double dx = sD[0][q], dy = sD[1][q], dz = sD[2][q];
+                                double xm = mf[s];
+#pragma unroll
+                                for (int e = 0; e < K; ++e) {
+                                    xm *= (e < ma[s]) ? dx : 1.0;
+                                    xm *= (e < mb[s]) ? dy : 1.0;
+                                    xm *= (e < mc[s]) ? dz : 1.0;
+                                }
+#pragma unroll
+                                for (int d = 0; d < MAXOPS; ++d)
+                                    if (d < nops) accr[d] = fma(xm, sWl[d][q], accr[d]);
+                            }
+#pragma unroll
+                            for (int d = 0; d < MAXOPS; ++d)
+                                if (d < nops) r[s][d] = target3(ops.op[d], m) - accr[d];
+                        }
+#pragma unroll
+                        for (int d = 0; d < MAXOPS; ++d) {
+                            const double ar = fabs(r[s][d]);
+                            rm = (ar > rm || ar != ar) ? ar : rm;
+                        }
+                    }
+                    if (!isfinite(rm)) rm = INFINITY;
+                    res = wave_max(rm);
+                    if (!(res > a.tol_stop) || iters >= a.max_iters) break;
+                    lu_solve_w<P, LD>(sM, sRs, sCs, sPerm, r, nops);
+                    __syncthreads();
+#pragma unroll
+                    for (int s = 0; s < 2; ++s)
+                        if (lane + 64 * s < P)
+#pragma unroll
+                            for (int d = 0; d < MAXOPS; ++d)
+                                if (d < nops) sPsi[d][lane + 64 * s] = r[s][d];
+                    __syncthreads();
+#pragma unroll
+                    for (int js = 0; js < JS; ++js) {
+                        const int q = lane + 64 * js;
+                        if (q < N) {
+                            Basis3<K> B;
+                            basis3_prepare<K>(B, dxr[js], dyr[js], dzr[js], a.rbf, a.sigma);
+                            double dw[MAXOPS];
+#pragma unroll
+                            for (int d = 0; d < MAXOPS; ++d) dw[d] = 0.0;
+#pragma unroll
+                            for (int m = 0; m < P; ++m) {
+                                const double wm = abf3<K>(B, m);
+#pragma unroll
+                                for (int d = 0; d < MAXOPS; ++d)
+                                    if (d < nops) dw[d] = fma(wm, sPsi[d][m], dw[d]);
+                            }
+#pragma unroll
+                            for (int d = 0; d < MAXOPS; ++d)
+                                if (d < nops) {
+                                    wreg[js][d] += dw[d];
+                                    sWl[d][q] = wreg[js][d];
+                                }
+                        }
+                    }
+                    __syncthreads();
+                    ++iters;
+                }
+                if (!(res <= a.tol_pass)) status = LABFM_ST_NOT_CONVERGED;
+
+                // ---- unscale and store
+#pragma unroll
+                for (int d = 0; d < MAXOPS; ++d) {
+                    if (d >= nops) continue;
+                    const double hl = ops.op[d] == LABFM_OP_LAP ? h * h : h;
+#pragma unroll
+                    for (int js = 0; js < JS; ++js) {
+                        const int q = lane + 64 * js;
+                        if (q < N) a.w64[(int64_t)d * a.nnz + s0 + q] = wreg[js][d] / hl;
+                    }
+                }
+            }
+        }
+        const bool failed = !(status == LABFM_ST_OK || status == LABFM_ST_NOT_CONVERGED);
+        if (failed) {
+            for (int d = 0; d < nops; ++d)
+                for (int q = lane; q < N; q += 64) a.w64[(int64_t)d * a.nnz + s0 + q] = 0.0;
+            res = INFINITY;
+            iters = 0;
+        }
+        if (lane == 0) {
+            a.status[i] = (int8_t)status;
+            if (a.resid) a.resid[i] = (float)res;
+            if (a.iters) a.iters[i] = (int8_t)iters;
+        }
+        __syncthreads();
+    }
+}
+
+template <typename Kern>
+int grid3_of(Kern kern) {
+    int dev = 0, ncu = 0, per = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, 64, 0);
+    if (ncu <= 0) ncu = 256;
+    if (per <= 0) per = 1;
+    return ncu * per;
+}
+
 template <int K>
 int grid3_for() {
     static int g = 0;
-    if (g == 0) {
-        int dev = 0, ncu = 0, per = 0;
-        (void)hipGetDevice(&dev);
-        (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_weights3<K>, 64, 0);
-        if (ncu <= 0) ncu = 256;
-        if (per <= 0) per = 1;
-        g = ncu * per;
-    }
+    if (g == 0) g = grid3_of(k_weights3<K>);
+    return g;
+}
+template <int K>
+int grid3w_for() {
+    static int g = 0;
+    if (g == 0) g = grid3_of(k_weights3w<K>);
     return g;
 }
 
 template <int K>
 void launch3(const W3Args& a, const OpList& ops, hipStream_t st) {
     k_weights3<K><<<grid3_for<K>(), 64, 0, st>>>(a, ops);
+}
+template <int K>
+void launch3w(const W3Args& a, const OpList& ops, hipStream_t st) {
+    k_weights3w<K><<<grid3w_for<K>(), 64, 0, st>>>(a, ops);
 }
 
 }  // namespace
@@ -489,13 +912,16 @@ labfm_err weights3(Context* c, const double* x, const double* y, const double* z
     ops.nops = 0;
     for (int b = 0; b < 6; ++b)
         if (opt->ops & (1u << b)) ops.op[ops.nops++] = 1u << b;
-    static const char* names[K3MAX + 1] = {"", "weights3d_k1", "weights3d_k2", "weights3d_k3", "weights3d_k4"};
+    static const char* names[K3MAX + 1] = {"",           "weights3d_k1", "weights3d_k2", "weights3d_k3",
+                                           "weights3d_k4", "weights3d_k5", "weights3d_k6"};
     KernelTimer timer(c, names[k], st);
     switch (k) {
         case 1: launch3<1>(a, ops, st); break;
         case 2: launch3<2>(a, ops, st); break;
         case 3: launch3<3>(a, ops, st); break;
-        default: launch3<4>(a, ops, st); break;
+        case 4: launch3<4>(a, ops, st); break;
+        case 5: launch3<5>(a, ops, st); break;
+        default: launch3w<6>(a, ops, st); break;
     }
     LABFM_HIP_CHECK(hipGetLastError());
     return LABFM_OK;
