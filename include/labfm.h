@@ -82,8 +82,18 @@ enum {
  *        refinement does not converge are recomputed on the FP64 path.
  * MLP: as MIXED, but nodes of the network's order start the refinement from
  *        the network's Psi0 (labfm_wopts.mlp) instead of from a first solve
- *        with the FP32 factors. */
-typedef enum { LABFM_PREC_FP64 = 0, LABFM_PREC_MIXED = 1, LABFM_PREC_MLP = 2 } labfm_prec;
+ *        with the FP32 factors.
+ * MLP_NOLU: nodes of the network's order take w = W Psi0 as it stands, with
+ *        no moment matrix and no factorisation; a node whose FP64 moment
+ *        residual from Psi0 is at or below tol_pass is finished (iters 0),
+ *        any other is solved by the FP64 LU path (iters 64 + its count).
+ *        Other orders: as MIXED. */
+typedef enum {
+    LABFM_PREC_FP64 = 0,
+    LABFM_PREC_MIXED = 1,
+    LABFM_PREC_MLP = 2,
+    LABFM_PREC_MLP_NOLU = 3
+} labfm_prec;
 
 /* Per-node status written by labfm_weights.  The weight calls are
  * asynchronous, so per-node numerical failures are reported here only: a call
@@ -193,7 +203,7 @@ labfm_err labfm_build_neighbours(void* ctx, const double* x, const double* y, in
  * solved by row-then-column max equilibration and LU with partial
  * pivoting, refined on the weights (r = C - X^T w; w += W M^-1 r) in FP64,
  * and unscaled by h^l (l = 1, 1, 2, 4, 6 for DX, DY, LAP, BIHARM, TRIHARM).
- * With LABFM_PREC_MLP the network must serve exactly opt->ops; its features
+ * With LABFM_PREC_MLP(_NOLU) the network must serve exactly opt->ops; its features
  * and outputs for every node are computed first (library scratch of
  * 4 n dims[n_layers] bytes plus a chunk of 65536 nodes' activations).
  * Outputs (device): w64 [nops][nnz] FP64 and/or w32 [nops][nnz] FP32 (either

@@ -19,7 +19,7 @@ ABF_HERMITE, ABF_PAPER, ABF_PAPER_D1 = 0, 1, 2
 RBF_WENDLAND_C2, RBF_CONE, RBF_QUADRATIC, RBF_WENDLAND_C6, RBF_GAUSSIAN = 0, 1, 2, 3, 4
 OP_DX, OP_DY, OP_LAP, OP_BIHARM, OP_TRIHARM = 1, 2, 4, 8, 16
 OP_DZ = 32  # three-dimensional calls only
-PREC_FP64, PREC_MIXED, PREC_MLP = 0, 1, 2
+PREC_FP64, PREC_MIXED, PREC_MLP, PREC_MLP_NOLU = 0, 1, 2, 3
 NOALLOC_MAX_NODES = 1 << 20  # largest n of labfm_weights_noalloc
 ST_OK, ST_NOT_CONVERGED, ST_SINGULAR, ST_TOO_FEW, ST_DEGENERATE, ST_ORDER_TOO_LOW, ST_TOO_MANY = range(7)
 MAX_NEIGHBOURS = 128
@@ -319,7 +319,9 @@ class Context:
         """Weights [nops, nnz] (FP64 and/or FP32), status[n] int8, resid[n] f32, iters[n] int8.
 
         prec=PREC_MLP starts the refinement of the network's order from
-        `mlp` (an MLP) instead of from a first solve.  noalloc=True calls
+        `mlp` (an MLP) instead of from a first solve; PREC_MLP_NOLU takes the
+        network's coefficients without a factorisation and solves the nodes
+        they leave above tol_pass on the FP64 path.  noalloc=True calls
         labfm_weights_noalloc (no library allocation; the outputs are still
         allocated here unless `out` is given)."""
         torch = self.torch
@@ -347,9 +349,9 @@ class Context:
         o = WOpts(int(abf), int(rbf), float(sigma), int(ops), int(prec), float(tol_stop), float(tol_pass),
                   int(max_iters), None)
         desc = None
-        if prec == PREC_MLP:
+        if prec in (PREC_MLP, PREC_MLP_NOLU):
             if mlp is None:
-                raise LabfmError("PREC_MLP needs a network (mlp=...)")
+                raise LabfmError("the warm start needs a network (mlp=...)")
             desc = mlp.desc()
             o.mlp = C.pointer(desc)
         dom = make_domain(domain)

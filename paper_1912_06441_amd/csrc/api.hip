@@ -303,7 +303,8 @@ labfm_err check_weights_args(const char* who, const double* x, const double* y, 
     if (!w64 && !w32) return fail(LABFM_EINVAL, w + "w64 and w32 are both NULL");
     if (n > 0 && (!x || !y || !R || !order || !row_ptr || !status || (nnz > 0 && !col)))
         return fail(LABFM_EINVAL, w + "NULL array");
-    if (opt->prec != LABFM_PREC_FP64 && opt->prec != LABFM_PREC_MIXED && opt->prec != LABFM_PREC_MLP)
+    if (opt->prec != LABFM_PREC_FP64 && opt->prec != LABFM_PREC_MIXED && opt->prec != LABFM_PREC_MLP &&
+        opt->prec != LABFM_PREC_MLP_NOLU)
         return fail(LABFM_EINVAL, w + "bad prec");
     return LABFM_OK;
 }
@@ -375,7 +376,7 @@ labfm_err labfm_weights(void* ctx, const double* x, const double* y, int64_t n, 
     if (!ctx) return fail(LABFM_EINVAL, "labfm_weights: ctx is NULL");
     labfm_err e = check_weights_args("labfm_weights", x, y, n, dom, R, order, row_ptr, col, nnz, opt, w64, w32, status);
     if (e != LABFM_OK) return e;
-    if (opt->prec == LABFM_PREC_MLP) {
+    if (opt->prec == LABFM_PREC_MLP || opt->prec == LABFM_PREC_MLP_NOLU) {
         std::string why;
         if (!mlp_serves(opt->mlp, why)) return fail(LABFM_EINVAL, "labfm_weights: network: " + why);
         if (opt->mlp->ops != opt->ops) return fail(LABFM_EINVAL, "labfm_weights: network ops differ from opt->ops");
@@ -393,7 +394,7 @@ labfm_err labfm_weights(void* ctx, const double* x, const double* y, int64_t n, 
     if ((e = ensure(c->mixed, sizeof(int32_t) * (size_t)(n + LABFM_MAX_ORDER + 2))) != LABFM_OK) return e;
     int32_t* rl = (int32_t*)c->mixed.p;
     if (opt->prec == LABFM_PREC_MIXED) return weights_mixed(c, a, &a.one, wl, rl, 0u, st);
-    return weights_mlp(c, a, wl, rl, opt->mlp, st);
+    return weights_mlp(c, a, wl, rl, opt->mlp, st, opt->prec == LABFM_PREC_MLP_NOLU);
 }
 
 labfm_err labfm_weights_noalloc(void* ctx, const double* x, const double* y, int64_t n, const labfm_domain* dom,
@@ -404,8 +405,8 @@ labfm_err labfm_weights_noalloc(void* ctx, const double* x, const double* y, int
     labfm_err e =
         check_weights_args("labfm_weights_noalloc", x, y, n, dom, R, order, row_ptr, col, nnz, opt, w64, w32, status);
     if (e != LABFM_OK) return e;
-    if (opt->prec == LABFM_PREC_MLP)
-        return fail(LABFM_EUNSUPPORTED, "labfm_weights_noalloc: LABFM_PREC_MLP needs library scratch; use labfm_weights");
+    if (opt->prec == LABFM_PREC_MLP || opt->prec == LABFM_PREC_MLP_NOLU)
+        return fail(LABFM_EUNSUPPORTED, "labfm_weights_noalloc: the warm start needs library scratch; use labfm_weights");
     if (n > NOALLOC_MAX_NODES)
         return fail(LABFM_EINVAL, "labfm_weights_noalloc: n = " + std::to_string(n) + " exceeds LABFM_NOALLOC_MAX_NODES (" +
                                       std::to_string(NOALLOC_MAX_NODES) + ")");
@@ -441,7 +442,8 @@ labfm_err labfm_weights_batched(void* ctx, int nsets, const labfm_node_set* sets
     if (!(opt->sigma > 0.0) || !std::isfinite(opt->sigma)) return fail(LABFM_EINVAL, "labfm_weights_batched: sigma must be > 0");
     if (opt->max_iters < 0 || opt->max_iters > 63) return fail(LABFM_EINVAL, "labfm_weights_batched: max_iters must be in 0..63");
     if (!(opt->tol_stop >= 0.0) || !(opt->tol_pass >= 0.0)) return fail(LABFM_EINVAL, "labfm_weights_batched: bad tolerances");
-    if (opt->prec == LABFM_PREC_MLP) return fail(LABFM_EUNSUPPORTED, "labfm_weights_batched: LABFM_PREC_MLP is not batched");
+    if (opt->prec == LABFM_PREC_MLP || opt->prec == LABFM_PREC_MLP_NOLU)
+        return fail(LABFM_EUNSUPPORTED, "labfm_weights_batched: the warm start is not batched");
     if (opt->prec != LABFM_PREC_FP64 && opt->prec != LABFM_PREC_MIXED) return fail(LABFM_EINVAL, "labfm_weights_batched: bad prec");
     int64_t total = 0;
     for (int s = 0; s < nsets; ++s) {

@@ -205,12 +205,13 @@ labfm_err weights_fp64_lists(Context* c, const WeightArgs& a, const int32_t* lis
                              const int32_t* cnt, unsigned mask, hipStream_t st);
 // whole computations; host_sets: host copy of the set table (nsets entries, or &a.one)
 labfm_err weights_fp64(Context* c, const WeightArgs& a, const NodeSet* host_sets, int32_t* wl, hipStream_t st);
-// mixed kernels for the orders not in fp64_orders, FP64 kernels for those and for the retry list
-// rl: >= ntotal + KMAX + 2 int32
+// mixed kernels for the orders not in fp64_orders, FP64 kernels for those and for the retry list;
+// direct_order (1..8, needs NodeSet::psi0): that order takes the warm start's Psi0 without a
+// factorisation, its nodes above tol_pass go to the retry list.  rl: >= ntotal + KMAX + 2 int32
 labfm_err weights_mixed(Context* c, const WeightArgs& a, const NodeSet* host_sets, int32_t* wl, int32_t* rl,
-                        unsigned fp64_orders, hipStream_t st);
+                        unsigned fp64_orders, hipStream_t st, int direct_order = 0);
 labfm_err weights_mixed_lists(Context* c, const WeightArgs& a, const int32_t* list, const int32_t* off,
-                              const int32_t* cnt, int32_t* rl, unsigned mask, hipStream_t st);
+                              const int32_t* cnt, int32_t* rl, unsigned mask, hipStream_t st, int direct_order = 0);
 
 // ---- learned warm start
 labfm_err mlp_features(Context* c, const double* x, const double* y, const double* R, const int64_t* row_ptr,
@@ -226,8 +227,10 @@ labfm_err mlp_moment_loss(Context* c, const float* y, const float* M, const floa
 labfm_err mlp_adam(Context* c, float* p, const float* g, float* m, float* v, void* pb, int64_t n, const labfm_adam* hp,
                    int64_t t, hipStream_t st);
 labfm_err mlp_cast_bf16(const float* src, void* dst, int64_t n, hipStream_t st);
+// learned warm start: refine from the network's Psi0 with the FP32 factors (direct = false), or
+// take Psi0 without a factorisation and solve the nodes it leaves above tol_pass on the FP64 path
 labfm_err weights_mlp(Context* c, const WeightArgs& a, int32_t* wl, int32_t* rl, const labfm_mlp* net,
-                      hipStream_t st);
+                      hipStream_t st, bool direct = false);
 
 // ---- application and time stepping
 labfm_err apply_launch(Context* c, const int64_t* row_ptr, const int32_t* col, int64_t n, int64_t nnz, int nops,

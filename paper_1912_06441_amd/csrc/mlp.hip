@@ -737,7 +737,7 @@ labfm_err mlp_cast_bf16(const float* src, void* dst, int64_t n, hipStream_t st) 
 constexpr int64_t MLP_CHUNK = 65536;
 
 labfm_err weights_mlp(Context* c, const WeightArgs& a0, int32_t* wl, int32_t* rl, const labfm_mlp* net,
-                      hipStream_t st) {
+                      hipStream_t st, bool direct) {
     const NodeSet& S = a0.one;
     const int64_t n = S.n;
     const int L = net->n_layers;
@@ -759,7 +759,7 @@ labfm_err weights_mlp(Context* c, const WeightArgs& a0, int32_t* wl, int32_t* rl
     a.one.psi0 = psi0;
     a.psi0_order = net->order;
     a.psi0_ld = nout;
-    return weights_mixed(c, a, &a.one, wl, rl, 0u, st);
+    return weights_mixed(c, a, &a.one, wl, rl, 0u, st, direct ? net->order : 0);
 }
 
 }  // namespace labfm

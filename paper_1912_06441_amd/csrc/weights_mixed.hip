@@ -388,6 +388,195 @@ __global__ __launch_bounds__(64) void k_weights_mixed(WeightArgs a, OpList ops, 
     }
 }
 
+// ---- learned warm start without a factorisation ---------------------------
+// Nodes of the network's order take w_j = W(d_j) . Psi0 with the network's
+// coefficients as they stand and the FP64 moment residual r = C - X^T w; a
+// node at or below tol_pass is finished (iters 0), any other goes to the
+// retry list, whose nodes the FP64 LU kernels then solve from scratch.  No
+// moment matrix is assembled here.
+template <int K, int FAM>
+__global__ __launch_bounds__(64) void k_weights_psi0(WeightArgs a, OpList ops, const int32_t* list,
+                                                     const int32_t* list_off, const int32_t* list_cnt,
+                                                     int32_t* retry_list, int32_t* retry_cnt) {
+    constexpr int P = p_of_k(K);
+    constexpr int JS = NMAX / 64;
+    __shared__ double sD[2][NMAX];
+    __shared__ double sWl[MAXOPS][NMAX];
+    __shared__ double sPsi[MAXOPS][P];
+
+    const int lane = threadIdx.x;
+    const int nops = ops.nops;
+    const int count = list_cnt[K];
+    const int32_t* mylist = list + list_off[K];
+
+    for (int t = blockIdx.x; t < count; t += gridDim.x) {
+        const int32_t g = mylist[t];
+        NodeSet S;
+        int64_t i;
+        resolve(a, g, S, i);
+        const int64_t s0 = S.row_ptr[i];
+        const int N = (int)(S.row_ptr[i + 1] - s0);
+        const double h = 0.5 * S.R[i];
+        int status = LABFM_ST_OK;
+        double res = INFINITY;
+
+        for (int d = 0; d < nops; ++d)
+            if (K < min_order(ops.op[d])) status = LABFM_ST_ORDER_TOO_LOW;
+        if (status == LABFM_ST_OK && N < P) status = LABFM_ST_TOO_FEW;
+        if (status == LABFM_ST_OK && N > NMAX) status = LABFM_ST_TOO_MANY;
+
+        double dxr[JS], dyr[JS];
+        if (status == LABFM_ST_OK) {
+            const double xi = S.x[i], yi = S.y[i];
+            bool bad = false;
+#pragma unroll
+            for (int js = 0; js < JS; ++js) {
+                const int q = lane + 64 * js;
+                dxr[js] = 0.0;
+                dyr[js] = 0.0;
+                if (q < N) {
+                    const int32_t j = S.col[s0 + q];
+                    dxr[js] = min_image(S.x[j] - xi, S.Lx, S.perx) / h;
+                    dyr[js] = min_image(S.y[j] - yi, S.Ly, S.pery) / h;
+                    sD[0][q] = dxr[js];
+                    sD[1][q] = dyr[js];
+                    if (FAM != LABFM_ABF_HERMITE && dxr[js] == 0.0 && dyr[js] == 0.0) bad = true;
+                }
+            }
+            if (__any(bad)) status = LABFM_ST_DEGENERATE;
+            if (lane < P)
+                for (int d = 0; d < nops; ++d) sPsi[d][lane] = (double)S.psi0[i * (int64_t)a.psi0_ld + d * P + lane];
+        }
+        __syncthreads();
+
+        bool retry = false;
+        if (status == LABFM_ST_OK) {
+            double wreg[JS][MAXOPS];
+#pragma unroll
+            for (int js = 0; js < JS; ++js) {
+                const int q = lane + 64 * js;
+#pragma unroll
+                for (int d = 0; d < MAXOPS; ++d) wreg[js][d] = 0.0;
+                if (q < N) {
+                    BasisState<K> B;
+                    basis_prepare<K, FAM>(B, dxr[js], dyr[js], a.rbf, a.sigma);
+#pragma unroll
+                    for (int m = 0; m < P; ++m) {
+                        const double wm = abf<K, FAM>(B, m);
+#pragma unroll
+                        for (int d = 0; d < MAXOPS; ++d)
+                            if (d < nops) wreg[js][d] = fma(wm, sPsi[d][m], wreg[js][d]);
+                    }
+#pragma unroll
+                    for (int d = 0; d < MAXOPS; ++d)
+                        if (d < nops) sWl[d][q] = wreg[js][d];
+                }
+            }
+            __syncthreads();
+            // FP64 moment residual: lane m < P sums over the neighbours
+            const int ma = lane < P ? ELEM.a[lane] : 0;
+            const int mb = lane < P ? ELEM.b[lane] : 0;
+            const double mf = lane < P ? inv_fact(ma) * inv_fact(mb) : 0.0;
+            double rm = 0.0;
+            if (lane < P) {
+                double accr[MAXOPS];
+#pragma unroll
+                for (int d = 0; d < MAXOPS; ++d) accr[d] = 0.0;
+                for (int q = 0; q < N; ++q) {
+                    const double dx = sD[0][q], dy = sD[1][q];
+                    double xm = mf;
+#pragma unroll
+                    for (int e = 0; e < K; ++e) {
+                        xm *= (e < ma) ? dx : 1.0;
+                        xm *= (e < mb) ? dy : 1.0;
+                    }
+#pragma unroll
+                    for (int d = 0; d < MAXOPS; ++d)
+                        if (d < nops) accr[d] = fma(xm, sWl[d][q], accr[d]);
+                }
+#pragma unroll
+                for (int d = 0; d < MAXOPS; ++d)
+                    if (d < nops) {
+                        const double ar = fabs(target(ops.op[d], lane) - accr[d]);
+                        rm = (ar > rm || ar != ar) ? ar : rm;
+                    }
+            }
+            if (!isfinite(rm)) rm = INFINITY;
+            res = wave_max(rm);
+            retry = !(res <= a.tol_pass);
+            if (!retry) {
+#pragma unroll
+                for (int d = 0; d < MAXOPS; ++d) {
+                    if (d >= nops) continue;
+                    double hl = 1.0;
+                    for (int e = 0; e < deriv_order(ops.op[d]); ++e) hl *= h;
+#pragma unroll
+                    for (int js = 0; js < JS; ++js) {
+                        const int q = lane + 64 * js;
+                        if (q < N) {
+                            const double wv = wreg[js][d] / hl;
+                            if (S.w64) S.w64[(int64_t)d * S.nnz + s0 + q] = wv;
+                            if (S.w32) S.w32[(int64_t)d * S.nnz + s0 + q] = (float)wv;
+                        }
+                    }
+                }
+            }
+        }
+        if (retry) {
+            if (lane == 0) {
+                const int pos = atomicAdd(&retry_cnt[K], 1);
+                retry_list[list_off[K] + pos] = g;
+            }
+        } else {
+            if (status != LABFM_ST_OK) {
+                for (int d = 0; d < nops; ++d)
+                    for (int q = lane; q < N; q += 64) {
+                        if (S.w64) S.w64[(int64_t)d * S.nnz + s0 + q] = 0.0;
+                        if (S.w32) S.w32[(int64_t)d * S.nnz + s0 + q] = 0.0f;
+                    }
+                res = INFINITY;
+            }
+            if (lane == 0) {
+                S.status[i] = (int8_t)status;
+                if (S.resid) S.resid[i] = (float)res;
+                if (S.iters) S.iters[i] = 0;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <int K, int FAM>
+int grid_for_psi0() {
+    static int g = 0;
+    if (g == 0) {
+        int dev = 0, ncu = 0, per = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_weights_psi0<K, FAM>, 64, 0);
+        if (ncu <= 0) ncu = 256;
+        if (per <= 0) per = 1;
+        g = ncu * per;
+    }
+    return g;
+}
+
+template <int FAM>
+void launch_psi0(Context* c, const WeightArgs& a, const OpList& ops, const int32_t* list, const int32_t* off,
+                 const int32_t* cnt, int32_t* rlist, int32_t* rcnt, int K, hipStream_t st) {
+    KernelTimer timer(c, "weights_psi0", st);
+    switch (K) {
+        case 1: k_weights_psi0<1, FAM><<<grid_for_psi0<1, FAM>(), 64, 0, st>>>(a, ops, list, off, cnt, rlist, rcnt); break;
+        case 2: k_weights_psi0<2, FAM><<<grid_for_psi0<2, FAM>(), 64, 0, st>>>(a, ops, list, off, cnt, rlist, rcnt); break;
+        case 3: k_weights_psi0<3, FAM><<<grid_for_psi0<3, FAM>(), 64, 0, st>>>(a, ops, list, off, cnt, rlist, rcnt); break;
+        case 4: k_weights_psi0<4, FAM><<<grid_for_psi0<4, FAM>(), 64, 0, st>>>(a, ops, list, off, cnt, rlist, rcnt); break;
+        case 5: k_weights_psi0<5, FAM><<<grid_for_psi0<5, FAM>(), 64, 0, st>>>(a, ops, list, off, cnt, rlist, rcnt); break;
+        case 6: k_weights_psi0<6, FAM><<<grid_for_psi0<6, FAM>(), 64, 0, st>>>(a, ops, list, off, cnt, rlist, rcnt); break;
+        case 7: k_weights_psi0<7, FAM><<<grid_for_psi0<7, FAM>(), 64, 0, st>>>(a, ops, list, off, cnt, rlist, rcnt); break;
+        default: k_weights_psi0<8, FAM><<<grid_for_psi0<8, FAM>(), 64, 0, st>>>(a, ops, list, off, cnt, rlist, rcnt); break;
+    }
+}
+
 template <int K, int FAM>
 int grid_for_mixed() {
     static int g = 0;
@@ -449,7 +638,7 @@ void init_mixed_grids() {
 // Mixed kernels of the orders in `mask` over given lists, then FP64 kernels on
 // the nodes they hand back.  rl: >= ntotal + KMAX + 2 int32 (counters first).
 labfm_err weights_mixed_lists(Context* c, const WeightArgs& a0, const int32_t* list, const int32_t* off,
-                              const int32_t* cnt, int32_t* rl, unsigned mask, hipStream_t st) {
+                              const int32_t* cnt, int32_t* rl, unsigned mask, hipStream_t st, int direct_order) {
     int32_t* rcnt = rl;
     int32_t* rlist = rcnt + (KMAX + 2);
     labfm_err e = fill_i32(rcnt, KMAX + 2, 0, st);
@@ -458,12 +647,22 @@ labfm_err weights_mixed_lists(Context* c, const WeightArgs& a0, const int32_t* l
     ops.nops = 0;
     for (int b = 0; b < 5; ++b)
         if (a0.ops & (1u << b)) ops.op[ops.nops++] = 1u << b;
+    unsigned mixed_mask = mask;
+    if (direct_order >= 1 && direct_order <= KMAX && ((mask >> direct_order) & 1u)) {
+        mixed_mask &= ~(1u << direct_order);
+        if (a0.abf == LABFM_ABF_HERMITE)
+            launch_psi0<LABFM_ABF_HERMITE>(c, a0, ops, list, off, cnt, rlist, rcnt, direct_order, st);
+        else if (a0.abf == LABFM_ABF_PAPER)
+            launch_psi0<LABFM_ABF_PAPER>(c, a0, ops, list, off, cnt, rlist, rcnt, direct_order, st);
+        else
+            launch_psi0<LABFM_ABF_PAPER_D1>(c, a0, ops, list, off, cnt, rlist, rcnt, direct_order, st);
+    }
     if (a0.abf == LABFM_ABF_HERMITE)
-        launch_mixed_all<LABFM_ABF_HERMITE>(c, a0, ops, list, off, cnt, rlist, rcnt, mask, st);
+        launch_mixed_all<LABFM_ABF_HERMITE>(c, a0, ops, list, off, cnt, rlist, rcnt, mixed_mask, st);
     else if (a0.abf == LABFM_ABF_PAPER)
-        launch_mixed_all<LABFM_ABF_PAPER>(c, a0, ops, list, off, cnt, rlist, rcnt, mask, st);
+        launch_mixed_all<LABFM_ABF_PAPER>(c, a0, ops, list, off, cnt, rlist, rcnt, mixed_mask, st);
     else
-        launch_mixed_all<LABFM_ABF_PAPER_D1>(c, a0, ops, list, off, cnt, rlist, rcnt, mask, st);
+        launch_mixed_all<LABFM_ABF_PAPER_D1>(c, a0, ops, list, off, cnt, rlist, rcnt, mixed_mask, st);
     LABFM_HIP_CHECK(hipGetLastError());
     // FP64 recomputation of the retry list; iters of those nodes are offset by 64
     WeightArgs a = a0;
@@ -472,14 +671,14 @@ labfm_err weights_mixed_lists(Context* c, const WeightArgs& a0, const int32_t* l
 }
 
 labfm_err weights_mixed(Context* c, const WeightArgs& a0, const NodeSet* hs, int32_t* wl, int32_t* rl,
-                        unsigned fp64_orders, hipStream_t st) {
+                        unsigned fp64_orders, hipStream_t st, int direct_order) {
     int32_t *list = wl, *off, *cnt;
     labfm_err e = build_order_lists(c, a0, hs, st, &list, &off, &cnt);
     if (e != LABFM_OK) return e;
     if ((e = weights_invalid_orders(a0, list, off, cnt, st)) != LABFM_OK) return e;
     if (fp64_orders & ALL_ORDERS)
         if ((e = weights_fp64_lists(c, a0, list, off, cnt, fp64_orders & ALL_ORDERS, st)) != LABFM_OK) return e;
-    return weights_mixed_lists(c, a0, list, off, cnt, rl, ALL_ORDERS & ~fp64_orders, st);
+    return weights_mixed_lists(c, a0, list, off, cnt, rl, ALL_ORDERS & ~fp64_orders, st, direct_order);
 }
 
 }  // namespace labfm

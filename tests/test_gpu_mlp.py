@@ -12,6 +12,13 @@
 * training on oracle stencils, then warm-started weights: every node passes the
   1e-10 moment gate and matches the oracle's weights like the mixed path; the
   trained network's initial residual beats a zero start.
+* the warm start without a factorisation (PREC_MLP_NOLU): a zero network sends
+  every node to the FP64 LU path (weights equal PREC_FP64's bit for bit,
+  iters 64 + its count); on a perfect lattice (one stencil shape) a network
+  that outputs the exact Psi finishes every node without a factorisation at a
+  gate that FP32 Psi can meet, with the oracle's weights to FP32 accuracy.
+* full scale (2 M training stencils, the 1024^2 set): the three routes and
+  the LU-free one timed side by side; every route at the 1e-10 gate.
 """
 import sys
 
@@ -362,9 +369,46 @@ def test_mlp_training_and_warm_start(env):
     assert m_tr <= m_zero
 
 
-@pytest.mark.skipif(not __import__("os").environ.get("LABFM_C4_FULL"),
-                    reason="full-scale warm-start measurement (2M training stencils, 1M-node evaluation); "
-                           "set LABFM_C4_FULL=1 to run it")
+def test_warm_start_without_factorisation(env):
+    torch, O, L = env["torch"], env["O"], env["L"]
+    k, ops, kmax = 4, 7, 16
+    P = O.p_of_k(k)
+    dims = (3 * kmax, 16, 3 * P)
+    cases = {}
+    for name, eps in (("jittered", 0.3), ("perfect", 0.0)):
+        E = MD.lattice_stencils(24, eps, 7, k, 2.85)
+        cases[name] = (E, [_dev(env, E[a]) for a in ("x", "y", "R", "order", "rp", "col")])
+    # (a) zero network: every node above the gate, all solved by the FP64 LU path
+    E, (xt, yt, Rt, ot, rpt, colt) = cases["jittered"]
+    zero = L.MLP(env["ctx"], dims=dims, order=k, ops=ops, kmax=kmax, seed=1)
+    zero.set_output_scaling(np.zeros(dims[-1]), np.zeros(dims[-1]))
+    ref = env["ctx"].weights(xt, yt, Rt, ot, rpt, colt, E["domain"], prec=L.PREC_FP64)
+    got = env["ctx"].weights(xt, yt, Rt, ot, rpt, colt, E["domain"], prec=L.PREC_MLP_NOLU, mlp=zero)
+    torch.cuda.synchronize()
+    assert torch.equal(got[0], ref[0]) and torch.equal(got[2], ref[2]) and torch.equal(got[3], ref[3])
+    assert torch.equal(got[4].to(torch.int32), ref[4].to(torch.int32) + 64)
+    # (b) the exact Psi of the one stencil shape, rounded to FP32: no node needs a factorisation
+    E, (xt, yt, Rt, ot, rpt, colt) = cases["perfect"]
+    psi, M, st = MD.targets(E, k, ops)
+    assert np.all(st == 0) and np.abs(psi - psi[0]).max() <= 1e-12 * np.abs(psi[0]).max()
+    exact = L.MLP(env["ctx"], dims=dims, order=k, ops=ops, kmax=kmax, seed=2)
+    exact.set_output_scaling(psi[0], np.zeros(dims[-1]))
+    w64, _, st, res, it = env["ctx"].weights(xt, yt, Rt, ot, rpt, colt, E["domain"], prec=L.PREC_MLP_NOLU,
+                                             mlp=exact, tol_pass=1e-6)
+    torch.cuda.synchronize()
+    w_or, st_or, _, _ = O.weights(E["x"], E["y"], E["domain"], E["R"], E["order"], E["rp"], E["col"])
+    rel = np.abs(w64.cpu().numpy() - w_or).max() / np.abs(w_or).max()
+    _say("  no factorisation, exact Psi in FP32: max residual %.2e, weights vs oracle %.2e" %
+         (float(res.max()), rel))
+    assert np.all(st.cpu().numpy() == 0) and np.all(it.cpu().numpy() == 0) and float(res.max()) <= 1e-6
+    assert rel <= 1e-6
+    # at the 1e-10 gate the FP32 Psi cannot finish a node: all go to the FP64 path
+    w64, _, st, res, it = env["ctx"].weights(xt, yt, Rt, ot, rpt, colt, E["domain"], prec=L.PREC_MLP_NOLU,
+                                             mlp=exact)
+    torch.cuda.synchronize()
+    assert np.all(st.cpu().numpy() == 0) and np.all(it.cpu().numpy() >= 64) and float(res.max()) <= 1e-10
+
+
 def test_mlp_full_scale_measurement(env):
     """Configured scale: train on stencils of train_sets lattices, evaluate on the
     1024x1024 set against the mixed and FP64 paths (time per node, refinement
@@ -387,7 +431,8 @@ def test_mlp_full_scale_measurement(env):
     ot, rpt, colt = _dev(env, E["order"]), _dev(env, E["rp"]), _dev(env, E["col"])
     n = E["x"].size
     res = {}
-    for name, prec in (("fp64", L.PREC_FP64), ("mixed", L.PREC_MIXED), ("mlp", L.PREC_MLP)):
+    for name, prec in (("fp64", L.PREC_FP64), ("mixed", L.PREC_MIXED), ("mlp", L.PREC_MLP),
+                       ("nolu", L.PREC_MLP_NOLU)):
         out = env["ctx"].weights(xt, yt, Rt, ot, rpt, colt, E["domain"], prec=prec, mlp=net)
         torch.cuda.synchronize()
         ts = []
