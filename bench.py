@@ -149,6 +149,9 @@ def main():
     ap.add_argument("--no-3d", action="store_true", help="skip the three-dimensional weights measurement")
     ap.add_argument("--burgers-steps", type=int, default=200)
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-set batched weights measurement")
+    ap.add_argument("--no-c4", action="store_true", help="skip the learned warm start measurement")
+    ap.add_argument("--c4-train-sets", type=int, default=32, help="96x96 lattices of training stencils")
+    ap.add_argument("--c4-epochs", type=int, default=4)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device to device 4 times (counter calibration) and exit")
     args = ap.parse_args()
@@ -285,6 +288,7 @@ def main():
 
     if not args.no_rk4:
         rec["rk4_c5"] = run_rk4(ctx, torch, np, L, WL, args.rk4_steps)
+        rec["apply_fp32_c5"] = run_apply_c5(ctx, torch, np, L, WL)
     if not args.no_burgers:
         rec["burgers_1024"] = run_burgers(ctx, torch, np, L, WL, args.burgers_steps)
     if not args.no_poisson:
@@ -296,6 +300,8 @@ def main():
     if not args.no_batch:
         rec["batch_c3"] = run_batch(ctx, torch, np, L, WL, reps=3)
     rec["mlp_bf16"] = run_mlp(ctx, torch, L, WL)
+    if not args.no_c4:
+        rec["warm_start_c4"] = run_c4(ctx, torch, np, L, WL, args.c4_train_sets, args.c4_epochs)
 
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = run_cpu_baseline(nd, cfg)
@@ -380,6 +386,133 @@ def run_rk4(ctx, torch, np, L, WL, nsteps):
             "operator_apps_nodes_per_s": 12 * n / (ms_step / 1e3),
             "GB_per_s": bytes_step / (ms_step / 1e3) / 1e9, "hbm_frac": bytes_step / (ms_step / 1e3) / PEAK_HBM,
             "weights_all_ok": bool((st == 0).all().item()), "u_max": float(u.abs().max().item())}
+
+
+def run_apply_c5(ctx, torch, np, L, WL, reps=20):
+    """One FP32 operator (the Laplacian) applied on the 1024x1024 periodic
+    order-6 set: algorithmic bytes per node N (4 B index + 4 B weight) + 8 B
+    of row offset + 4 B u_i + 4 B result (408 B at the mean N)."""
+    dev = torch.device("cuda:0")
+    cfg = WL.config("c5")
+    nd = WL.make_nodes(cfg)
+    n = nd["x"].size
+    x = torch.from_numpy(nd["x"]).to(dev)
+    y = torch.from_numpy(nd["y"]).to(dev)
+    R = torch.from_numpy(nd["R"]).to(dev)
+    order = torch.from_numpy(nd["order"]).to(dev)
+    rp, col = ctx.build_neighbours(x, y, R, order, nd["domain"])
+    _, w32, st, _, _ = ctx.weights(x, y, R, order, rp, col, nd["domain"], ops=4, want64=False, want32=True)
+    u = torch.from_numpy(WL.gaussian_pulse(nd["x"], nd["y"])).to(dev).to(torch.float32)
+    w = w32[0].contiguous()
+    out = torch.empty(n, dtype=torch.float32, device=dev)
+    for _ in range(3):
+        ctx.apply_operator(rp, col, w, u, out=out.view(1, -1))
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    for _ in range(reps):
+        ctx.apply_operator(rp, col, w, u, out=out.view(1, -1))
+    torch.cuda.synchronize()
+    ctx.timing(False)
+    nk, ms = ctx.timing_read("apply_f32")
+    ctx.timing_read(None)
+    ms /= max(nk, 1)
+    nnz = col.numel()
+    bytes_launch = nnz * (4 + 4) + n * (8 + 4 + 4)
+    return {"nodes": n, "nnz": nnz, "ms_per_apply": ms, "nodes_per_s": n / (ms / 1e3),
+            "bytes_per_node": bytes_launch / n, "GB_per_s": bytes_launch / (ms / 1e3) / 1e9,
+            "hbm_frac": bytes_launch / (ms / 1e3) / PEAK_HBM,
+            "traffic": measured_traffic("apply_f32", ["apply.hip", "stencil_rows.hpp"]),
+            "weights_all_ok": bool((st == 0).all().item())}
+
+
+def run_c4(ctx, torch, np, L, WL, train_sets, epochs, batch=512, reps=3):
+    """Learned warm start end to end on the GPU: training stencils from jittered
+    96x96 periodic lattices (GPU neighbours, moment matrices and coefficients
+    from labfm_moment_systems, features), the network trained with the
+    library's kernels (moment-residual loss, Adam), then the 1024x1024 order-8
+    set through the FP64, mixed, warm-started and factorisation-free routes at
+    the 1e-10 gate: ms per 1 M nodes, fallback rate, refinement sweeps."""
+    dev = torch.device("cuda:0")
+    cfg = WL.config("c4")
+    k, ops, kmax = cfg["k"], cfg["ops"], cfg["kmax"]
+    t0 = time.perf_counter()
+    feats, Ms, psis = [], [], []
+    for i in range(train_sets):
+        seed = cfg["train_seed0"] + i
+        eps = float(np.random.default_rng(seed).uniform(0.0, cfg["eps_max"]))
+        xs, ys, s = WL.jittered_lattice(cfg["train_side"], eps=eps, seed=seed, periodic=True)
+        dom = WL.unit_domain(True)
+        x, y = torch.from_numpy(xs).to(dev), torch.from_numpy(ys).to(dev)
+        R = torch.full((xs.size,), cfg["R_s"] * s, dtype=torch.float64, device=dev)
+        order = torch.full((xs.size,), k, dtype=torch.int8, device=dev)
+        rp, col = ctx.build_neighbours(x, y, R, order, dom)
+        M, psi, st = ctx.moment_systems(x, y, R, k, rp, col, dom, ops=ops)
+        keep = st == 0
+        feats.append(ctx.mlp_features(x, y, R, rp, col, dom, kmax=kmax)[keep])
+        Ms.append(M[keep])
+        psis.append(psi[keep])
+    X = torch.cat(feats)
+    Mt = torch.cat(Ms)
+    del feats, Ms
+    # per-component median and 1.4826 x median absolute deviation of the training coefficients
+    P = torch.cat(psis).cpu().numpy().astype(np.float64)
+    mu = np.median(P, axis=0)
+    sd = 1.4826 * np.median(np.abs(P - mu), axis=0)
+    sd = np.where(sd > 0, sd, 1.0)
+    net = L.MLP(ctx, dims=cfg["dims"], order=k, ops=ops, kmax=kmax, seed=0)
+    net.set_output_scaling(mu, sd)
+    ntrain = X.shape[0]
+    g = torch.Generator(device="cuda").manual_seed(0)
+    cache = net.cache_for(batch)
+    steps = epochs * (ntrain // batch)
+    t = 0
+    for e in range(epochs):
+        perm = torch.randperm(ntrain, device="cuda", generator=g)
+        for b in range(ntrain // batch):
+            idx = perm[b * batch:(b + 1) * batch]
+            lr = cfg["lr"] * 0.5 * (1.0 + np.cos(np.pi * t / steps))
+            net.train_step(X[idx].contiguous(), Mt[idx].contiguous(), lr, cache=cache)
+            t += 1
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    # initial moment residual of the trained network on held-out stencils (first 65536 of the set)
+    xs, ys, s = WL.jittered_lattice(cfg["eval_side"], eps=cfg["eval_eps"], seed=cfg["eval_seed"], periodic=True)
+    dom = WL.unit_domain(True)
+    n = xs.size
+    x, y = torch.from_numpy(xs).to(dev), torch.from_numpy(ys).to(dev)
+    R = torch.full((n,), cfg["R_s"] * s, dtype=torch.float64, device=dev)
+    order = torch.full((n,), k, dtype=torch.int8, device=dev)
+    rp, col = ctx.build_neighbours(x, y, R, order, dom)
+    m = 65536
+    rp_s = rp[:m + 1].contiguous()
+    Me, _, st_e = ctx.moment_systems(x, y, R, k, rp_s, col, dom, ops=ops)
+    fe = ctx.mlp_features(x, y, R, rp, col, dom, kmax=kmax)[:m].contiguous()
+    r_tr = net.moment_loss(net.forward(fe), Me)[0].sqrt()
+    del Me, fe, X, Mt
+    torch.cuda.empty_cache()
+    routes = {}
+    for name, prec in (("fp64", L.PREC_FP64), ("mixed", L.PREC_MIXED), ("mlp", L.PREC_MLP),
+                       ("mlp_nolu", L.PREC_MLP_NOLU)):
+        out = ctx.weights(x, y, R, order, rp, col, dom, prec=prec, mlp=net)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * reps)]
+        for r_ in range(reps):
+            ev[2 * r_].record()
+            ctx.weights(x, y, R, order, rp, col, dom, prec=prec, mlp=net, out=out)
+            ev[2 * r_ + 1].record()
+        torch.cuda.synchronize()
+        ms = min(ev[2 * r_].elapsed_time(ev[2 * r_ + 1]) for r_ in range(reps))
+        st = out[2].cpu().numpy()
+        it = out[4].cpu().numpy().astype(np.int64)
+        res = out[3].cpu().numpy()
+        direct = it < 64
+        routes[name] = {"ms_per_1M_nodes": ms * (1 << 20) / n, "ns_per_node": 1e6 * ms / n,
+                        "nodes_ok": int((st == 0).sum()), "max_resid_ok": float(res[st == 0].max()),
+                        "fallback_nodes": int((~direct).sum()), "fallback_frac": float((~direct).mean()),
+                        "mean_sweeps": float(it[direct].mean()) if direct.any() else None}
+        del out
+    return {"train_stencils": int(ntrain), "train_sets": train_sets, "epochs": epochs, "train_s": t_train,
+            "eval_nodes": n, "initial_resid_median_trained": float(r_tr.median().item()),
+            "initial_resid_zero_start": 2.0, "routes": routes}
 
 
 def run_burgers(ctx, torch, np, L, WL, nsteps):

@@ -486,6 +486,21 @@ labfm_err labfm_mlp_features(void* ctx, const double* x, const double* y, int64_
                              const double* R, const int64_t* row_ptr, const int32_t* col, int kmax, float* feat,
                              void* stream);
 
+/* Training data of the warm start, made on the GPU: for every node i < n (all
+ * taken at order k, 1..8; x, y hold every node col refers to) with
+ * h_i = R_i / 2, the moment matrix of eq.
+ * (disc_form) in scaled offsets, M[i] = sum_j X(d_j) W(d_j)^T, FP32 [n][p][p]
+ * (row = monomial) as assembled, and the coefficients Psi^d of eq. (lsys) for
+ * opt->ops (the FP64 path's equilibration, partial-pivot LU and one solve, no
+ * refinement), FP32 [n][nops p] operator-major, which labfm_mlp_moment_loss
+ * and the network's output scaling take.  opt->abf, rbf, sigma, ops are used;
+ * prec, tolerances and max_iters are not.  status int8 [n] as labfm_weights
+ * (OK, SINGULAR, TOO_FEW, TOO_MANY, DEGENERATE, ORDER_TOO_LOW); nodes that
+ * are not OK get zeros.  All arrays device memory.  Asynchronous. */
+labfm_err labfm_moment_systems(void* ctx, const double* x, const double* y, int64_t n, const labfm_domain* dom,
+                               const double* R, int k, const int64_t* row_ptr, const int32_t* col, int64_t nnz,
+                               const labfm_wopts* opt, float* M, float* psi, int8_t* status, void* stream);
+
 /* Forward pass of B rows: in FP32 [B][dims[0]] -> out FP32 [B][dims[n_layers]]
  * (de-normalised when denorm != 0).  cache (device FP32, NULL for inference):
  * receives, per hidden layer l, the pre-activations Z_l then the activations

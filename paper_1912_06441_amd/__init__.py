@@ -31,7 +31,7 @@ EXPORTED = sorted(["labfm_last_error", "labfm_create", "labfm_destroy", "labfm_b
                    "labfm_mlp_backward", "labfm_mlp_moment_loss", "labfm_mlp_adam", "labfm_mlp_cast_bf16",
                    "labfm_weights_batched", "labfm_autotune_query", "labfm_burgers_step",
                    "labfm_poisson_solve", "labfm_ns_step", "labfm_build_neighbours3", "labfm_weights3",
-                   "labfm_weights_noalloc", "labfm_neumann_rows"])
+                   "labfm_weights_noalloc", "labfm_neumann_rows", "labfm_moment_systems"])
 MLP_MAX_LAYERS = 8
 
 
@@ -128,6 +128,8 @@ def load_library(path=LIB_PATH):
     L.labfm_neumann_rows.argtypes = [vp, vp, vp, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.POINTER(i64), vp]
     L.labfm_poisson_solve.argtypes = [vp, C.POINTER(PoissonPlan), vp, vp, vp, C.POINTER(C.c_int),
                                       C.POINTER(C.c_double), C.POINTER(C.c_int), vp]
+    L.labfm_moment_systems.argtypes = [vp, vp, vp, i64, C.POINTER(Domain), vp, C.c_int, vp, vp, i64, C.POINTER(WOpts),
+                                       vp, vp, vp, vp]
     L.labfm_mlp_features.argtypes = [vp, vp, vp, i64, C.POINTER(Domain), vp, vp, vp, C.c_int, vp, vp]
     L.labfm_mlp_forward.argtypes = [vp, C.POINTER(MLPDesc), vp, i64, vp, vp, C.c_int, vp]
     L.labfm_mlp_cache_floats.argtypes = [C.POINTER(MLPDesc), i64]
@@ -461,6 +463,28 @@ class Context:
         _check(self.lib.labfm_mlp_features(self.h, _ptr(x), _ptr(y), n, C.byref(dom), _ptr(R), _ptr(row_ptr),
                                            _ptr(col), int(kmax), _ptr(feat), _stream(torch)), "labfm_mlp_features")
         return feat
+
+    def moment_systems(self, x, y, R, k, row_ptr, col, domain, ops=OP_DX | OP_DY | OP_LAP, abf=ABF_HERMITE,
+                       rbf=RBF_WENDLAND_C2, sigma=1.0):
+        """Training data of the warm start for the first n = row_ptr.numel() - 1
+        nodes, at order k (x, y hold every node col refers to): moment matrices
+        [n, p, p] FP32 (as assembled), coefficients Psi [n, nops p] FP32
+        (operator-major) and status [n] int8."""
+        torch = self.torch
+        n = row_ptr.numel() - 1
+        for nm, t in (("x", x), ("y", y), ("R", R)):
+            _need(nm, t, torch.float64, n)
+        _need_csr(torch, row_ptr, col, n)
+        p = (k * k + 3 * k) // 2
+        M = torch.empty((n, p, p), dtype=torch.float32, device=x.device)
+        psi = torch.empty((n, nops_of(ops) * p), dtype=torch.float32, device=x.device)
+        st = torch.empty(n, dtype=torch.int8, device=x.device)
+        o = WOpts(int(abf), int(rbf), float(sigma), int(ops), PREC_FP64, 0.0, 0.0, 0, None)
+        dom = make_domain(domain)
+        _check(self.lib.labfm_moment_systems(self.h, _ptr(x), _ptr(y), n, C.byref(dom), _ptr(R), int(k),
+                                             _ptr(row_ptr), _ptr(col), col.numel(), C.byref(o), _ptr(M), _ptr(psi),
+                                             _ptr(st), _stream(torch)), "labfm_moment_systems")
+        return M, psi, st
 
     # ------------------------------------------------------------------ time stepping
     def step(self, row_ptr, col, w_lin, w_bh, gamma, dt, u, nsteps, scratch=None, use_graph=True, fixed=None):

@@ -606,6 +606,27 @@ labfm_err labfm_mlp_features(void* ctx, const double* x, const double* y, int64_
                         dom->periodic[0] != 0, dom->periodic[1] != 0, kmax, feat, (hipStream_t)stream);
 }
 
+labfm_err labfm_moment_systems(void* ctx, const double* x, const double* y, int64_t n, const labfm_domain* dom,
+                               const double* R, int k, const int64_t* row_ptr, const int32_t* col, int64_t nnz,
+                               const labfm_wopts* opt, float* M, float* psi, int8_t* status, void* stream) {
+    if (!ctx || !opt) return fail(LABFM_EINVAL, "labfm_moment_systems: ctx or opt is NULL");
+    if (n < 0 || n > INT32_MAX || nnz < 0) return fail(LABFM_EINVAL, "labfm_moment_systems: n or nnz out of range");
+    if (k < 1 || k > LABFM_MAX_ORDER) return fail(LABFM_EINVAL, "labfm_moment_systems: k must be 1..8");
+    if (!domain_ok(dom)) return fail(LABFM_EINVAL, "labfm_moment_systems: bad domain");
+    if (opt->ops == 0 || (opt->ops & ~31u)) return fail(LABFM_EINVAL, "labfm_moment_systems: bad ops");
+    if (opt->abf < LABFM_ABF_HERMITE || opt->abf > LABFM_ABF_PAPER_D1) return fail(LABFM_EINVAL, "labfm_moment_systems: bad abf");
+    if (opt->rbf < 0 || opt->rbf > 4) return fail(LABFM_EINVAL, "labfm_moment_systems: bad rbf");
+    if (!(opt->sigma > 0.0) || !std::isfinite(opt->sigma)) return fail(LABFM_EINVAL, "labfm_moment_systems: sigma must be > 0");
+    if (n > 0 && (!x || !y || !R || !row_ptr || !M || !psi || !status || (nnz > 0 && !col)))
+        return fail(LABFM_EINVAL, "labfm_moment_systems: NULL array");
+    Context* c = (Context*)ctx;
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(LABFM_EHIP, "labfm_moment_systems: hipSetDevice failed");
+    WeightArgs a;
+    one_set_args(a, x, y, n, dom, R, nullptr, row_ptr, col, nnz, opt, nullptr, nullptr, status, nullptr, nullptr);
+    return moment_systems(c, a, k, M, psi, status, (hipStream_t)stream);
+}
+
 int64_t labfm_mlp_cache_floats(const labfm_mlp* net, int64_t B) {
     std::string why;
     if (!mlp_ok(net, why) || B < 0) return -1;

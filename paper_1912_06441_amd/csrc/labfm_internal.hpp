@@ -227,6 +227,9 @@ labfm_err mlp_moment_loss(Context* c, const float* y, const float* M, const floa
 labfm_err mlp_adam(Context* c, float* p, const float* g, float* m, float* v, void* pb, int64_t n, const labfm_adam* hp,
                    int64_t t, hipStream_t st);
 labfm_err mlp_cast_bf16(const float* src, void* dst, int64_t n, hipStream_t st);
+// training data of the warm start: M (FP32 [n][p][p]) and Psi (FP32 [n][nops p]) of every node, order k
+labfm_err moment_systems(Context* c, const WeightArgs& a, int k, float* M, float* psi, int8_t* status,
+                         hipStream_t st);
 // learned warm start: refine from the network's Psi0 with the FP32 factors (direct = false), or
 // take Psi0 without a factorisation and solve the nodes it leaves above tol_pass on the FP64 path
 labfm_err weights_mlp(Context* c, const WeightArgs& a, int32_t* wl, int32_t* rl, const labfm_mlp* net,

@@ -546,6 +546,241 @@ labfm_err colsum(Context* c, const float* Z, int64_t M, int N, int64_t ld, float
     return LABFM_OK;
 }
 
+// ------------------------------------------------------------------ training data
+// For every node (all of order K) the moment matrix M = sum_j X(d_j) W(d_j)^T
+// of eq. (disc_form) in scaled offsets, written in FP32 [p][p] (row =
+// monomial) as assembled, and the coefficients Psi^d of eq. (lsys) from the
+// FP64 path's equilibration, partial-pivot LU and one solve (no refinement),
+// in FP32, operator-major [nops][p].  Nodes that are not OK get zeros.  The
+// assembly, equilibration and LU are the FP64 weight kernel's steps.
+template <int K, int FAM>
+__global__ __launch_bounds__(64) void k_moment_systems(WeightArgs a, OpList ops, float* __restrict__ Mo,
+                                                       float* __restrict__ psio, int8_t* __restrict__ sto) {
+    constexpr int P = p_of_k(K);
+    constexpr int BS = (P + 7) / 8;
+    constexpr int PP = 8 * BS;
+    constexpr int LD = P + 1;
+
+    __shared__ double sM[P * LD];
+    __shared__ double sChunk[2 * CH * PP];
+    __shared__ double sD[2][NMAX];
+    __shared__ double sRs[P], sCs[P];
+    __shared__ int sPerm[P];
+
+    const NodeSet& S = a.one;
+    const int lane = threadIdx.x;
+    const int nops = ops.nops;
+
+    for (int64_t i = blockIdx.x; i < S.n; i += gridDim.x) {
+        const int64_t s0 = S.row_ptr[i];
+        const int N = (int)(S.row_ptr[i + 1] - s0);
+        const double h = 0.5 * S.R[i];
+        int status = LABFM_ST_OK;
+        for (int d = 0; d < nops; ++d)
+            if (K < min_order(ops.op[d])) status = LABFM_ST_ORDER_TOO_LOW;
+        if (status == LABFM_ST_OK && N < P) status = LABFM_ST_TOO_FEW;
+        if (status == LABFM_ST_OK && N > NMAX) status = LABFM_ST_TOO_MANY;
+        if (status == LABFM_ST_OK) {
+            const double xi = S.x[i], yi = S.y[i];
+            bool bad = false;
+            for (int q = lane; q < N; q += 64) {
+                const int32_t j = S.col[s0 + q];
+                const double dx = min_image(S.x[j] - xi, S.Lx, S.perx) / h;
+                const double dy = min_image(S.y[j] - yi, S.Ly, S.pery) / h;
+                sD[0][q] = dx;
+                sD[1][q] = dy;
+                if (FAM != LABFM_ABF_HERMITE && dx == 0.0 && dy == 0.0) bad = true;
+            }
+            if (__any(bad)) status = LABFM_ST_DEGENERATE;
+        }
+        __syncthreads();
+
+        if (status == LABFM_ST_OK) {
+            // ---- assembly: M = sum_j X(d_j) W(d_j)^T, register-blocked
+            const int lr = lane / 8, lc = lane % 8;
+            double acc[BS][BS];
+#pragma unroll
+            for (int r = 0; r < BS; ++r)
+#pragma unroll
+                for (int c = 0; c < BS; ++c) acc[r][c] = 0.0;
+            double* sX = sChunk;
+            double* sW = sChunk + CH * PP;
+            for (int j0 = 0; j0 < N; j0 += CH) {
+                if (lane < 2 * CH) {
+                    const int jj = lane % CH;
+                    const int j = j0 + jj;
+                    double* dst = (lane < CH ? sX : sW) + jj * PP;
+                    if (j < N) {
+                        BasisState<K> B;
+                        basis_prepare<K, FAM>(B, sD[0][j], sD[1][j], a.rbf, a.sigma);
+                        if (lane < CH) {
+#pragma unroll
+                            for (int m = 0; m < P; ++m) dst[m] = monomial<K>(B, m);
+                        } else {
+#pragma unroll
+                            for (int m = 0; m < P; ++m) dst[m] = abf<K, FAM>(B, m);
+                        }
+                    } else {
+#pragma unroll
+                        for (int m = 0; m < P; ++m) dst[m] = 0.0;
+                    }
+#pragma unroll
+                    for (int m = P; m < PP; ++m) dst[m] = 0.0;
+                }
+                __syncthreads();
+                const int jmax = min(CH, N - j0);
+                for (int jj = 0; jj < jmax; ++jj) {
+                    double xv[BS], wv[BS];
+#pragma unroll
+                    for (int r = 0; r < BS; ++r) xv[r] = sX[jj * PP + lr * BS + r];
+#pragma unroll
+                    for (int c = 0; c < BS; ++c) wv[c] = sW[jj * PP + lc * BS + c];
+#pragma unroll
+                    for (int r = 0; r < BS; ++r)
+#pragma unroll
+                        for (int c = 0; c < BS; ++c) acc[r][c] = fma(xv[r], wv[c], acc[r][c]);
+                }
+                __syncthreads();
+            }
+#pragma unroll
+            for (int r = 0; r < BS; ++r)
+#pragma unroll
+                for (int c = 0; c < BS; ++c) {
+                    int m = lr * BS + r, nn = lc * BS + c;
+                    if (m < P && nn < P) sM[m * LD + nn] = acc[r][c];
+                }
+            __syncthreads();
+
+            // the moment matrix as assembled, before any scaling
+            for (int e = lane; e < P * P; e += 64) Mo[i * (int64_t)(P * P) + e] = (float)sM[(e / P) * LD + e % P];
+            __syncthreads();
+
+            // ---- equilibration: rows, then columns
+            bool sing = false;
+            if (lane < P) {
+                double mx = 0.0;
+                for (int c = 0; c < P; ++c) mx = fmax(mx, fabs(sM[lane * LD + c]));
+                if (!(mx > 0.0) || !isfinite(mx)) sing = true;
+                double rs = 1.0 / mx;
+                sRs[lane] = rs;
+                for (int c = 0; c < P; ++c) sM[lane * LD + c] *= rs;
+            }
+            __syncthreads();
+            if (lane < P) {
+                double mx = 0.0;
+                for (int r = 0; r < P; ++r) mx = fmax(mx, fabs(sM[r * LD + lane]));
+                if (!(mx > 0.0) || !isfinite(mx)) sing = true;
+                double cs = 1.0 / mx;
+                sCs[lane] = cs;
+                for (int r = 0; r < P; ++r) sM[r * LD + lane] *= cs;
+            }
+            __syncthreads();
+            if (__any(sing)) status = LABFM_ST_SINGULAR;
+
+            // ---- LU with partial pivoting (ties: lowest row)
+            int perm = lane;
+            if (status == LABFM_ST_OK) {
+                for (int kk = 0; kk < P; ++kk) {
+                    // pivot: largest |M[r][kk]| over r >= kk, ties to the lowest row
+                    const double v = (lane >= kk && lane < P) ? fabs(sM[lane * LD + kk]) : -1.0;
+                    const double vmax = wave_max_double(v);
+                    const unsigned long long hit = __ballot(v == vmax);
+                    if (!(vmax > 0.0) || !isfinite(vmax) || hit == 0ull) {
+                        status = LABFM_ST_SINGULAR;
+                        break;
+                    }
+                    const int pr = __ffsll((long long)hit) - 1;
+                    if (pr != kk) {
+                        if (lane < P) {
+                            const double u = sM[kk * LD + lane];
+                            sM[kk * LD + lane] = sM[pr * LD + lane];
+                            sM[pr * LD + lane] = u;
+                        }
+                        // permutation bookkeeping: position kk <-> pr
+                        const int pk = __builtin_amdgcn_readlane(perm, kk), pp = __builtin_amdgcn_readlane(perm, pr);
+                        if (lane == kk) perm = pp;
+                        if (lane == pr) perm = pk;
+                    }
+                    __syncthreads();
+                    // one pass: lane c > kk updates column c of the trailing rows, lane kk
+                    // stores the multipliers l_r = M[r][kk] / M[kk][kk] (every lane reads
+                    // M[r][kk] before lane kk overwrites it; rows in groups of eight)
+                    if (lane >= kk && lane < P) {
+                        const double inv = 1.0 / sM[kk * LD + kk];
+                        const double u = sM[kk * LD + lane];
+                        const bool own = lane == kk;
+                        int r = kk + 1;
+                        for (; r + 8 <= P; r += 8) {
+                            double l[8], a[8];
+#pragma unroll
+                            for (int e = 0; e < 8; ++e) {
+                                l[e] = sM[(r + e) * LD + kk];
+                                a[e] = sM[(r + e) * LD + lane];
+                            }
+#pragma unroll
+                            for (int e = 0; e < 8; ++e) {
+                                const double m = l[e] * inv;
+                                sM[(r + e) * LD + lane] = own ? m : fma(-m, u, a[e]);
+                            }
+                        }
+                        for (; r < P; ++r) {
+                            const double m = sM[r * LD + kk] * inv;
+                            const double a0 = sM[r * LD + lane];
+                            sM[r * LD + lane] = own ? m : fma(-m, u, a0);
+                        }
+                    }
+                    __syncthreads();
+                }
+            }
+            if (lane < P) sPerm[lane] = perm;
+            __syncthreads();
+            if (status == LABFM_ST_OK) {
+                double b[MAXOPS];
+#pragma unroll
+                for (int d = 0; d < MAXOPS; ++d) b[d] = (d < nops) ? target(ops.op[d], lane) : 0.0;
+                lu_solve<P, LD>(sM, sRs, sCs, sPerm, b, nops);
+                if (lane < P)
+                    for (int d = 0; d < nops; ++d) psio[(i * nops + d) * (int64_t)P + lane] = (float)b[d];
+            }
+        }
+        if (status != LABFM_ST_OK) {
+            for (int e = lane; e < P * P; e += 64) Mo[i * (int64_t)(P * P) + e] = 0.f;
+            for (int e = lane; e < nops * P; e += 64) psio[i * (int64_t)(nops * P) + e] = 0.f;
+        }
+        if (lane == 0) sto[i] = (int8_t)status;
+        __syncthreads();
+    }
+}
+
+template <int K, int FAM>
+void launch_moment_systems(const WeightArgs& a, const OpList& ops, float* Mo, float* psio, int8_t* sto,
+                           hipStream_t st) {
+    static int grid = 0;
+    if (grid == 0) {
+        int dev = 0, ncu = 0, per = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_moment_systems<K, FAM>, 64, 0);
+        grid = (ncu > 0 ? ncu : 256) * (per > 0 ? per : 1);
+    }
+    k_moment_systems<K, FAM><<<grid, 64, 0, st>>>(a, ops, Mo, psio, sto);
+}
+
+template <int FAM>
+void moment_systems_fam(const WeightArgs& a, const OpList& ops, int k, float* Mo, float* psio, int8_t* sto,
+                        hipStream_t st) {
+    switch (k) {
+        case 1: launch_moment_systems<1, FAM>(a, ops, Mo, psio, sto, st); break;
+        case 2: launch_moment_systems<2, FAM>(a, ops, Mo, psio, sto, st); break;
+        case 3: launch_moment_systems<3, FAM>(a, ops, Mo, psio, sto, st); break;
+        case 4: launch_moment_systems<4, FAM>(a, ops, Mo, psio, sto, st); break;
+        case 5: launch_moment_systems<5, FAM>(a, ops, Mo, psio, sto, st); break;
+        case 6: launch_moment_systems<6, FAM>(a, ops, Mo, psio, sto, st); break;
+        case 7: launch_moment_systems<7, FAM>(a, ops, Mo, psio, sto, st); break;
+        default: launch_moment_systems<8, FAM>(a, ops, Mo, psio, sto, st); break;
+    }
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ host entry points (internal)
@@ -735,6 +970,24 @@ labfm_err mlp_cast_bf16(const float* src, void* dst, int64_t n, hipStream_t st) 
 // MLP_CHUNK nodes), then the mixed kernels start the order-net->order systems
 // from Psi0 and the FP64 kernels take the nodes that do not converge.
 constexpr int64_t MLP_CHUNK = 65536;
+
+labfm_err moment_systems(Context* c, const WeightArgs& a, int k, float* M, float* psi, int8_t* status,
+                         hipStream_t st) {
+    if (a.one.n == 0) return LABFM_OK;
+    OpList ops{};
+    ops.nops = 0;
+    for (int b = 0; b < 5; ++b)
+        if (a.ops & (1u << b)) ops.op[ops.nops++] = 1u << b;
+    KernelTimer timer(c, "moment_systems", st);
+    if (a.abf == LABFM_ABF_HERMITE)
+        moment_systems_fam<LABFM_ABF_HERMITE>(a, ops, k, M, psi, status, st);
+    else if (a.abf == LABFM_ABF_PAPER)
+        moment_systems_fam<LABFM_ABF_PAPER>(a, ops, k, M, psi, status, st);
+    else
+        moment_systems_fam<LABFM_ABF_PAPER_D1>(a, ops, k, M, psi, status, st);
+    LABFM_HIP_CHECK(hipGetLastError());
+    return LABFM_OK;
+}
 
 labfm_err weights_mlp(Context* c, const WeightArgs& a0, int32_t* wl, int32_t* rl, const labfm_mlp* net,
                       hipStream_t st, bool direct) {

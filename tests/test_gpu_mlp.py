@@ -369,6 +369,34 @@ def test_mlp_training_and_warm_start(env):
     assert m_tr <= m_zero
 
 
+@pytest.mark.parametrize("k,abf,rbf", [(8, 0, 0), (4, 2, 2)])
+def test_moment_systems_parity(env, k, abf, rbf):
+    """Training data made on the GPU: moment matrices within FP32 rounding of the
+    oracle's, coefficients within 1e-5 per node (one FP64 solve, then FP32),
+    statuses equal."""
+    O = env["O"]
+    E = MD.lattice_stencils(40, 0.3, 11, k, {8: 4.4, 4: 2.85}[k], periodic=(k == 8))
+    dx, dy, N = MD.padded_offsets(E)
+    psi_o, st_o, _, M_o = O.stencils_psi(k, dx, dy, N, want_M=True, ops=7, family=abf, rbf=rbf)
+    xt, yt, Rt = _dev(env, E["x"]), _dev(env, E["y"]), _dev(env, E["R"])
+    rpt, colt = _dev(env, E["rp"]), _dev(env, E["col"])
+    M, psi, st = env["ctx"].moment_systems(xt, yt, Rt, k, rpt, colt, E["domain"], ops=7, abf=abf, rbf=rbf)
+    env["torch"].cuda.synchronize()
+    M, psi, st = M.cpu().numpy(), psi.cpu().numpy(), st.cpu().numpy()
+    ok = st_o == 0
+    assert np.all(st[ok] == 0) and ok.mean() > 0.9
+    final = (st_o != 0) & (st_o != 1)  # failures before any refinement
+    assert np.array_equal(st[final], st_o[final])
+    dM = np.abs(M[ok] - M_o[ok]).max(axis=(1, 2)) / np.abs(M_o[ok]).max(axis=(1, 2))
+    po = psi_o.reshape(psi_o.shape[0], -1)[ok]
+    dP = np.abs(psi[ok] - po).max(axis=1) / np.abs(po).max(axis=1)
+    _say("  moment systems k=%d abf %d: M rel max %.2e, Psi rel max %.2e median %.2e" %
+         (k, abf, dM.max(), dP.max(), np.median(dP)))
+    assert dM.max() <= 1e-6 and dP.max() <= 1e-5
+    bad = st != 0
+    assert np.all(M[bad] == 0) and np.all(psi[bad] == 0)
+
+
 def test_warm_start_without_factorisation(env):
     torch, O, L = env["torch"], env["O"], env["L"]
     k, ops, kmax = 4, 7, 16
