@@ -297,6 +297,8 @@ def main():
         rec["taylor_green_256"] = run_ns(ctx, torch, np, L, WL)
     if not args.no_3d:
         rec["weights3d_64"] = run_weights3d(ctx, torch, np, L, WL)
+        rec["weights3d_32_k5"] = run_weights3d(ctx, torch, np, L, WL, side=32, k=5)
+        rec["weights3d_32_k6"] = run_weights3d(ctx, torch, np, L, WL, side=32, k=6)
     if not args.no_batch:
         rec["batch_c3"] = run_batch(ctx, torch, np, L, WL, reps=3)
     rec["mlp_bf16"] = run_mlp(ctx, torch, L, WL)
@@ -645,12 +647,14 @@ def run_ns(ctx, torch, np, L, WL, side=256, k=6, nsteps=10):
             "weights_all_ok": bool((st == 0).all().item())}
 
 
-def run_weights3d(ctx, torch, np, L, WL, reps=3):
-    """Three-dimensional FP64 weights {dx, dy, lap, dz} of order 4 (p = 34) on a
-    64^3 periodic lattice: neighbours, then weight sets per second."""
+def run_weights3d(ctx, torch, np, L, WL, reps=3, side=None, k=None):
+    """Three-dimensional FP64 weights {dx, dy, lap, dz} of order k (4: p = 34,
+    the 64^3 default) on a periodic lattice: neighbours, then weight sets per
+    second."""
     dev = torch.device("cuda:0")
     cfg = WL.config("c3d")
-    side, k = cfg["bench_side"], cfg["bench_k"]
+    side = cfg["bench_side"] if side is None else side
+    k = cfg["bench_k"] if k is None else k
     x_np, y_np, z_np, s = WL.jittered_lattice3(side, eps=cfg["eps"], seed=cfg["seed"], periodic=True)
     n = x_np.size
     x, y, z = (torch.from_numpy(a).to(dev) for a in (x_np, y_np, z_np))
@@ -674,7 +678,7 @@ def run_weights3d(ctx, torch, np, L, WL, reps=3):
     st_np = st.cpu().numpy()
     N = np.diff(rp.cpu().numpy()).astype(np.float64)
     its = it.cpu().numpy().astype(np.float64)
-    p, nd = 34, 4
+    p, nd = sum(m * (m + 1) // 2 for m in range(2, k + 2)), 4
     flops = float((2 * N * p * p + 2 * p ** 3 / 3 + (1 + its) * (2 * nd * p * p + 4 * N * p * nd)).sum())
     return {"nodes": n, "nnz": col.numel(), "order": k, "p": p, "mean_N": float(N.mean()), "ms": ms,
             "neighbours_ms": t_neigh, "weight_sets_per_s": int((st_np == 0).sum()) / (ms / 1e3),
