@@ -97,13 +97,20 @@ def run_cpu_baseline(nd, cfg, runs=5, sample1=8192):
     f = WL.trig_field(nd["x"], nd["y"], WL.trig_poly(0))[0]
     threads = O.num_threads()
     rates, good = [], 0
+    stage = {"neighbours": [], "weights": [], "apply_3ops": []}
     for _ in range(runs):
         t0 = time.perf_counter()
         rp, col, R = O.neighbours(nd["x"], nd["y"], nd["domain"], nd["R"], nd["order"])
+        t1 = time.perf_counter()
         w, st, res, _ = O.weights(nd["x"], nd["y"], nd["domain"], R, nd["order"], rp, col)
+        t2 = time.perf_counter()
         for d in range(3):
             O.apply(rp, col, w[d], f)
-        dt = time.perf_counter() - t0
+        t3 = time.perf_counter()
+        dt = t3 - t0
+        stage["neighbours"].append(1e3 * (t1 - t0))
+        stage["weights"].append(1e3 * (t2 - t1))
+        stage["apply_3ops"].append(1e3 * (t3 - t2))
         good = int(((st == 0) & (nd["order"] == 8)).sum())
         rates.append(good / dt)
     # one thread: weights of a sample of order-8 nodes
@@ -128,6 +135,7 @@ def run_cpu_baseline(nd, cfg, runs=5, sample1=8192):
             "sample": "the full 512x512 workload, whole steps (neighbours + FP64 weights + 3 operators), "
                       "median of %d runs (%d order-8 nodes at the gate per run)" % (runs, good),
             "runs": [round(r, 1) for r in rates], "nproc": nproc, "cpu_model": model,
+            "stage_ms_median": {k: float(np.median(v)) for k, v in stage.items()},
             "single_thread": {"value": float(np.median(rates1)), "unit": "weight-sets/s (order 8)", "cores": 1,
                               "sample": "FP64 weights of %d seeded order-8 nodes of the same workload, "
                                         "median of %d runs" % (good1, runs),
