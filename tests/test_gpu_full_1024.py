@@ -176,3 +176,36 @@ def test_full_rk4_1000_steps(full):
     _say("  1000 FP32 steps vs FP64 oracle: %.2e; L2 vs free-space solution: gpu %.2e oracle %.2e" %
          (err, np.linalg.norm(g - ex) / np.linalg.norm(ex), np.linalg.norm(ref - ex) / np.linalg.norm(ex)))
     assert err <= 1e-3
+
+
+def test_full_rk4_step_growth(full):
+    """Reading of the configured time step: on this node set the RK4 step map
+    with the composed hyperviscosity grows at dt = 0.2 s and decays at the
+    0.1 s the benchmark runs (power iteration of the FP64 step on the GPU; the
+    oracle at full size gives 5.05 and 0.993 per step)."""
+    f = full
+    torch = f["torch"]
+    cfg, nd = f["cfg"], f["nd"]
+    a, nu = cfg["a"], cfg["nu"]
+    wlin, _ = f["ctx"].combine(f["w64"][:3], [-a[0], -a[1], nu], want64=True, want32=False)
+    wbh = f["w64"][3].contiguous()
+    s = nd["s"]
+    h = 0.5 * cfg["R_s"] * s
+    n = nd["x"].size
+    growth = {}
+    for dts in (0.2, 0.1):
+        dt = dts * s
+        gamma = cfg["beta"] * h ** 8 / dt
+        g = torch.Generator(device="cuda").manual_seed(0)
+        u = torch.randn(n, dtype=torch.float64, device="cuda", generator=g)
+        u /= u.norm()
+        scratch = torch.empty(5 * n, dtype=torch.float64, device="cuda")
+        rates = []
+        for _ in range(40):
+            f["ctx"].step(f["rp"], f["col"], wlin, wbh, gamma, dt, u, 1, scratch=scratch)
+            nrm = u.norm()
+            rates.append(float(nrm))
+            u /= nrm
+        growth[dts] = float(np.mean(rates[-10:]))
+    _say("  RK4 step growth per step: dt = 0.2 s %.3f, dt = 0.1 s %.4f" % (growth[0.2], growth[0.1]))
+    assert growth[0.2] > 2.0 and growth[0.1] < 1.0
