@@ -100,9 +100,10 @@ __device__ inline double target3(unsigned op, int m) {
 // M = sum_j X(d_j) W(d_j)^T into sM (row stride P + 1).  Lane (lr, lc) of an
 // 8 x 8 grid owns the BS x BS block at (lr BS, lc BS) of the padded matrix;
 // the block's rows are accumulated RB at a time (one pass over the basis
-// chunks per group of RB rows), which bounds the accumulator registers.  Each
-// entry sums over j in ascending order whatever RB is.
-template <int K, int RB>
+// chunks per group of RB rows), which bounds the accumulator registers; CHN
+// neighbours per basis chunk.  Each entry sums over j in ascending order
+// whatever RB and CHN are.
+template <int K, int RB, int CHN = CH>
 __device__ inline void assemble3(double* sM, double* sChunk, const double (*sD)[NM3], int N, int rbf, double sigma) {
     constexpr int P = p3_of_k(K);
     constexpr int BS = (P + 7) / 8;
@@ -111,7 +112,7 @@ __device__ inline void assemble3(double* sM, double* sChunk, const double (*sD)[
     const int lane = threadIdx.x;
     const int lr = lane / 8, lc = lane % 8;
     double* sX = sChunk;
-    double* sW = sChunk + CH * PP;
+    double* sW = sChunk + CHN * PP;
 #pragma unroll
     for (int r0 = 0; r0 < BS; r0 += RB) {
         double acc[RB][BS];
@@ -119,15 +120,15 @@ __device__ inline void assemble3(double* sM, double* sChunk, const double (*sD)[
         for (int r = 0; r < RB; ++r)
 #pragma unroll
             for (int c = 0; c < BS; ++c) acc[r][c] = 0.0;
-        for (int j0 = 0; j0 < N; j0 += CH) {
-            if (lane < 2 * CH) {
-                const int jj = lane % CH;
+        for (int j0 = 0; j0 < N; j0 += CHN) {
+            if (lane < 2 * CHN) {
+                const int jj = lane % CHN;
                 const int j = j0 + jj;
-                double* dst = (lane < CH ? sX : sW) + jj * PP;
+                double* dst = (lane < CHN ? sX : sW) + jj * PP;
                 if (j < N) {
                     Basis3<K> B;
                     basis3_prepare<K>(B, sD[0][j], sD[1][j], sD[2][j], rbf, sigma);
-                    if (lane < CH) {
+                    if (lane < CHN) {
 #pragma unroll
                         for (int m = 0; m < P; ++m) dst[m] = monomial3<K>(B, m);
                     } else {
@@ -142,7 +143,7 @@ __device__ inline void assemble3(double* sM, double* sChunk, const double (*sD)[
                 for (int m = P; m < PP; ++m) dst[m] = 0.0;
             }
             __syncthreads();
-            const int jmax = min(CH, N - j0);
+            const int jmax = min(CHN, N - j0);
             for (int jj = 0; jj < jmax; ++jj) {
                 double xv[RB], wv[BS];
 #pragma unroll
@@ -195,14 +196,23 @@ __global__ __launch_bounds__(64) void k_weights3(W3Args a, OpList ops) {
     constexpr int LD = P + 1;
     constexpr int JS = NM3 / 64;
     static_assert(P <= 64, "one row per lane");
+    // From k = 5 the basis chunks (8 neighbours each) share one buffer with the
+    // coefficients and the scaled weights, which are used only after the
+    // assembly: 44 KB of LDS per node system, three per CU instead of two.
+    constexpr bool SHARE = K >= 5;
+    constexpr int CHK = SHARE ? 8 : CH;
+    constexpr int NU = SHARE ? cmax(2 * CHK * PP, MAXOPS * NM3 + MAXOPS * PP) : 2 * CH * PP;
 
     __shared__ double sM[P * LD];
-    __shared__ double sChunk[2 * CH * PP];
+    __shared__ double sU[NU];
     __shared__ double sD[3][NM3];
-    __shared__ double sWl[MAXOPS][NM3];
-    __shared__ double sPsi[MAXOPS][PP];
+    __shared__ double sWlA[SHARE ? 1 : MAXOPS * NM3];
+    __shared__ double sPsiA[SHARE ? 1 : MAXOPS * PP];
     __shared__ double sRs[P], sCs[P];
     __shared__ int sPerm[P];
+    double* const sChunk = sU;
+    double (*const sWl)[NM3] = reinterpret_cast<double (*)[NM3]>(SHARE ? sU : sWlA);
+    double (*const sPsi)[PP] = reinterpret_cast<double (*)[PP]>(SHARE ? sU + MAXOPS * NM3 : sPsiA);
 
     const int lane = threadIdx.x;
     const int nops = ops.nops;
@@ -241,7 +251,7 @@ __global__ __launch_bounds__(64) void k_weights3(W3Args a, OpList ops) {
 
         if (status == LABFM_ST_OK) {
             // ---- assembly: M = sum_j X(d_j) W(d_j)^T, register-blocked
-            assemble3<K, rb3(K)>(sM, sChunk, sD, N, a.rbf, a.sigma);
+            assemble3<K, rb3(K), CHK>(sM, sChunk, sD, N, a.rbf, a.sigma);
 
             // ---- equilibration: rows, then columns
             bool sing = false;
@@ -547,14 +557,21 @@ __global__ __launch_bounds__(64) void k_weights3w(W3Args a, OpList ops) {
     constexpr int PP = 8 * BS;
     constexpr int LD = P + 1;
     constexpr int JS = NM3 / 64;
+    // The basis chunks (CHW neighbours each) are needed only during the
+    // assembly, the coefficients and the scaled weights only after it: the two
+    // share one buffer, which keeps a node system under 80 KB of LDS so that
+    // two fit in a CU's 160 KB.
+    constexpr int CHW = 10;
+    constexpr int NU = cmax(2 * CHW * PP, MAXOPS * NM3 + MAXOPS * PP);
 
     __shared__ double sM[P * LD];
-    __shared__ double sChunk[2 * CH * PP];
+    __shared__ double sU[NU];
     __shared__ double sD[3][NM3];
-    __shared__ double sWl[MAXOPS][NM3];
-    __shared__ double sPsi[MAXOPS][PP];
     __shared__ double sRs[P], sCs[P];
     __shared__ int sPerm[P];
+    double* const sChunk = sU;
+    double (*const sWl)[NM3] = reinterpret_cast<double (*)[NM3]>(sU);
+    double (*const sPsi)[PP] = reinterpret_cast<double (*)[PP]>(sU + MAXOPS * NM3);
 
     const int lane = threadIdx.x;
     const int nops = ops.nops;
@@ -590,7 +607,7 @@ __global__ __launch_bounds__(64) void k_weights3w(W3Args a, OpList ops) {
         __syncthreads();
 
         if (status == LABFM_ST_OK) {
-            assemble3<K, rb3(K)>(sM, sChunk, sD, N, a.rbf, a.sigma);
+            assemble3<K, rb3(K), CHW>(sM, sChunk, sD, N, a.rbf, a.sigma);
 
             // ---- equilibration: rows, then columns (lane: rows / columns lane, lane + 64)
             bool sing = false;
