@@ -444,7 +444,7 @@ labfm_err labfm_ns_step(void* ctx, const labfm_ns_plan* plan, double* omega, dou
                         int* solver_iters, int* all_converged, void* stream);
 
 /* ---- three dimensions ----------------------------------------------------
- * Sec. 3.1 gives p in 3-D (3, 9, 19, 34 for k = 1..4).  Element m is (a, b, c)
+ * Sec. 3.1 gives p in 3-D (3, 9, 19, 34, 55, 83 for k = 1..6).  Element m is (a, b, c)
  * over total order n = 1..k with a = n..0, then b = n-a..0, c = n-a-b;
  * X_m = x^a y^b z^c / (a! b! c!); ABFs of the HERMITE family only,
  * H_a(s x) H_b(s y) H_c(s z) phi(|d|).  Operators: LABFM_OP_DX, _DY, _DZ
