@@ -50,6 +50,12 @@ def measured_traffic(kernel, sources):
     return None
 
 
+def factor_flops(N, p, nd):
+    """The factor kernel's share of weight_flops: basis evaluation 10Np, assembly
+    2Np^2, LU 2p^3/3 and the first solve 2 nd p^2."""
+    return 10.0 * N * p + 2.0 * N * p * p + 2.0 * p ** 3 / 3.0 + 2.0 * nd * p * p
+
+
 def weight_flops(N, p, nd, iters):
     """Algorithmic FP64 flops of one weight set: basis evaluation 10Np (the
     monomials and ABFs of every neighbour), assembly 2Np^2, LU 2p^3/3,
@@ -229,10 +235,11 @@ def main():
     ctx.timing(False)
     ms = (t1 - t0) * 1e3 / args.steps
     step_ms = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)])
-    # read the order-8 kernel separately, then every weights kernel
-    k8 = ctx.timing_read("weights64_k8")
+    # read the order-8 kernels (factor, then weights and refinement) separately, then every weights kernel
+    k8f = ctx.timing_read("weights64f_k8")
+    k8r = ctx.timing_read("weights64r_k8")
     kw_rest = ctx.timing_read("weights")
-    kw = (k8[0] + kw_rest[0], k8[1] + kw_rest[1])
+    kw = (k8f[0] + k8r[0] + kw_rest[0], k8f[1] + k8r[1] + kw_rest[1])
     kn = ctx.timing_read("neigh")
     ka = ctx.timing_read("apply")
     ctx.timing_read(None)
@@ -245,10 +252,17 @@ def main():
     good8 = int(((status == 0) & is8).sum())
     value = good8 / (ms / 1e3)
 
-    # roofline of the dominant kernel (order-8 weights), algorithmic flops per launch
-    flops8 = float(weight_flops(N[is8].astype(np.float64), 44, 3, iters[is8]).sum())
-    k8_ms = k8[1] / max(k8[0], 1)
-    achieved = flops8 / (k8_ms / 1e3)
+    # roofline of the dominant kernel (the order-8 factor kernel: basis, assembly, LU and the
+    # first solve), algorithmic flops per launch; and of the order-8 weights as a whole
+    N8 = N[is8].astype(np.float64)
+    flops8 = float(weight_flops(N8, 44, 3, iters[is8]).sum())
+    flops8f = float(factor_flops(N8, 44, 3).sum())
+    k8f_ms = k8f[1] / max(k8f[0], 1)
+    k8r_ms = k8r[1] / max(k8r[0], 1)
+    launches8 = max(k8f[0], 1) / args.steps  # launches per step (chunks of the work list)
+    achieved = flops8f / launches8 / (k8f_ms / 1e3)
+    k8_ms = (k8f[1] + k8r[1]) / args.steps
+    achieved8 = flops8 / (k8_ms / 1e3)
     # operator application: algorithmic bytes per launch (col 4 B + 3 FP64 weights per entry;
     # row_ptr, u_i and 3 FP64 outputs per node)
     apply_bytes = nnz * (4 + 3 * 8) + n * (8 + 8 + 3 * 8)
@@ -274,15 +288,20 @@ def main():
         "step_ms": {"median": float(np.median(step_ms)), "min": float(step_ms.min()), "max": float(step_ms.max()),
                     "steps": args.steps},
         "stages_ms": {"neighbours": kn[1] / args.steps, "weights": kw[1] / args.steps,
-                      "weights_order8_kernel": k8_ms, "apply_3ops": ka_ms},
+                      "weights_order8_kernels": k8_ms, "order8_factor_kernel": k8f_ms,
+                      "order8_refine_kernel": k8r_ms, "apply_3ops": ka_ms},
         "accuracy": {"nodes_passing_1e-10": int((status == 0).sum()), "nodes": n,
                      "max_moment_residual": float(resid.max()), "mean_refinement_iters": float(iters.mean())},
         "operator_apps": {"value": n / (ka_ms / 1e3), "unit": "nodes/s (3 fused FP64 operators)",
                           "GB_per_s": apply_bytes / (ka_ms / 1e3) / 1e9},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64,
-                     "traffic": measured_traffic("weights64_k8", ["weights.hip", "weights_common.hpp", "basis.hpp"]),
-                     "kernel": "weights64_k8", "flops_per_launch": flops8},
+                     "traffic": measured_traffic("weights64f_k8", ["weights_split.hip", "weights_common.hpp",
+                                                                   "basis.hpp"]),
+                     "kernel": "weights64f_k8", "flops_per_launch": flops8f / launches8},
+        "roofline_weights_order8": {"bound": "alu", "achieved": achieved8 / 1e12, "peak": PEAK_FP64 / 1e12,
+                                    "unit": "TFLOP/s", "frac": achieved8 / PEAK_FP64,
+                                    "kernels": ["weights64f_k8", "weights64r_k8"], "flops_per_step": flops8},
         "roofline_apply": {"bound": "hbm", "achieved": apply_bytes / (ka_ms / 1e3) / 1e9, "peak": PEAK_HBM / 1e9,
                            "unit": "GB/s", "frac": apply_bytes / (ka_ms / 1e3) / PEAK_HBM,
                            "traffic": measured_traffic("apply_f64", ["apply.hip", "stencil_rows.hpp"]),

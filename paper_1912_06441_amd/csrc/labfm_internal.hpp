@@ -43,6 +43,7 @@ struct Context {
     Scratch mlp_psi;      // network output Psi0 of every node [n][outputs]
     Scratch mlp_part;     // column-sum partials of the bias gradients
     Scratch poisson;      // reduction partials and scalars of the Krylov solve
+    Scratch factors;      // LU factors, scales, pivots and Psi of one chunk of FP64 node systems
     // cached RK4 step graph (replayed while plan, buffers and stream are unchanged)
     hipGraphExec_t step_exec = nullptr;
     hipStream_t step_stream = nullptr;
@@ -205,6 +206,9 @@ labfm_err weights_fp64_lists(Context* c, const WeightArgs& a, const int32_t* lis
                              const int32_t* cnt, unsigned mask, hipStream_t st);
 // whole computations; host_sets: host copy of the set table (nsets entries, or &a.one)
 labfm_err weights_fp64(Context* c, const WeightArgs& a, const NodeSet* host_sets, int32_t* wl, hipStream_t st);
+// the same FP64 weights in two kernels per order (factor, then weights and refinement), the
+// factors passing through the context's workspace; one node set (host_sets = &a.one)
+labfm_err weights_fp64_split(Context* c, const WeightArgs& a, const NodeSet* host_sets, int32_t* wl, hipStream_t st);
 // mixed kernels for the orders not in fp64_orders, FP64 kernels for those and for the retry list;
 // direct_order (1..8, needs NodeSet::psi0): that order takes the warm start's Psi0 without a
 // factorisation, its nodes above tol_pass go to the retry list.  rl: >= ntotal + KMAX + 2 int32

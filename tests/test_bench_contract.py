@@ -76,3 +76,11 @@ def test_weight_flops_terms():
 def test_cpu_model_reports_processor_count():
     name, nproc = bench.cpu_model()
     assert isinstance(name, str) and nproc >= 1
+
+
+def test_factor_flops_are_the_first_pass_of_weight_flops():
+    # the factor kernel: basis 10Np, assembly 2Np^2, LU 2p^3/3, first solve 2 nd p^2; the rest of
+    # weight_flops (weights and residual, and every refinement sweep) is the refine kernel's
+    N, p, nd = 60, 44, 3
+    assert bench.factor_flops(N, p, nd) == pytest.approx(10 * N * p + 2 * N * p * p + 2 * p ** 3 / 3 + 2 * nd * p * p)
+    assert bench.weight_flops(N, p, nd, 0) - bench.factor_flops(N, p, nd) == pytest.approx(4 * N * p * nd)
