@@ -4,9 +4,11 @@
 // Nasar: M = sum_j X(d_j) W(d_j)^T, M Psi = C, w = W Psi, refinement on the
 // moment residual r = C - X^T w), split where its resource needs change:
 //   * k_factor64: assembly, equilibration, partial-pivot LU and the first
-//     solve.  It needs few registers, and the basis chunks share M's LDS
-//     buffer (they are read only while M is still in registers), so two
-//     node systems run per SIMD.
+//     solve.  The basis chunks share M's LDS buffer (they are read only while
+//     M is still in registers), so two node systems run per SIMD.  The LU
+//     keeps one row of M per lane in registers and pivots by place instead of
+//     moving rows: each elimination step broadcasts the pivot row by
+//     readlane and updates the trailing rows without touching LDS.
 //   * k_refine64: weights w = W Psi, the FP64 moment residual and the
 //     refinement.  A node that needs a correction reads its factors back
 //     straight into registers (lane r takes row r), so the kernel keeps no
@@ -30,6 +32,26 @@ struct FactorWs {
     int32_t* perm;  // [slots][P]
     int8_t* st;     // [slots]
 };
+
+// v of another lane of the same row of 16, by a DPP move of both halves
+// (CTRL 0x121..0x12f: rotate the row right by 1..15 lanes)
+template <int CTRL>
+__device__ inline double dpp_d(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Maximum over the wavefront: rotations by 8, 4, 2 and 1 lanes leave every
+// lane with its row's maximum, then the four row maxima are combined.  fmax
+// skips NaN in any order, so the result is the same as a butterfly's.
+__device__ inline double wave_max_dpp(double v) {
+    v = fmax(v, dpp_d<0x128>(v));
+    v = fmax(v, dpp_d<0x124>(v));
+    v = fmax(v, dpp_d<0x122>(v));
+    v = fmax(v, dpp_d<0x121>(v));
+    return fmax(fmax(bcast(v, 0), bcast(v, 16)), fmax(bcast(v, 32), bcast(v, 48)));
+}
 
 template <int K, int FAM>
 __global__ __launch_bounds__(64) void k_factor64(WeightArgs a, OpList ops, const int32_t* list,
@@ -171,79 +193,86 @@ __global__ __launch_bounds__(64) void k_factor64(WeightArgs a, OpList ops, const
             __syncthreads();
             if (__any(sing)) status = LABFM_ST_SINGULAR;
 
-            // ---- LU with partial pivoting (ties: lowest row)
-            int perm = lane;
+            // ---- LU with partial pivoting, one row per lane in registers.  Rows
+            // stay in the lanes they were assembled in; pos is a row's place in
+            // the pivoted order, and ties of the pivot search go to the lowest
+            // place, as when rows are swapped in memory.
+            double row[P];
+#pragma unroll
+            for (int c = 0; c < P; ++c) row[c] = lane < P ? sM[lane * LD + c] : 0.0;
+            int pos = lane;  // lanes >= P are never candidates and never updated
             if (status == LABFM_ST_OK) {
+#pragma unroll
                 for (int kk = 0; kk < P; ++kk) {
-                    // pivot: largest |M[r][kk]| over r >= kk, ties to the lowest row
-                    const double v = (lane >= kk && lane < P) ? fabs(sM[lane * LD + kk]) : -1.0;
-                    const double vmax = wave_max_double(v);
+                    const double v = (pos >= kk && pos < P) ? fabs(row[kk]) : -1.0;
+                    const double vmax = wave_max_dpp(v);
                     const unsigned long long hit = __ballot(v == vmax);
                     if (!(vmax > 0.0) || !isfinite(vmax) || hit == 0ull) {
                         status = LABFM_ST_SINGULAR;
                         break;
                     }
-                    const int pr = __ffsll((long long)hit) - 1;
-                    if (pr != kk) {
-                        if (lane < P) {
-                            const double u = sM[kk * LD + lane];
-                            sM[kk * LD + lane] = sM[pr * LD + lane];
-                            sM[pr * LD + lane] = u;
-                        }
-                        // permutation bookkeeping: position kk <-> pr
-                        const int pk = __builtin_amdgcn_readlane(perm, kk), pp = __builtin_amdgcn_readlane(perm, pr);
-                        if (lane == kk) perm = pp;
-                        if (lane == pr) perm = pk;
-                    }
-                    __syncthreads();
-                    // one pass: lane c > kk updates column c of the trailing rows, lane kk
-                    // stores the multipliers l_r = M[r][kk] / M[kk][kk] (every lane reads
-                    // M[r][kk] before lane kk overwrites it; rows in groups of eight)
-                    if (lane >= kk && lane < P) {
-                        const double inv = 1.0 / sM[kk * LD + kk];
-                        const double u = sM[kk * LD + lane];
-                        const bool own = lane == kk;
-                        int r = kk + 1;
-                        for (; r + 8 <= P; r += 8) {
-                            double l[8], a[8];
+                    int pl = __ffsll((long long)hit) - 1;
+                    if (__popcll(hit) > 1) {  // tied candidates: the lowest place wins
+                        int cand = v == vmax ? pos : 1 << 20;
 #pragma unroll
-                            for (int e = 0; e < 8; ++e) {
-                                l[e] = sM[(r + e) * LD + kk];
-                                a[e] = sM[(r + e) * LD + lane];
-                            }
-#pragma unroll
-                            for (int e = 0; e < 8; ++e) {
-                                const double m = l[e] * inv;
-                                sM[(r + e) * LD + lane] = own ? m : fma(-m, u, a[e]);
-                            }
-                        }
-                        for (; r < P; ++r) {
-                            const double m = sM[r * LD + kk] * inv;
-                            const double a0 = sM[r * LD + lane];
-                            sM[r * LD + lane] = own ? m : fma(-m, u, a0);
-                        }
+                        for (int off = 32; off >= 1; off >>= 1) cand = min(cand, __shfl_xor(cand, off, 64));
+                        pl = __ffsll((long long)__ballot(pos == cand)) - 1;
                     }
-                    __syncthreads();
+                    const int ppos = __builtin_amdgcn_readlane(pos, pl);
+                    pos = lane == pl ? kk : (pos == kk ? ppos : pos);
+                    const double inv = 1.0 / bcast(row[kk], pl);
+                    const bool upd = pos > kk && pos < P;
+                    const double m = row[kk] * inv;
+#pragma unroll
+                    for (int c = kk + 1; c < P; ++c) {
+                        const double nv = fma(-m, bcast(row[c], pl), row[c]);
+                        row[c] = upd ? nv : row[c];
+                    }
+                    row[kk] = upd ? m : row[kk];
                 }
             }
-            if (lane < P) sPerm[lane] = perm;
+            if (lane < P) sPerm[pos] = lane;  // place -> row
             __syncthreads();
             if (status == LABFM_ST_OK) {
-                // ---- initial solve: lane m holds C^d[m]
-                double b[MAXOPS];
+                // ---- initial solve: lane m holds C^d[m] for row m; the value of
+                // place c lives in lane sPerm[c]
+                double t[MAXOPS];
+                const double rs = lane < P ? sRs[lane] : 0.0;
 #pragma unroll
-                for (int d = 0; d < MAXOPS; ++d) b[d] = (d < nops) ? target(ops.op[d], lane) : 0.0;
-                lu_solve<P, LD>(sM, sRs, sCs, sPerm, b, nops);
-                if (lane < P)
+                for (int d = 0; d < MAXOPS; ++d) t[d] = ((d < nops) ? target(ops.op[d], lane) : 0.0) * rs;
+#pragma unroll
+                for (int c = 0; c < P - 1; ++c) {
+                    const int src = sPerm[c];
+                    const double l = (pos > c && pos < P) ? row[c] : 0.0;
 #pragma unroll
                     for (int d = 0; d < MAXOPS; ++d)
-                        if (d < nops) w.psi[(slot * MAXOPS + d) * (int64_t)P + lane] = b[d];
-                const double* srcM = sM;
+                        if (d < nops) t[d] -= l * bcast(t[d], src);
+                }
+#pragma unroll
+                for (int c = P - 1; c >= 0; --c) {
+                    const int src = sPerm[c];
+                    const double u = pos < c ? row[c] : 0.0;
+#pragma unroll
+                    for (int d = 0; d < MAXOPS; ++d) {
+                        if (d < nops) {
+                            if (lane == src) t[d] = t[d] / row[c];
+                            t[d] -= u * bcast(t[d], src);
+                        }
+                    }
+                }
+                const int from = lane < P ? sPerm[lane] : 0;
+                const double cs = lane < P ? sCs[lane] : 0.0;
+#pragma unroll
+                for (int d = 0; d < MAXOPS; ++d) {
+                    const double z = __shfl(t[d], from, 64) * cs;
+                    if (lane < P && d < nops) w.psi[(slot * MAXOPS + d) * (int64_t)P + lane] = z;
+                }
                 double* lu = w.lu + slot * (int64_t)(P * P);
-                for (int e = lane; e < P * P; e += 64) lu[e] = srcM[(e % P) * LD + e / P];
                 if (lane < P) {
-                    w.rs[slot * (int64_t)P + lane] = sRs[lane];
-                    w.cs[slot * (int64_t)P + lane] = sCs[lane];
+#pragma unroll
+                    for (int c = 0; c < P; ++c) lu[c * P + pos] = row[c];
+                    w.rs[slot * (int64_t)P + lane] = rs;
+                    w.cs[slot * (int64_t)P + lane] = cs;
                     w.perm[slot * (int64_t)P + lane] = sPerm[lane];
                 }
             }
