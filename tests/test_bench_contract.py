@@ -45,6 +45,7 @@ def _recorded(kernel):
 
 @pytest.mark.parametrize("kernel,sources", [
     ("weights64_k8", ["weights.hip", "weights_common.hpp", "basis.hpp"]),
+    ("weights64f_k8", ["weights_split.hip", "weights_common.hpp", "basis.hpp"]),
     ("apply_f64", ["apply.hip", "stencil_rows.hpp"]),
 ])
 def test_traffic_follows_the_source_hash(kernel, sources):
