@@ -35,6 +35,13 @@ struct FactorWs {
 
 // v of another lane of the same row of 16, by a DPP move of both halves
 // (CTRL 0x121..0x12f: rotate the row right by 1..15 lanes)
+// Operator slots 0..NB-1 are always computed: a call with fewer operators
+// runs them on zero coefficients (zero right-hand sides, so zero solutions),
+// which keeps the common three-operator case free of per-slot branches.
+// Slots beyond NB follow the run-time count.
+constexpr int NB = 3;
+__device__ inline bool live(int d, int nops) { return d < NB || d < nops; }
+
 template <int CTRL>
 __device__ inline double dpp_d(double v) {
     const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
@@ -246,7 +253,7 @@ __global__ __launch_bounds__(64) void k_factor64(WeightArgs a, OpList ops, const
                     const double l = (pos > c && pos < P) ? row[c] : 0.0;
 #pragma unroll
                     for (int d = 0; d < MAXOPS; ++d)
-                        if (d < nops) t[d] -= l * bcast(t[d], src);
+                        if (live(d, nops)) t[d] -= l * bcast(t[d], src);
                 }
 #pragma unroll
                 for (int c = P - 1; c >= 0; --c) {
@@ -254,7 +261,7 @@ __global__ __launch_bounds__(64) void k_factor64(WeightArgs a, OpList ops, const
                     const double u = pos < c ? row[c] : 0.0;
 #pragma unroll
                     for (int d = 0; d < MAXOPS; ++d) {
-                        if (d < nops) {
+                        if (live(d, nops)) {
                             if (lane == src) t[d] = t[d] / row[c];
                             t[d] -= u * bcast(t[d], src);
                         }
@@ -310,7 +317,7 @@ __device__ inline void lu_solve_rows(const double* lu_node, double rs, double cs
     for (int c = 0; c < P - 1; ++c)
 #pragma unroll
         for (int d = 0; d < MAXOPS; ++d)
-            if (d < nops) t[d] -= row[c] * bcast(t[d], c);
+            if (live(d, nops)) t[d] -= row[c] * bcast(t[d], c);
     // backward: lane c divides by its diagonal, lanes above it subtract
 #pragma unroll
     for (int c = 0; c < P; ++c) row[c] = (lane <= c) ? lu[c * P + lane] : 0.0;
@@ -319,7 +326,7 @@ __device__ inline void lu_solve_rows(const double* lu_node, double rs, double cs
         const double u = lane < c ? row[c] : 0.0;
 #pragma unroll
         for (int d = 0; d < MAXOPS; ++d) {
-            if (d < nops) {
+            if (live(d, nops)) {
                 if (lane == c) t[d] = t[d] / row[c];
                 t[d] -= u * bcast(t[d], c);
             }
@@ -366,7 +373,8 @@ __global__ __launch_bounds__(64) void k_refine64(WeightArgs a, OpList ops, const
                 sD[1][q] = min_image(S.y[j] - yi, S.Ly, S.pery) / h;
             }
             if (lane < P)
-                for (int d = 0; d < nops; ++d) sPsi[d][lane] = w.psi[(slot * MAXOPS + d) * (int64_t)P + lane];
+                for (int d = 0; d < MAXOPS; ++d)
+                    if (live(d, nops)) sPsi[d][lane] = d < nops ? w.psi[(slot * MAXOPS + d) * (int64_t)P + lane] : 0.0;
         }
         __syncthreads();
 
@@ -385,11 +393,11 @@ __global__ __launch_bounds__(64) void k_refine64(WeightArgs a, OpList ops, const
                         double wm = abf<K, FAM>(B, m);
 #pragma unroll
                         for (int d = 0; d < MAXOPS; ++d)
-                            if (d < nops) wv[d] = fma(wm, sPsi[d][m], wv[d]);
+                            if (live(d, nops)) wv[d] = fma(wm, sPsi[d][m], wv[d]);
                     }
 #pragma unroll
                     for (int d = 0; d < MAXOPS; ++d)
-                        if (d < nops) sWl[d][q] = wv[d];
+                        if (live(d, nops)) sWl[d][q] = wv[d];
                 }
                 __syncthreads();
 
@@ -411,8 +419,15 @@ __global__ __launch_bounds__(64) void k_refine64(WeightArgs a, OpList ops, const
                         double accr[MAXOPS];
 #pragma unroll
                         for (int d = 0; d < MAXOPS; ++d) accr[d] = 0.0;
+                        // every slot's sum is read and accumulated without a branch (a slot
+                        // beyond the operator count holds values that are never used), and four
+                        // neighbours are loaded ahead, so the LDS reads overlap
+#pragma unroll 4
                         for (int q = 0; q < N; ++q) {
                             const double dx = sD[0][q], dy = sD[1][q];
+                            double wv[MAXOPS];
+#pragma unroll
+                            for (int d = 0; d < MAXOPS; ++d) wv[d] = sWl[d][q];
                             double xm = mf;
 #pragma unroll
                             for (int e = 0; e < K; ++e) {
@@ -420,8 +435,7 @@ __global__ __launch_bounds__(64) void k_refine64(WeightArgs a, OpList ops, const
                                 xm *= (e < mb) ? dy : 1.0;
                             }
 #pragma unroll
-                            for (int d = 0; d < MAXOPS; ++d)
-                                if (d < nops) accr[d] = fma(xm, sWl[d][q], accr[d]);
+                            for (int d = 0; d < MAXOPS; ++d) accr[d] = fma(xm, wv[d], accr[d]);
                         }
 #pragma unroll
                         for (int d = 0; d < MAXOPS; ++d)
@@ -448,7 +462,7 @@ __global__ __launch_bounds__(64) void k_refine64(WeightArgs a, OpList ops, const
                     if (lane < P)
 #pragma unroll
                         for (int d = 0; d < MAXOPS; ++d)
-                            if (d < nops) sPsi[d][lane] = r[d];
+                            if (live(d, nops)) sPsi[d][lane] = r[d];
                     __syncthreads();
                     for (int q = lane; q < N; q += 64) {
                         asm volatile("" ::: "memory");  // as above
@@ -462,11 +476,11 @@ __global__ __launch_bounds__(64) void k_refine64(WeightArgs a, OpList ops, const
                             double wm = abf<K, FAM>(B, m);
 #pragma unroll
                             for (int d = 0; d < MAXOPS; ++d)
-                                if (d < nops) dw[d] = fma(wm, sPsi[d][m], dw[d]);
+                                if (live(d, nops)) dw[d] = fma(wm, sPsi[d][m], dw[d]);
                         }
 #pragma unroll
                         for (int d = 0; d < MAXOPS; ++d)
-                            if (d < nops) sWl[d][q] += dw[d];
+                            if (live(d, nops)) sWl[d][q] += dw[d];
                     }
                     __syncthreads();
                     ++iters;
