@@ -211,7 +211,11 @@ labfm_err labfm_build_neighbours(void* ctx, const double* x, const double* y, in
  * max-norm moment residual over the operators); iters int8 [n] (FP64
  * refinement updates; on the MIXED path at most 30, and 64 + the FP64
  * path's count for nodes the mixed path handed to the FP64 path).  Failed
- * nodes get zero weights.  Asynchronous. */
+ * nodes get zero weights.  Asynchronous.
+ * The FP64 path (and the FP64 recomputation of the other paths) runs two
+ * kernels per order, passing each node's factors through library scratch:
+ * 18,129 bytes per node for min(n, 262144) nodes (4.75 GB from n = 262144
+ * on), kept by the context for later calls. */
 labfm_err labfm_weights(void* ctx, const double* x, const double* y, int64_t n,
                         const labfm_domain* dom, const double* R, const int8_t* order,
                         const int64_t* row_ptr, const int32_t* col, int64_t nnz,
@@ -239,8 +243,11 @@ labfm_err labfm_weights_noalloc(void* ctx, const double* x, const double* y, int
 
 /* Batched weights: nsets independent node sets, each with its own arrays,
  * domain and outputs (layouts as in labfm_weights; col holds indices within
- * the set).  One persistent kernel per order covers the nodes of every set,
- * so small and low-order sets share the GPU instead of each filling it alone.
+ * the set).  One pair of persistent kernels per order (factor, then weights
+ * and refinement, as in labfm_weights) covers the nodes of every set, so
+ * small and low-order sets share the GPU instead of each filling it alone;
+ * the batch keeps its own factor scratch (18,129 bytes per node for up to
+ * 262144 nodes at a time), allocated before any graph capture.
  * prec FP64 or MIXED (LABFM_PREC_MLP returns LABFM_EUNSUPPORTED).
  * use_graph != 0: work lists, weight kernels and the FP64 fallback of the
  *   whole batch are captured once as a HIP graph per (sets, options, stream)

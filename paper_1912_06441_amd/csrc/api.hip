@@ -198,7 +198,7 @@ labfm_err labfm_destroy(void* ctx) {
     Scratch* all[] = {&c->grid_count, &c->grid_idx, &c->node_cell, &c->counts, &c->scan_tmp, &c->worklist,
                       &c->mixed,      &c->mlp_act,  &c->mlp_feat,  &c->mlp_psi, &c->mlp_part, &c->poisson,
                       &c->factors,
-                      &c->batch.d_sets, &c->batch.d_off, &c->batch.wl, &c->batch.rl};
+                      &c->batch.d_sets, &c->batch.d_off, &c->batch.wl, &c->batch.rl, &c->batch.factors};
     for (Scratch* s : all)
         if (s->p) hipFree(s->p);
     delete c;
@@ -391,10 +391,10 @@ labfm_err labfm_weights(void* ctx, const double* x, const double* y, int64_t n, 
     hipStream_t st = (hipStream_t)stream;
     if ((e = ensure(c->worklist, sizeof(int32_t) * (size_t)(n + 3 * (LABFM_MAX_ORDER + 2)))) != LABFM_OK) return e;
     int32_t* wl = (int32_t*)c->worklist.p;
-    if (opt->prec == LABFM_PREC_FP64) return weights_fp64_split(c, a, &a.one, wl, st);
+    if (opt->prec == LABFM_PREC_FP64) return weights_fp64_split(c, a, &a.one, wl, c->factors, st);
     if ((e = ensure(c->mixed, sizeof(int32_t) * (size_t)(n + LABFM_MAX_ORDER + 2))) != LABFM_OK) return e;
     int32_t* rl = (int32_t*)c->mixed.p;
-    if (opt->prec == LABFM_PREC_MIXED) return weights_mixed(c, a, &a.one, wl, rl, 0u, st);
+    if (opt->prec == LABFM_PREC_MIXED) return weights_mixed(c, a, &a.one, wl, rl, 0u, st, 0, &c->factors);
     return weights_mlp(c, a, wl, rl, opt->mlp, st, opt->prec == LABFM_PREC_MLP_NOLU);
 }
 

@@ -96,9 +96,12 @@ labfm_err tune(Context* c, const WeightArgs& a, const NodeSet* hs, int32_t* wl, 
             float ms_m = 0.f, ms_f = 0.f;
             for (int rep = 0; rep < 2; ++rep) {  // the first pass warms up
                 LABFM_HIP_CHECK(hipEventRecord(ev[0], st));
-                if ((e = weights_mixed_lists(c, a, list, off, tcnt, rl, 1u << K, st)) != LABFM_OK) break;
+                if ((e = weights_mixed_lists(c, a, list, off, tcnt, rl, 1u << K, st, 0, &c->batch.factors)) !=
+                    LABFM_OK)
+                    break;
                 LABFM_HIP_CHECK(hipEventRecord(ev[1], st));
-                if ((e = weights_fp64_lists(c, a, list, off, tcnt, 1u << K, st)) != LABFM_OK) break;
+                if ((e = weights_fp64_split_lists(c, a, list, off, tcnt, 1u << K, c->batch.factors, st)) != LABFM_OK)
+                    break;
                 LABFM_HIP_CHECK(hipEventRecord(ev[2], st));
                 LABFM_HIP_CHECK(hipEventSynchronize(ev[2]));
                 LABFM_HIP_CHECK(hipEventElapsedTime(&ms_m, ev[0], ev[1]));
@@ -117,7 +120,8 @@ labfm_err tune(Context* c, const WeightArgs& a, const NodeSet* hs, int32_t* wl, 
 
 labfm_err enqueue(Context* c, const WeightArgs& a, const NodeSet* hs, int32_t* wl, int32_t* rl, unsigned fp64_orders,
                   int prec, hipStream_t st) {
-    return prec == LABFM_PREC_FP64 ? weights_fp64(c, a, hs, wl, st) : weights_mixed(c, a, hs, wl, rl, fp64_orders, st);
+    return prec == LABFM_PREC_FP64 ? weights_fp64_split(c, a, hs, wl, c->batch.factors, st)
+                                   : weights_mixed(c, a, hs, wl, rl, fp64_orders, st, 0, &c->batch.factors);
 }
 
 }  // namespace
@@ -159,6 +163,10 @@ labfm_err weights_batched(Context* c, int nsets, const labfm_node_set* sets, con
     int32_t* wl = (int32_t*)B.wl.p;
     int32_t* rl = (int32_t*)B.rl.p;
     int32_t* tcnt = rl + ntotal + (KMAX_ORDERS + 2);  // tuning counters, after the retry list
+
+    // the FP64 factor workspace and launch grids, sized here so that nothing allocates under capture
+    if ((e = fp64_split_reserve(B.factors, ntotal)) != LABFM_OK) return e;
+    init_split_grids();
 
     unsigned fp64_orders = 0;
     if (opt->prec == LABFM_PREC_MIXED)

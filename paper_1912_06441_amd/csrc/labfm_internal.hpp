@@ -64,6 +64,7 @@ struct Context {
         hipStream_t stream = nullptr;
         unsigned fp64_orders = 0;
         Scratch d_sets, d_off, wl, rl;  // owned by the graph
+        Scratch factors;                // the FP64 factor workspace its graph writes
         hipGraphExec_t exec = nullptr;
     } batch;
     // autotuned route of each order on the mixed path, per (abf, rbf, ops)
@@ -207,15 +208,24 @@ labfm_err weights_fp64_lists(Context* c, const WeightArgs& a, const int32_t* lis
 // whole computations; host_sets: host copy of the set table (nsets entries, or &a.one)
 labfm_err weights_fp64(Context* c, const WeightArgs& a, const NodeSet* host_sets, int32_t* wl, hipStream_t st);
 // the same FP64 weights in two kernels per order (factor, then weights and refinement), the
-// factors passing through the context's workspace; one node set (host_sets = &a.one)
-labfm_err weights_fp64_split(Context* c, const WeightArgs& a, const NodeSet* host_sets, int32_t* wl, hipStream_t st);
-// mixed kernels for the orders not in fp64_orders, FP64 kernels for those and for the retry list;
-// direct_order (1..8, needs NodeSet::psi0): that order takes the warm start's Psi0 without a
-// factorisation, its nodes above tol_pass go to the retry list.  rl: >= ntotal + KMAX + 2 int32
+// factors of each chunk of nodes passing through the workspace ws (grown by ensure() as needed:
+// reserve it with fp64_split_reserve, and the grids with init_split_grids, before a graph capture)
+labfm_err weights_fp64_split_lists(Context* c, const WeightArgs& a, const int32_t* list, const int32_t* off,
+                                   const int32_t* cnt, unsigned mask, Scratch& ws, hipStream_t st);
+labfm_err weights_fp64_split(Context* c, const WeightArgs& a, const NodeSet* host_sets, int32_t* wl, Scratch& ws,
+                             hipStream_t st);
+labfm_err fp64_split_reserve(Scratch& ws, int64_t ntotal);
+void init_split_grids();
+// mixed kernels for the orders not in fp64_orders, FP64 kernels for those and for the retry list
+// (the two-kernel FP64 route through fp64_ws when given, else the single FP64 kernel, which
+// allocates nothing); direct_order (1..8, needs NodeSet::psi0): that order takes the warm start's
+// Psi0 without a factorisation, its nodes above tol_pass go to the retry list.
+// rl: >= ntotal + KMAX + 2 int32
 labfm_err weights_mixed(Context* c, const WeightArgs& a, const NodeSet* host_sets, int32_t* wl, int32_t* rl,
-                        unsigned fp64_orders, hipStream_t st, int direct_order = 0);
+                        unsigned fp64_orders, hipStream_t st, int direct_order = 0, Scratch* fp64_ws = nullptr);
 labfm_err weights_mixed_lists(Context* c, const WeightArgs& a, const int32_t* list, const int32_t* off,
-                              const int32_t* cnt, int32_t* rl, unsigned mask, hipStream_t st, int direct_order = 0);
+                              const int32_t* cnt, int32_t* rl, unsigned mask, hipStream_t st, int direct_order = 0,
+                              Scratch* fp64_ws = nullptr);
 
 // ---- learned warm start
 labfm_err mlp_features(Context* c, const double* x, const double* y, const double* R, const int64_t* row_ptr,

@@ -1012,7 +1012,7 @@ labfm_err weights_mlp(Context* c, const WeightArgs& a0, int32_t* wl, int32_t* rl
     a.one.psi0 = psi0;
     a.psi0_order = net->order;
     a.psi0_ld = nout;
-    return weights_mixed(c, a, &a.one, wl, rl, 0u, st, direct ? net->order : 0);
+    return weights_mixed(c, a, &a.one, wl, rl, 0u, st, direct ? net->order : 0, &c->factors);
 }
 
 }  // namespace labfm

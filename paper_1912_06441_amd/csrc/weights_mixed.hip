@@ -638,7 +638,8 @@ void init_mixed_grids() {
 // Mixed kernels of the orders in `mask` over given lists, then FP64 kernels on
 // the nodes they hand back.  rl: >= ntotal + KMAX + 2 int32 (counters first).
 labfm_err weights_mixed_lists(Context* c, const WeightArgs& a0, const int32_t* list, const int32_t* off,
-                              const int32_t* cnt, int32_t* rl, unsigned mask, hipStream_t st, int direct_order) {
+                              const int32_t* cnt, int32_t* rl, unsigned mask, hipStream_t st, int direct_order,
+                              Scratch* fp64_ws) {
     int32_t* rcnt = rl;
     int32_t* rlist = rcnt + (KMAX + 2);
     labfm_err e = fill_i32(rcnt, KMAX + 2, 0, st);
@@ -667,18 +668,22 @@ labfm_err weights_mixed_lists(Context* c, const WeightArgs& a0, const int32_t* l
     // FP64 recomputation of the retry list; iters of those nodes are offset by 64
     WeightArgs a = a0;
     a.iters_offset = 64;
+    if (fp64_ws) return weights_fp64_split_lists(c, a, rlist, off, rcnt, mask, *fp64_ws, st);
     return weights_fp64_lists(c, a, rlist, off, rcnt, mask, st);
 }
 
 labfm_err weights_mixed(Context* c, const WeightArgs& a0, const NodeSet* hs, int32_t* wl, int32_t* rl,
-                        unsigned fp64_orders, hipStream_t st, int direct_order) {
+                        unsigned fp64_orders, hipStream_t st, int direct_order, Scratch* fp64_ws) {
     int32_t *list = wl, *off, *cnt;
     labfm_err e = build_order_lists(c, a0, hs, st, &list, &off, &cnt);
     if (e != LABFM_OK) return e;
     if ((e = weights_invalid_orders(a0, list, off, cnt, st)) != LABFM_OK) return e;
-    if (fp64_orders & ALL_ORDERS)
-        if ((e = weights_fp64_lists(c, a0, list, off, cnt, fp64_orders & ALL_ORDERS, st)) != LABFM_OK) return e;
-    return weights_mixed_lists(c, a0, list, off, cnt, rl, ALL_ORDERS & ~fp64_orders, st, direct_order);
+    if (fp64_orders & ALL_ORDERS) {
+        e = fp64_ws ? weights_fp64_split_lists(c, a0, list, off, cnt, fp64_orders & ALL_ORDERS, *fp64_ws, st)
+                    : weights_fp64_lists(c, a0, list, off, cnt, fp64_orders & ALL_ORDERS, st);
+        if (e != LABFM_OK) return e;
+    }
+    return weights_mixed_lists(c, a0, list, off, cnt, rl, ALL_ORDERS & ~fp64_orders, st, direct_order, fp64_ws);
 }
 
 }  // namespace labfm

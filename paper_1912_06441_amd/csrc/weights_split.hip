@@ -531,12 +531,39 @@ int split_grid(Kern kern) {
     return ncu * per;
 }
 
+// persistent grid sizes (workgroups resident at once), set before the first launch
+template <int K, int FAM>
+int& grid_factor() {
+    static int g = 0;
+    return g;
+}
+template <int K, int FAM>
+int& grid_refine() {
+    static int g = 0;
+    return g;
+}
+template <int K, int FAM>
+void init_grid() {
+    if (grid_factor<K, FAM>() == 0) grid_factor<K, FAM>() = split_grid(k_factor64<K, FAM>);
+    if (grid_refine<K, FAM>() == 0) grid_refine<K, FAM>() = split_grid(k_refine64<K, FAM>);
+}
+template <int FAM>
+void init_grids() {
+    init_grid<1, FAM>();
+    init_grid<2, FAM>();
+    init_grid<3, FAM>();
+    init_grid<4, FAM>();
+    init_grid<5, FAM>();
+    init_grid<6, FAM>();
+    init_grid<7, FAM>();
+    init_grid<8, FAM>();
+}
+
 template <int K, int FAM>
 void launch_split(Context* c, const WeightArgs& a, const OpList& ops, const int32_t* list, const int32_t* off,
-                  const int32_t* cnt, int begin, int end, const FactorWs& w, hipStream_t st) {
-    static int gf = 0, gr = 0;
-    if (gf == 0) gf = split_grid(k_factor64<K, FAM>);
-    if (gr == 0) gr = split_grid(k_refine64<K, FAM>);
+                  const int32_t* cnt, unsigned mask, int begin, int end, const FactorWs& w, hipStream_t st) {
+    if (!((mask >> K) & 1u)) return;
+    init_grid<K, FAM>();
     static const char* fnames[KMAX + 1] = {"",              "weights64f_k1", "weights64f_k2", "weights64f_k3",
                                            "weights64f_k4", "weights64f_k5", "weights64f_k6", "weights64f_k7",
                                            "weights64f_k8"};
@@ -545,46 +572,41 @@ void launch_split(Context* c, const WeightArgs& a, const OpList& ops, const int3
                                            "weights64r_k8"};
     {
         KernelTimer timer(c, fnames[K], st);
-        k_factor64<K, FAM><<<gf, 64, 0, st>>>(a, ops, list, off, cnt, begin, end, w);
+        k_factor64<K, FAM><<<grid_factor<K, FAM>(), 64, 0, st>>>(a, ops, list, off, cnt, begin, end, w);
     }
     {
         KernelTimer timer(c, rnames[K], st);
-        k_refine64<K, FAM><<<gr, 64, 0, st>>>(a, ops, list, off, cnt, begin, end, w);
+        k_refine64<K, FAM><<<grid_refine<K, FAM>(), 64, 0, st>>>(a, ops, list, off, cnt, begin, end, w);
     }
 }
 
 template <int FAM>
 void launch_split_all(Context* c, const WeightArgs& a, const OpList& ops, const int32_t* list, const int32_t* off,
-                      const int32_t* cnt, int begin, int end, const FactorWs& w, hipStream_t st) {
-    launch_split<1, FAM>(c, a, ops, list, off, cnt, begin, end, w, st);
-    launch_split<2, FAM>(c, a, ops, list, off, cnt, begin, end, w, st);
-    launch_split<3, FAM>(c, a, ops, list, off, cnt, begin, end, w, st);
-    launch_split<4, FAM>(c, a, ops, list, off, cnt, begin, end, w, st);
-    launch_split<5, FAM>(c, a, ops, list, off, cnt, begin, end, w, st);
-    launch_split<6, FAM>(c, a, ops, list, off, cnt, begin, end, w, st);
-    launch_split<7, FAM>(c, a, ops, list, off, cnt, begin, end, w, st);
-    launch_split<8, FAM>(c, a, ops, list, off, cnt, begin, end, w, st);
+                      const int32_t* cnt, unsigned mask, int begin, int end, const FactorWs& w, hipStream_t st) {
+    launch_split<1, FAM>(c, a, ops, list, off, cnt, mask, begin, end, w, st);
+    launch_split<2, FAM>(c, a, ops, list, off, cnt, mask, begin, end, w, st);
+    launch_split<3, FAM>(c, a, ops, list, off, cnt, mask, begin, end, w, st);
+    launch_split<4, FAM>(c, a, ops, list, off, cnt, mask, begin, end, w, st);
+    launch_split<5, FAM>(c, a, ops, list, off, cnt, mask, begin, end, w, st);
+    launch_split<6, FAM>(c, a, ops, list, off, cnt, mask, begin, end, w, st);
+    launch_split<7, FAM>(c, a, ops, list, off, cnt, mask, begin, end, w, st);
+    launch_split<8, FAM>(c, a, ops, list, off, cnt, mask, begin, end, w, st);
 }
-
-}  // namespace
 
 // Node slots of the workspace: one chunk of a work list at a time (about
 // 4.8 GB at order 8); larger calls take several chunks.
 constexpr int64_t FACTOR_SLOTS = 1 << 18;
 
-labfm_err weights_fp64_split(Context* c, const WeightArgs& a, const NodeSet* hs, int32_t* wl, hipStream_t st) {
-    int32_t *list = wl, *off, *cnt;
-    labfm_err e = build_order_lists(c, a, hs, st, &list, &off, &cnt);
-    if (e != LABFM_OK) return e;
-    if ((e = weights_invalid_orders(a, list, off, cnt, st)) != LABFM_OK) return e;
-    const int64_t slots = a.ntotal < FACTOR_SLOTS ? (a.ntotal > 0 ? a.ntotal : 1) : FACTOR_SLOTS;
+int64_t slots_for(int64_t ntotal) { return ntotal < FACTOR_SLOTS ? (ntotal > 0 ? ntotal : 1) : FACTOR_SLOTS; }
+
+// workspace layout for `slots` node slots, each sized for the largest order
+FactorWs carve(void* p, int64_t slots) {
     constexpr int64_t PM = p_of_k(KMAX);
     const size_t b_lu = sizeof(double) * (size_t)(slots * PM * PM);
     const size_t b_sc = sizeof(double) * (size_t)(slots * PM);
     const size_t b_psi = sizeof(double) * (size_t)(slots * MAXOPS * PM);
     const size_t b_perm = sizeof(int32_t) * (size_t)(slots * PM);
-    if ((e = ensure(c->factors, b_lu + 2 * b_sc + b_psi + b_perm + (size_t)slots)) != LABFM_OK) return e;
-    char* base = (char*)c->factors.p;
+    char* base = (char*)p;
     FactorWs w;
     w.lu = (double*)base;
     w.rs = (double*)(base + b_lu);
@@ -592,6 +614,31 @@ labfm_err weights_fp64_split(Context* c, const WeightArgs& a, const NodeSet* hs,
     w.psi = (double*)(base + b_lu + 2 * b_sc);
     w.perm = (int32_t*)(base + b_lu + 2 * b_sc + b_psi);
     w.st = (int8_t*)(base + b_lu + 2 * b_sc + b_psi + b_perm);
+    return w;
+}
+
+size_t workspace_bytes(int64_t slots) {
+    constexpr int64_t PM = p_of_k(KMAX);
+    return sizeof(double) * (size_t)(slots * PM * PM) + 2 * sizeof(double) * (size_t)(slots * PM) +
+           sizeof(double) * (size_t)(slots * MAXOPS * PM) + sizeof(int32_t) * (size_t)(slots * PM) + (size_t)slots;
+}
+
+}  // namespace
+
+void init_split_grids() {
+    init_grids<LABFM_ABF_HERMITE>();
+    init_grids<LABFM_ABF_PAPER>();
+    init_grids<LABFM_ABF_PAPER_D1>();
+}
+
+labfm_err fp64_split_reserve(Scratch& ws, int64_t ntotal) { return ensure(ws, workspace_bytes(slots_for(ntotal))); }
+
+labfm_err weights_fp64_split_lists(Context* c, const WeightArgs& a, const int32_t* list, const int32_t* off,
+                                   const int32_t* cnt, unsigned mask, Scratch& ws, hipStream_t st) {
+    const int64_t slots = slots_for(a.ntotal);
+    labfm_err e = ensure(ws, workspace_bytes(slots));
+    if (e != LABFM_OK) return e;
+    const FactorWs w = carve(ws.p, slots);
     OpList ops{};
     ops.nops = 0;
     for (int b = 0; b < 5; ++b)
@@ -600,14 +647,23 @@ labfm_err weights_fp64_split(Context* c, const WeightArgs& a, const NodeSet* hs,
         const int begin = (int)b0;
         const int end = (int)(b0 + slots < a.ntotal ? b0 + slots : a.ntotal);
         if (a.abf == LABFM_ABF_HERMITE)
-            launch_split_all<LABFM_ABF_HERMITE>(c, a, ops, list, off, cnt, begin, end, w, st);
+            launch_split_all<LABFM_ABF_HERMITE>(c, a, ops, list, off, cnt, mask, begin, end, w, st);
         else if (a.abf == LABFM_ABF_PAPER)
-            launch_split_all<LABFM_ABF_PAPER>(c, a, ops, list, off, cnt, begin, end, w, st);
+            launch_split_all<LABFM_ABF_PAPER>(c, a, ops, list, off, cnt, mask, begin, end, w, st);
         else
-            launch_split_all<LABFM_ABF_PAPER_D1>(c, a, ops, list, off, cnt, begin, end, w, st);
+            launch_split_all<LABFM_ABF_PAPER_D1>(c, a, ops, list, off, cnt, mask, begin, end, w, st);
         LABFM_HIP_CHECK(hipGetLastError());
     }
     return LABFM_OK;
+}
+
+labfm_err weights_fp64_split(Context* c, const WeightArgs& a, const NodeSet* hs, int32_t* wl, Scratch& ws,
+                             hipStream_t st) {
+    int32_t *list = wl, *off, *cnt;
+    labfm_err e = build_order_lists(c, a, hs, st, &list, &off, &cnt);
+    if (e != LABFM_OK) return e;
+    if ((e = weights_invalid_orders(a, list, off, cnt, st)) != LABFM_OK) return e;
+    return weights_fp64_split_lists(c, a, list, off, cnt, ALL_ORDERS, ws, st);
 }
 
 }  // namespace labfm
