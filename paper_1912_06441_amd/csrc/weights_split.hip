@@ -8,7 +8,8 @@
 //     M is still in registers), so two node systems run per SIMD.  The LU
 //     keeps one row of M per lane in registers and pivots by place instead of
 //     moving rows: each elimination step broadcasts the pivot row by
-//     readlane and updates the trailing rows without touching LDS.
+//     readlane (four entries at a time, in uniform control flow) and only the
+//     rows below the pivot take the update, without touching LDS.
 //   * k_refine64: weights w = W Psi, the FP64 moment residual and the
 //     refinement.  A node that needs a correction reads its factors back
 //     straight into registers (lane r takes row r), so the kernel keeps no
@@ -230,12 +231,21 @@ __global__ __launch_bounds__(64) void k_factor64(WeightArgs a, OpList ops, const
                     const double inv = 1.0 / bcast(row[kk], pl);
                     const bool upd = pos > kk && pos < P;
                     const double m = row[kk] * inv;
+                    // pivot-row entries are read in uniform control flow, a group at a
+                    // time; only the rows below the pivot take the update
 #pragma unroll
-                    for (int c = kk + 1; c < P; ++c) {
-                        const double nv = fma(-m, bcast(row[c], pl), row[c]);
-                        row[c] = upd ? nv : row[c];
+                    for (int c0 = kk + 1; c0 < P; c0 += 4) {
+                        double u[4];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            if (c0 + q < P) u[q] = bcast(row[c0 + q], pl);
+                        if (upd) {
+#pragma unroll
+                            for (int q = 0; q < 4; ++q)
+                                if (c0 + q < P) row[c0 + q] = fma(-m, u[q], row[c0 + q]);
+                        }
                     }
-                    row[kk] = upd ? m : row[kk];
+                    if (upd) row[kk] = m;
                 }
             }
             if (lane < P) sPerm[pos] = lane;  // place -> row
