@@ -257,9 +257,10 @@ __global__ __launch_bounds__(64) void k_factor64(WeightArgs a, OpList ops, const
                 const double rs = lane < P ? sRs[lane] : 0.0;
 #pragma unroll
                 for (int d = 0; d < MAXOPS; ++d) t[d] = ((d < nops) ? target(ops.op[d], lane) : 0.0) * rs;
+                const int perm_reg = lane < P ? sPerm[lane] : 0;  // lane c: the row at place c
 #pragma unroll
                 for (int c = 0; c < P - 1; ++c) {
-                    const int src = sPerm[c];
+                    const int src = __builtin_amdgcn_readlane(perm_reg, c);
                     const double l = (pos > c && pos < P) ? row[c] : 0.0;
 #pragma unroll
                     for (int d = 0; d < MAXOPS; ++d)
@@ -267,12 +268,13 @@ __global__ __launch_bounds__(64) void k_factor64(WeightArgs a, OpList ops, const
                 }
 #pragma unroll
                 for (int c = P - 1; c >= 0; --c) {
-                    const int src = sPerm[c];
+                    const int src = __builtin_amdgcn_readlane(perm_reg, c);
                     const double u = pos < c ? row[c] : 0.0;
 #pragma unroll
                     for (int d = 0; d < MAXOPS; ++d) {
                         if (live(d, nops)) {
-                            if (lane == src) t[d] = t[d] / row[c];
+                            const double q = t[d] / row[c];  // every lane divides; lane src keeps it
+                            t[d] = lane == src ? q : t[d];
                             t[d] -= u * bcast(t[d], src);
                         }
                     }
@@ -337,7 +339,8 @@ __device__ inline void lu_solve_rows(const double* lu_node, double rs, double cs
 #pragma unroll
         for (int d = 0; d < MAXOPS; ++d) {
             if (live(d, nops)) {
-                if (lane == c) t[d] = t[d] / row[c];
+                const double q = t[d] / row[c];  // every lane divides; lane c keeps it
+                t[d] = lane == c ? q : t[d];
                 t[d] -= u * bcast(t[d], c);
             }
         }
