@@ -224,8 +224,10 @@ labfm_err labfm_weights(void* ctx, const double* x, const double* y, int64_t n,
 
 /* labfm_weights without any allocation, for callers that cannot allocate
  * device memory (code under HIP graph capture, serving loops, harnesses that
- * forbid hipMalloc): the same computation, kernels and results as
- * labfm_weights, for opt->prec LABFM_PREC_FP64 or LABFM_PREC_MIXED
+ * forbid hipMalloc): the same computation and, bit for bit, the same results
+ * as labfm_weights, for opt->prec LABFM_PREC_FP64 or LABFM_PREC_MIXED; its
+ * FP64 work runs in one kernel per order, which keeps each node's factors on
+ * chip instead of in labfm_weights' factor scratch
  * (LABFM_PREC_MLP returns LABFM_EUNSUPPORTED).  Its work lists live in a
  * fixed library array of (2 LABFM_NOALLOC_MAX_NODES + 40) int32 (about 8 MiB)
  * that every GPU the library runs on holds until the process ends; n above
