@@ -15,8 +15,8 @@
 //     straight into registers (lane r takes row r), so the kernel keeps no
 //     P x P matrix in LDS and two node systems run per SIMD.
 // Between the two, per node of the current chunk of a work list: the LU
-// factors (P x P, column-major), row and column scales, pivot rows, Psi and
-// the status, in a workspace of FACTOR_SLOTS node slots.  Every step and
+// factors (P x P, column-major), row and column scales, the row at each
+// pivot place, Psi and the status, in a workspace of FACTOR_SLOTS node slots.  Every step and
 // every rounding is the single kernel's, so the results are the same.
 #include "weights_common.hpp"
 
@@ -30,12 +30,10 @@ struct FactorWs {
     double* rs;     // [slots][P]
     double* cs;     // [slots][P]
     double* psi;    // [slots][MAXOPS][P]
-    int32_t* perm;  // [slots][P]
+    int32_t* perm;  // [slots][P]: the row (of the equilibrated M) at each place
     int8_t* st;     // [slots]
 };
 
-// v of another lane of the same row of 16, by a DPP move of both halves
-// (CTRL 0x121..0x12f: rotate the row right by 1..15 lanes)
 // Operator slots 0..NB-1 are always computed: a call with fewer operators
 // runs them on zero coefficients (zero right-hand sides, so zero solutions),
 // which keeps the common three-operator case free of per-slot branches.
@@ -43,6 +41,8 @@ struct FactorWs {
 constexpr int NB = 3;
 __device__ inline bool live(int d, int nops) { return d < NB || d < nops; }
 
+// v of another lane of the same row of 16, by a DPP move of both halves
+// (CTRL 0x121..0x12f: rotate the row right by 1..15 lanes)
 template <int CTRL>
 __device__ inline double dpp_d(double v) {
     const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
