@@ -479,7 +479,9 @@ labfm_err labfm_build_neighbours3(void* ctx, const double* x, const double* y, c
  * LABFM_PREC_FP64 and opt->abf LABFM_ABF_HERMITE, else LABFM_EUNSUPPORTED);
  * the refinement, status, residual and iteration outputs are those of
  * labfm_weights.  w64: device [nops][nnz]; status int8 [n]; resid FP32 [n]
- * and iters int8 [n] may be NULL.  Asynchronous. */
+ * and iters int8 [n] may be NULL.  Asynchronous.  Orders 1..4 pass each
+ * node's factors through library scratch (8 P^2 + 60 P + 1 bytes per node,
+ * 11,289 at k = 4, for min(n, 262144) nodes), kept by the context. */
 labfm_err labfm_weights3(void* ctx, const double* x, const double* y, const double* z, int64_t n,
                          const labfm_domain3* dom, const double* R, int k, const int64_t* row_ptr,
                          const int32_t* col, int64_t nnz, const labfm_wopts* opt, double* w64, int8_t* status,
@@ -547,7 +549,9 @@ labfm_err labfm_mlp_cast_bf16(void* ctx, const float* src, void* dst, int64_t co
  * capture).  labfm_timing_read waits for the recorded kernels whose name
  * contains `filter` (NULL: all), returns their count and summed duration in
  * milliseconds, and forgets them.  Kernel names: neigh_count, neigh_fill,
- * weights64_k1..k8, weights32_k1..k8, apply_f32, apply_f64, step_graph,
+ * weights64f_k1..k8 and weights64r_k1..k8 (the two FP64 kernels of an
+ * order), weights64_k1..k8 (the single FP64 kernel), weights32_k1..k8,
+ * weights3d_k1..k6 (every 3-D kernel of an order), apply_f32, apply_f64, step_graph,
  * step_direct, burgers_graph, burgers_direct, poisson_setup,
  * poisson_iterations, mlp_features, mlp_forward,
  * mlp_backward, mlp_loss, mlp_adam,

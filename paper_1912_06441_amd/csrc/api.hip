@@ -197,7 +197,7 @@ labfm_err labfm_destroy(void* ctx) {
     }
     Scratch* all[] = {&c->grid_count, &c->grid_idx, &c->node_cell, &c->counts, &c->scan_tmp, &c->worklist,
                       &c->mixed,      &c->mlp_act,  &c->mlp_feat,  &c->mlp_psi, &c->mlp_part, &c->poisson,
-                      &c->factors,
+                      &c->factors, &c->factors3,
                       &c->batch.d_sets, &c->batch.d_off, &c->batch.wl, &c->batch.rl, &c->batch.factors};
     for (Scratch* s : all)
         if (s->p) hipFree(s->p);

@@ -44,6 +44,7 @@ struct Context {
     Scratch mlp_part;     // column-sum partials of the bias gradients
     Scratch poisson;      // reduction partials and scalars of the Krylov solve
     Scratch factors;      // LU factors, scales, pivots and Psi of one chunk of FP64 node systems
+    Scratch factors3;     // the same for the three-dimensional node systems (orders 1..4)
     // cached RK4 step graph (replayed while plan, buffers and stream are unchanged)
     hipGraphExec_t step_exec = nullptr;
     hipStream_t step_stream = nullptr;

@@ -6,8 +6,12 @@
 // built and solved as in the two-dimensional FP64 kernel: one wavefront per
 // node, M accumulated in registers from basis chunks in LDS, row/column
 // equilibration, partial-pivot LU in LDS, FP64 refinement on the moment
-// residual, unscaling by h^l.  At k = 6 the system has more elements (83)
-// than a wavefront has lanes: k_weights3w gives each lane two rows.
+// residual, unscaling by h^l (k_weights3, used at k = 5).  At k = 6 the
+// system has more elements (83) than a wavefront has lanes: k_weights3w gives
+// each lane two rows.  Orders 1..4 run as the two-dimensional FP64 route
+// does, in two kernels (k_factor3, k_refine3) with the LU in registers and
+// the factors passed through a workspace; the results are the same bit for
+// bit.
 #include "weights_common.hpp"
 
 namespace labfm {
@@ -863,6 +867,416 @@ __global__ __launch_bounds__(64) void k_weights3w(W3Args a, OpList ops) {
     }
 }
 
+// ---- orders 1..4 in two kernels ----------------------------------------
+// The same node systems, steps and roundings as k_weights3, split as the
+// two-dimensional FP64 route is: k_factor3 (assembly, equilibration, LU with
+// one row per lane in registers, first solve) hands each node's factors
+// (column-major by pivot place), scales, places, Psi and status through a
+// workspace to k_refine3 (weights, FP64 moment residual, refinement), which
+// loads a node's LU rows straight into registers when it needs a correction.
+
+struct Factor3Ws {
+    double* lu;     // [slots][P * P]: entry (r, c) at c * P + r, rows by place
+    double* rs;     // [slots][P]
+    double* cs;     // [slots][P]
+    double* psi;    // [slots][MAXOPS][P]
+    int32_t* perm;  // [slots][P]: the row (of the equilibrated M) at each place
+    int8_t* st;     // [slots]
+};
+
+// Operator slots 0..NB3-1 are always computed, on zero coefficients when a
+// call asks for fewer; slots beyond follow the run-time count (a fourth slot
+// costs more in registers than its branches do).
+constexpr int NB3 = 3;
+__device__ inline bool live3(int d, int nops) { return d < NB3 || d < nops; }
+
+// v of another lane of the same row of 16 (CTRL 0x121..0x12f: rotate right)
+template <int CTRL>
+__device__ inline double dpp3(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+// maximum over the wavefront: rotations by 8, 4, 2, 1 lanes, then the four row maxima
+__device__ inline double wave_max3(double v) {
+    v = fmax(v, dpp3<0x128>(v));
+    v = fmax(v, dpp3<0x124>(v));
+    v = fmax(v, dpp3<0x122>(v));
+    v = fmax(v, dpp3<0x121>(v));
+    return fmax(fmax(bcast(v, 0), bcast(v, 16)), fmax(bcast(v, 32), bcast(v, 48)));
+}
+
+template <int K>
+__global__ __launch_bounds__(64) void k_factor3(W3Args a, OpList ops, int64_t begin, int64_t end, Factor3Ws w) {
+    constexpr int P = p3_of_k(K);
+    constexpr int BS = (P + 7) / 8;
+    constexpr int PP = 8 * BS;
+    constexpr int LD = P + 1;
+    constexpr int CHK = K >= 5 ? 8 : CH;
+    static_assert(P <= 64, "one row per lane");
+    // one pass of the assembly over the chunks (all accumulator rows at once):
+    // the chunks are read only before M is written, so they share its buffer
+    constexpr bool ALIAS = rb3(K) >= BS;
+    __shared__ double sMC[ALIAS ? cmax(P * LD, 2 * CHK * PP) : P * LD];
+    __shared__ double sCh[ALIAS ? 1 : 2 * CHK * PP];
+    double* const sM = sMC;
+    double* const sChunk = ALIAS ? sMC : sCh;
+    __shared__ double sD[3][NM3];
+    __shared__ double sRs[P], sCs[P];
+    __shared__ int sPerm[P];
+
+    const int lane = threadIdx.x;
+    const int nops = ops.nops;
+
+    for (int64_t i = begin + blockIdx.x; i < end; i += gridDim.x) {
+        const int64_t slot = i - begin;
+        const int64_t s0 = a.row_ptr[i];
+        const int N = (int)(a.row_ptr[i + 1] - s0);
+        const double h = 0.5 * a.R[i];
+        int status = LABFM_ST_OK;
+        for (int d = 0; d < nops; ++d)
+            if (ops.op[d] == LABFM_OP_LAP && K < 2) status = LABFM_ST_ORDER_TOO_LOW;
+        if (status == LABFM_ST_OK && N < P) status = LABFM_ST_TOO_FEW;
+        if (status == LABFM_ST_OK && N > NM3) status = LABFM_ST_TOO_MANY;
+
+        if (status == LABFM_ST_OK) {
+            const double xi = a.x[i], yi = a.y[i], zi = a.z[i];
+            for (int q = lane; q < N; q += 64) {
+                const int32_t j = a.col[s0 + q];
+                sD[0][q] = min_image(a.x[j] - xi, a.L[0], a.per[0]) / h;
+                sD[1][q] = min_image(a.y[j] - yi, a.L[1], a.per[1]) / h;
+                sD[2][q] = min_image(a.z[j] - zi, a.L[2], a.per[2]) / h;
+            }
+        }
+        __syncthreads();
+
+        if (status == LABFM_ST_OK) {
+            // ---- assembly: M = sum_j X(d_j) W(d_j)^T
+            assemble3<K, rb3(K), CHK>(sM, sChunk, sD, N, a.rbf, a.sigma);
+
+            // ---- equilibration: rows, then columns
+            bool sing = false;
+            if (lane < P) {
+                double mx = 0.0;
+                for (int c = 0; c < P; ++c) mx = fmax(mx, fabs(sM[lane * LD + c]));
+                if (!(mx > 0.0) || !isfinite(mx)) sing = true;
+                const double rs = 1.0 / mx;
+                sRs[lane] = rs;
+                for (int c = 0; c < P; ++c) sM[lane * LD + c] *= rs;
+            }
+            __syncthreads();
+            if (lane < P) {
+                double mx = 0.0;
+                for (int r = 0; r < P; ++r) mx = fmax(mx, fabs(sM[r * LD + lane]));
+                if (!(mx > 0.0) || !isfinite(mx)) sing = true;
+                const double cs = 1.0 / mx;
+                sCs[lane] = cs;
+                for (int r = 0; r < P; ++r) sM[r * LD + lane] *= cs;
+            }
+            __syncthreads();
+            if (__any(sing)) status = LABFM_ST_SINGULAR;
+
+            // ---- LU with partial pivoting, row r in lane r's registers; pos is
+            // the row's place in the pivoted order (ties: the lowest place)
+            double row[P];
+#pragma unroll
+            for (int c = 0; c < P; ++c) row[c] = lane < P ? sM[lane * LD + c] : 0.0;
+            int pos = lane;
+            if (status == LABFM_ST_OK) {
+#pragma unroll
+                for (int kk = 0; kk < P; ++kk) {
+                    const double v = (pos >= kk && pos < P) ? fabs(row[kk]) : -1.0;
+                    const double vmax = wave_max3(v);
+                    const unsigned long long hit = __ballot(v == vmax);
+                    if (!(vmax > 0.0) || !isfinite(vmax) || hit == 0ull) {
+                        status = LABFM_ST_SINGULAR;
+                        break;
+                    }
+                    int pl = __ffsll((long long)hit) - 1;
+                    if (__popcll(hit) > 1) {
+                        int cand = v == vmax ? pos : 1 << 20;
+#pragma unroll
+                        for (int off = 32; off >= 1; off >>= 1) cand = min(cand, __shfl_xor(cand, off, 64));
+                        pl = __ffsll((long long)__ballot(pos == cand)) - 1;
+                    }
+                    const int ppos = __builtin_amdgcn_readlane(pos, pl);
+                    pos = lane == pl ? kk : (pos == kk ? ppos : pos);
+                    const double inv = 1.0 / bcast(row[kk], pl);
+                    const bool upd = pos > kk && pos < P;
+                    const double m = row[kk] * inv;
+#pragma unroll
+                    for (int c0 = kk + 1; c0 < P; c0 += 4) {
+                        double u[4];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            if (c0 + q < P) u[q] = bcast(row[c0 + q], pl);
+                        if (upd) {
+#pragma unroll
+                            for (int q = 0; q < 4; ++q)
+                                if (c0 + q < P) row[c0 + q] = fma(-m, u[q], row[c0 + q]);
+                        }
+                    }
+                    if (upd) row[kk] = m;
+                }
+            }
+            if (lane < P) sPerm[pos] = lane;
+            __syncthreads();
+            if (status == LABFM_ST_OK) {
+                // ---- first solve, in places; the row at place c is in lane perm_reg of lane c
+                double t[MAXOPS];
+                const double rs = lane < P ? sRs[lane] : 0.0;
+#pragma unroll
+                for (int d = 0; d < MAXOPS; ++d) t[d] = ((d < nops) ? target3(ops.op[d], lane) : 0.0) * rs;
+                const int perm_reg = lane < P ? sPerm[lane] : 0;
+#pragma unroll
+                for (int c = 0; c < P - 1; ++c) {
+                    const int src = __builtin_amdgcn_readlane(perm_reg, c);
+                    const double l = (pos > c && pos < P) ? row[c] : 0.0;
+#pragma unroll
+                    for (int d = 0; d < MAXOPS; ++d)
+                        if (live3(d, nops)) t[d] -= l * bcast(t[d], src);
+                }
+#pragma unroll
+                for (int c = P - 1; c >= 0; --c) {
+                    const int src = __builtin_amdgcn_readlane(perm_reg, c);
+                    const double u = pos < c ? row[c] : 0.0;
+#pragma unroll
+                    for (int d = 0; d < MAXOPS; ++d) {
+                        if (live3(d, nops)) {
+                            const double q = t[d] / row[c];  // every lane divides; lane src keeps it
+                            t[d] = lane == src ? q : t[d];
+                            t[d] -= u * bcast(t[d], src);
+                        }
+                    }
+                }
+                const int from = lane < P ? sPerm[lane] : 0;
+                const double cs = lane < P ? sCs[lane] : 0.0;
+#pragma unroll
+                for (int d = 0; d < MAXOPS; ++d) {
+                    const double z = __shfl(t[d], from, 64) * cs;
+                    if (lane < P && d < nops) w.psi[(slot * MAXOPS + d) * (int64_t)P + lane] = z;
+                }
+                double* lu = w.lu + slot * (int64_t)(P * P);
+                if (lane < P) {
+#pragma unroll
+                    for (int c = 0; c < P; ++c) lu[c * P + pos] = row[c];
+                    w.rs[slot * (int64_t)P + lane] = rs;
+                    w.cs[slot * (int64_t)P + lane] = cs;
+                    w.perm[slot * (int64_t)P + lane] = sPerm[lane];
+                }
+            }
+        }
+        if (lane == 0) w.st[slot] = (int8_t)status;
+        __syncthreads();
+    }
+}
+
+// Solve M z = b with one node's factors from the workspace: lane r loads row r
+// (one contiguous load per column of the column-major store) and the solve
+// runs in registers; the arithmetic and its order are lu_solve's.
+template <int P>
+__device__ inline void lu_solve_rows3(const double* lu_node, double rs, double cs, int pr, double (&b)[MAXOPS],
+                                      int nops) {
+    const int lane = threadIdx.x;
+    // the base pointer passes through an empty asm so that the column
+    // addresses are formed here instead of being held across the caller's loop
+    uint64_t bits = (uint64_t)lu_node;
+    asm volatile("" : "+s"(bits));
+    const double* lu = (const double*)bits;
+    double t[MAXOPS];
+#pragma unroll
+    for (int d = 0; d < MAXOPS; ++d) t[d] = __shfl(b[d] * rs, pr, 64);
+    double row[P];
+#pragma unroll
+    for (int c = 0; c < P - 1; ++c) row[c] = (lane > c && lane < P) ? lu[c * P + lane] : 0.0;
+#pragma unroll
+    for (int c = 0; c < P - 1; ++c)
+#pragma unroll
+        for (int d = 0; d < MAXOPS; ++d)
+            if (live3(d, nops)) t[d] -= row[c] * bcast(t[d], c);
+#pragma unroll
+    for (int c = 0; c < P; ++c) row[c] = (lane <= c) ? lu[c * P + lane] : 0.0;
+#pragma unroll
+    for (int c = P - 1; c >= 0; --c) {
+        const double u = lane < c ? row[c] : 0.0;
+#pragma unroll
+        for (int d = 0; d < MAXOPS; ++d) {
+            if (live3(d, nops)) {
+                const double q = t[d] / row[c];  // every lane divides; lane c keeps it
+                t[d] = lane == c ? q : t[d];
+                t[d] -= u * bcast(t[d], c);
+            }
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < MAXOPS; ++d) b[d] = t[d] * cs;
+}
+
+template <int K>
+__global__ __launch_bounds__(64) void k_refine3(W3Args a, OpList ops, int64_t begin, int64_t end, Factor3Ws w) {
+    constexpr int P = p3_of_k(K);
+    constexpr int BS = (P + 7) / 8;
+    constexpr int PP = 8 * BS;
+    __shared__ double sD[3][NM3];
+    __shared__ double sWl[MAXOPS][NM3];  // scaled weights: running sums, and the residual's input
+    __shared__ double sPsi[MAXOPS][PP];
+
+    const int lane = threadIdx.x;
+    const int nops = ops.nops;
+
+    for (int64_t i = begin + blockIdx.x; i < end; i += gridDim.x) {
+        const int64_t slot = i - begin;
+        const int64_t s0 = a.row_ptr[i];
+        const int N = (int)(a.row_ptr[i + 1] - s0);
+        const double h = 0.5 * a.R[i];
+        int status = w.st[slot];
+        double res = INFINITY;
+        int iters = 0;
+
+        if (status == LABFM_ST_OK) {
+            const double xi = a.x[i], yi = a.y[i], zi = a.z[i];
+            for (int q = lane; q < N; q += 64) {
+                const int32_t j = a.col[s0 + q];
+                sD[0][q] = min_image(a.x[j] - xi, a.L[0], a.per[0]) / h;
+                sD[1][q] = min_image(a.y[j] - yi, a.L[1], a.per[1]) / h;
+                sD[2][q] = min_image(a.z[j] - zi, a.L[2], a.per[2]) / h;
+            }
+            if (lane < P)
+                for (int d = 0; d < MAXOPS; ++d)
+                    if (live3(d, nops)) sPsi[d][lane] = d < nops ? w.psi[(slot * MAXOPS + d) * (int64_t)P + lane] : 0.0;
+        }
+        __syncthreads();
+
+        if (status == LABFM_ST_OK) {
+            // ---- w_j = W(d_j) . Psi (lane q keeps neighbour q's sums in sWl)
+            for (int q = lane; q < N; q += 64) {
+                asm volatile("" ::: "memory");  // keeps Psi's loads inside the loop
+                double wv[MAXOPS];
+#pragma unroll
+                for (int d = 0; d < MAXOPS; ++d) wv[d] = 0.0;
+                Basis3<K> B;
+                basis3_prepare<K>(B, sD[0][q], sD[1][q], sD[2][q], a.rbf, a.sigma);
+#pragma unroll
+                for (int m = 0; m < P; ++m) {
+                    const double wm = abf3<K>(B, m);
+#pragma unroll
+                    for (int d = 0; d < MAXOPS; ++d)
+                        if (live3(d, nops)) wv[d] = fma(wm, sPsi[d][m], wv[d]);
+                }
+#pragma unroll
+                for (int d = 0; d < MAXOPS; ++d)
+                    if (live3(d, nops)) sWl[d][q] = wv[d];
+            }
+            __syncthreads();
+
+            const double* lu = w.lu + slot * (int64_t)(P * P);
+            double rs = 0.0, cs = 0.0;
+            int pr = 0;
+            bool lu_in = false;
+
+            // ---- refinement on the moment residual (FP64)
+            const int ma = lane < P ? ELEM3.a[lane] : 0;
+            const int mb = lane < P ? ELEM3.b[lane] : 0;
+            const int mc = lane < P ? ELEM3.c[lane] : 0;
+            const double mf = lane < P ? inv_fact(ma) * inv_fact(mb) * inv_fact(mc) : 0.0;
+            for (;;) {
+                double r[MAXOPS];
+#pragma unroll
+                for (int d = 0; d < MAXOPS; ++d) r[d] = 0.0;
+                if (lane < P) {
+                    double accr[MAXOPS];
+#pragma unroll
+                    for (int d = 0; d < MAXOPS; ++d) accr[d] = 0.0;
+                    // every slot's sums are read without a branch (a slot beyond the
+                    // operator count is never used); four neighbours loaded ahead
+#pragma unroll 4
+                    for (int q = 0; q < N; ++q) {
+                        const double dx = sD[0][q], dy = sD[1][q], dz = sD[2][q];
+                        double wq[MAXOPS];
+#pragma unroll
+                        for (int d = 0; d < MAXOPS; ++d) wq[d] = sWl[d][q];
+                        double xm = mf;
+#pragma unroll
+                        for (int e = 0; e < K; ++e) {
+                            xm *= (e < ma) ? dx : 1.0;
+                            xm *= (e < mb) ? dy : 1.0;
+                            xm *= (e < mc) ? dz : 1.0;
+                        }
+#pragma unroll
+                        for (int d = 0; d < MAXOPS; ++d) accr[d] = fma(xm, wq[d], accr[d]);
+                    }
+#pragma unroll
+                    for (int d = 0; d < MAXOPS; ++d)
+                        if (d < nops) r[d] = target3(ops.op[d], lane) - accr[d];
+                }
+                double rm = 0.0;
+#pragma unroll
+                for (int d = 0; d < MAXOPS; ++d) {
+                    const double ar = fabs(r[d]);
+                    rm = (ar > rm || ar != ar) ? ar : rm;
+                }
+                if (!isfinite(rm)) rm = INFINITY;
+                res = wave_max(rm);
+                if (!(res > a.tol_stop) || iters >= a.max_iters) break;
+                if (!lu_in) {
+                    if (lane < P) {
+                        rs = w.rs[slot * (int64_t)P + lane];
+                        cs = w.cs[slot * (int64_t)P + lane];
+                        pr = w.perm[slot * (int64_t)P + lane];
+                    }
+                    lu_in = true;
+                }
+                lu_solve_rows3<P>(lu, rs, cs, pr, r, nops);
+                if (lane < P)
+#pragma unroll
+                    for (int d = 0; d < MAXOPS; ++d)
+                        if (live3(d, nops)) sPsi[d][lane] = r[d];
+                __syncthreads();
+                for (int q = lane; q < N; q += 64) {
+                    asm volatile("" ::: "memory");
+                    Basis3<K> B;
+                    basis3_prepare<K>(B, sD[0][q], sD[1][q], sD[2][q], a.rbf, a.sigma);
+                    double dw[MAXOPS];
+#pragma unroll
+                    for (int d = 0; d < MAXOPS; ++d) dw[d] = 0.0;
+#pragma unroll
+                    for (int m = 0; m < P; ++m) {
+                        const double wm = abf3<K>(B, m);
+#pragma unroll
+                        for (int d = 0; d < MAXOPS; ++d)
+                            if (live3(d, nops)) dw[d] = fma(wm, sPsi[d][m], dw[d]);
+                    }
+#pragma unroll
+                    for (int d = 0; d < MAXOPS; ++d)
+                        if (live3(d, nops)) sWl[d][q] += dw[d];
+                }
+                __syncthreads();
+                ++iters;
+            }
+            if (!(res <= a.tol_pass)) status = LABFM_ST_NOT_CONVERGED;
+
+            // ---- unscale and store
+            for (int d = 0; d < nops; ++d) {
+                const double hl = ops.op[d] == LABFM_OP_LAP ? h * h : h;
+                for (int q = lane; q < N; q += 64) a.w64[(int64_t)d * a.nnz + s0 + q] = sWl[d][q] / hl;
+            }
+        }
+        const bool failed = !(status == LABFM_ST_OK || status == LABFM_ST_NOT_CONVERGED);
+        if (failed) {
+            for (int d = 0; d < nops; ++d)
+                for (int q = lane; q < N; q += 64) a.w64[(int64_t)d * a.nnz + s0 + q] = 0.0;
+            res = INFINITY;
+            iters = 0;
+        }
+        if (lane == 0) {
+            a.status[i] = (int8_t)status;
+            if (a.resid) a.resid[i] = (float)res;
+            if (a.iters) a.iters[i] = (int8_t)iters;
+        }
+        __syncthreads();
+    }
+}
+
 template <typename Kern>
 int grid3_of(Kern kern) {
     int dev = 0, ncu = 0, per = 0;
@@ -894,6 +1308,41 @@ void launch3(const W3Args& a, const OpList& ops, hipStream_t st) {
 template <int K>
 void launch3w(const W3Args& a, const OpList& ops, hipStream_t st) {
     k_weights3w<K><<<grid3w_for<K>(), 64, 0, st>>>(a, ops);
+}
+
+// node slots of the factor workspace: one chunk of nodes at a time
+constexpr int64_t FACTOR3_SLOTS = 1 << 18;
+
+template <int K>
+size_t factor3_bytes(int64_t slots) {
+    constexpr int64_t P = p3_of_k(K);
+    return sizeof(double) * (size_t)(slots * (P * P + 2 * P + MAXOPS * P)) + sizeof(int32_t) * (size_t)(slots * P) +
+           (size_t)slots;
+}
+
+template <int K>
+labfm_err launch3_split(Context* c, const W3Args& a, const OpList& ops, hipStream_t st) {
+    constexpr int64_t P = p3_of_k(K);
+    static int gf = 0, gr = 0;
+    if (gf == 0) gf = grid3_of(k_factor3<K>);
+    if (gr == 0) gr = grid3_of(k_refine3<K>);
+    const int64_t slots = a.n < FACTOR3_SLOTS ? a.n : FACTOR3_SLOTS;
+    labfm_err e = ensure(c->factors3, factor3_bytes<K>(slots));
+    if (e != LABFM_OK) return e;
+    char* base = (char*)c->factors3.p;
+    Factor3Ws w;
+    w.lu = (double*)base;
+    w.rs = w.lu + slots * P * P;
+    w.cs = w.rs + slots * P;
+    w.psi = w.cs + slots * P;
+    w.perm = (int32_t*)(w.psi + slots * MAXOPS * P);
+    w.st = (int8_t*)(w.perm + slots * P);
+    for (int64_t b0 = 0; b0 < a.n; b0 += slots) {
+        const int64_t end = b0 + slots < a.n ? b0 + slots : a.n;
+        k_factor3<K><<<gf, 64, 0, st>>>(a, ops, b0, end, w);
+        k_refine3<K><<<gr, 64, 0, st>>>(a, ops, b0, end, w);
+    }
+    return LABFM_OK;
 }
 
 }  // namespace
@@ -931,15 +1380,20 @@ labfm_err weights3(Context* c, const double* x, const double* y, const double* z
         if (opt->ops & (1u << b)) ops.op[ops.nops++] = 1u << b;
     static const char* names[K3MAX + 1] = {"",           "weights3d_k1", "weights3d_k2", "weights3d_k3",
                                            "weights3d_k4", "weights3d_k5", "weights3d_k6"};
+    // orders 1..4: the two-kernel route.  Order 5 keeps the single kernel: its
+    // 55 rows in registers spill, and the pair took 17.7 ms at 32^3 against
+    // 10.4 ms.  Order 6 (83 elements, two rows per lane): one kernel.
     KernelTimer timer(c, names[k], st);
+    labfm_err e = LABFM_OK;
     switch (k) {
-        case 1: launch3<1>(a, ops, st); break;
-        case 2: launch3<2>(a, ops, st); break;
-        case 3: launch3<3>(a, ops, st); break;
-        case 4: launch3<4>(a, ops, st); break;
+        case 1: e = launch3_split<1>(c, a, ops, st); break;
+        case 2: e = launch3_split<2>(c, a, ops, st); break;
+        case 3: e = launch3_split<3>(c, a, ops, st); break;
+        case 4: e = launch3_split<4>(c, a, ops, st); break;
         case 5: launch3<5>(a, ops, st); break;
         default: launch3w<6>(a, ops, st); break;
     }
+    if (e != LABFM_OK) return e;
     LABFM_HIP_CHECK(hipGetLastError());
     return LABFM_OK;
 }
