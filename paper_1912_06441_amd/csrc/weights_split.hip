@@ -321,18 +321,20 @@ __device__ inline void lu_solve_rows(const double* lu_node, double rs, double cs
         double v = b[d] * rs;
         t[d] = __shfl(v, pr, 64);
     }
+    // the whole row at once: the lower part for the forward pass, the upper
+    // part and the diagonal for the backward pass
     double row[P];
+#pragma unroll
+    for (int c = 0; c < P; ++c) row[c] = lane < P ? lu[c * P + lane] : 0.0;
     // forward: unit lower triangle
 #pragma unroll
-    for (int c = 0; c < P - 1; ++c) row[c] = (lane > c && lane < P) ? lu[c * P + lane] : 0.0;
-#pragma unroll
-    for (int c = 0; c < P - 1; ++c)
+    for (int c = 0; c < P - 1; ++c) {
+        const double l = lane > c ? row[c] : 0.0;
 #pragma unroll
         for (int d = 0; d < MAXOPS; ++d)
-            if (live(d, nops)) t[d] -= row[c] * bcast(t[d], c);
+            if (live(d, nops)) t[d] -= l * bcast(t[d], c);
+    }
     // backward: lane c divides by its diagonal, lanes above it subtract
-#pragma unroll
-    for (int c = 0; c < P; ++c) row[c] = (lane <= c) ? lu[c * P + lane] : 0.0;
 #pragma unroll
     for (int c = P - 1; c >= 0; --c) {
         const double u = lane < c ? row[c] : 0.0;
