@@ -12,6 +12,8 @@
 * Through the whole GPU path (neighbours, weights, application): gradient
   errors fall ~h^k and the Laplacian ~h^(k-1) from 12^3 to 24^3.
 * Degenerate requests: order 1 with a Laplacian, stencils with N < p.
+* Calls with one to three operators (the unused operator slots of orders 1..4
+  run on zero coefficients) keep every status and the weights within 1e-10.
 """
 import sys
 
@@ -145,6 +147,34 @@ def test_weights3_parity(env, k, periodic, side):
     assert loose.size <= max(2, st.size // 500)
     failed = (st != 0) & (st != 1)
     assert np.all(w.cpu().numpy()[:, np.repeat(failed, np.diff(rp_o))] == 0.0)
+
+
+@pytest.mark.parametrize("k,ops", [(4, "DX"), (3, "DZ|LAP"), (2, "DY"), (4, "DX|DY|DZ"), (1, "DZ")])
+def test_weights3_fewer_operators(env, k, ops):
+    """Calls with one to three operators: the kernels of orders 1..4 always
+    compute three operator slots and run the unused ones on zero coefficients;
+    nothing of those slots may reach the outputs.  Periodic lattice: every
+    status OK as the oracle's, weights within 1e-10 of the oracle's."""
+    O = env["O"]
+    cfg = WL.config("c3d")
+    mask = 0
+    for name in ops.split("|"):
+        mask |= getattr(O, "OP_" + name)
+    x, y, z, s = WL.jittered_lattice3(10, eps=cfg["eps"], seed=60 + k, periodic=True)
+    dom = WL.unit_domain3(True)
+    R = cfg["R_s"][k] * s
+    rp_o, col_o = O.neighbours3(x, y, z, dom, R)
+    w_o, st_o, res_o, _ = O.weights3(x, y, z, dom, R, k, rp_o, col_o, ops=mask, sigma=cfg["sigma"])
+    xt, yt, zt, Rt, rp, col = _gpu_neigh(env, x, y, z, R, dom)
+    w, st, res, it = env["ctx"].weights3(xt, yt, zt, Rt, k, rp, col, dom, ops=mask, sigma=cfg["sigma"])
+    env["torch"].cuda.synchronize()
+    st = st.cpu().numpy()
+    assert w.shape[0] == w_o.shape[0]
+    assert np.array_equal(st, st_o) and np.all(st == 0)
+    assert float(res.max()) <= 1e-10
+    par = _row_parity(rp_o, w.cpu().numpy(), w_o)
+    _say("  3-D k=%d ops %s: parity max %.2e" % (k, ops, par.max()))
+    assert par.max() <= 1e-10
 
 
 @pytest.mark.parametrize("k,rg,rl", [(2, 1.7, 0.9), (3, 2.6, 1.6), (4, 3.5, 2.4), (5, 4.5, 3.5), (6, 5.5, 4.5)])
